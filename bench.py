@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Fit throughput of the CS-RBF normal-equation path on one MI355X.
+
+Workload "terrain2d": N = 2^20 clustered points (64 anisotropic Gaussians,
+scanline-thinned) carrying a 256-mode fractal height field plus noise
+(sigma 1e-3), 1 % held out; 256 x 256 grid of reference points; Wendland
+phi_{3,1} with a radius covering ~40 centres; ridge lambda_rel = 1e-4; solved
+to a relative residual of 1e-10.
+
+One step = one whole fit on inputs already resident in HBM: hash + pattern
+(rbf_fit_plan), assembly of B and g (rbf_assemble), Jacobi-PCG (rbf_solve) and
+evaluation of the held-out RMSE (rbf_eval).  The headline value is the
+mixed-precision path (float32 basis/assembly/CG with float64 reliable
+updates); the float64 path is timed the same way and reported beside it,
+with both held-out RMSEs (matched when they agree to 0.1 %).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fit throughput (data pts/s, assembly+CG) at matched RMSE; FP32-mixed vs FP64"
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+LAMBDA_REL = 1e-4
+RTOL = 1e-10
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(nnz_full: int, m: int, val_bytes: int, vec_bytes: int) -> int:
+    """Algorithmic HBM bytes of one CG SpMV launch: every stored value and column
+    index once, the row pointers once, and four length-M vectors (z and p_old
+    read, p_new and q written)."""
+    return nnz_full * (val_bytes + 4) + (m + 1) * 8 + 4 * m * vec_bytes
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("cg_kernels.hip", "solver.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1806_07884_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(prob, frac: float):
+    """The oracle (as it stands) on a bounded window of the same workload."""
+    import numpy as np
+    from oracle import rbf_oracle as orc
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    w = frac
+    ctr = prob.centers
+    keep_c = np.all(ctr <= w + 1e-12, axis=0)
+    c_win = np.ascontiguousarray(ctr[:, keep_c])
+    keep_p = np.all(prob.points <= w + prob.rho, axis=0)
+    p_win = np.ascontiguousarray(prob.points[:, keep_p])
+    h_win = np.ascontiguousarray(prob.values[keep_p])
+    t0 = time.perf_counter()
+    ne = orc.normal_equations(p_win, h_win, c_win, prob.rho, prob.phi, lambda_rel=LAMBDA_REL)
+    orc.solve(ne)
+    dt = time.perf_counter() - t0
+    n_used = p_win.shape[1]
+    return {"value": n_used / dt, "unit": "pts/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"window [0,{w}]^2 of the same workload: {c_win.shape[1]} centres, "
+                       f"{n_used} points (those within rho of the window), assembly of "
+                       f"A, B = A^T A, g = A^T h plus Cholesky solve; {dt:.1f} s"),
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed float64 fits for the comparison (default: --steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-window", type=float, default=0.5)
+    ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1806_07884_amd as rbf
+    import synthdata as sd
+
+    log("generating terrain2d inputs")
+    prob = sd.make_problem("terrain2d", scale=args.scale)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    pts, vals, ctr = dev(prob.points), dev(prob.values), dev(prob.centers)
+    tpts, tvals = dev(prob.test_points), dev(prob.test_values)
+    n_train = prob.points.shape[1]
+    torch.cuda.synchronize()
+
+    def fit(prec: str, profile: bool = False):
+        plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL)
+        if profile:
+            rbf.rbf_profile(plan, True)
+        rbf.rbf_assemble(plan, prob.phi, prec, vals)
+        c, info = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
+        _, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+        return plan, info, rmse
+
+    def timed(prec: str, steps: int, warm: int):
+        for _ in range(warm):
+            plan, info, rmse = fit(prec)
+            plan.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per = []
+        spmv_n, spmv_ms, asm_ms = 0, 0.0, 0.0
+        for _ in range(steps):
+            plan, info, rmse = fit(prec, profile=True)
+            n, ms = rbf.rbf_profile_read(plan, "spmv")
+            _, ams = rbf.rbf_profile_read(plan, "assemble")
+            spmv_n += n
+            spmv_ms += ms
+            asm_ms += ams
+            per.append((info, rmse))
+            stats = rbf.rbf_plan_info(plan)
+            plan.close()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        log(f"{prec}: {dt * 1e3:.1f} ms/fit, iters {per[-1][0]['iterations']}, "
+            f"rmse {per[-1][1]:.6e}, spmv avg {spmv_ms / max(spmv_n, 1) * 1e3:.2f} us")
+        return dt, per, stats, spmv_n, spmv_ms, asm_ms / steps
+
+    steps = max(1, args.steps)
+    dt32, per32, stats, n32, ms32, asm32 = timed("fp32", steps, args.warmup)
+    dt64, per64, _, n64, ms64, asm64 = timed("fp64", args.fp64_steps or steps, args.warmup)
+    value = n_train / dt32
+    rmse32, rmse64 = per32[-1][1], per64[-1][1]
+    matched = abs(rmse32 - rmse64) <= 1e-3 * rmse64
+
+    nnz, m = stats["nnz_full"], stats["n_centers"]
+    avg_s = ms32 / max(n32, 1) / 1e3
+    bytes32 = spmv_bytes(nnz, m, 4, 4)
+    achieved = bytes32 / avg_s if avg_s > 0 else 0.0
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "spmv_fp32_terrain2d_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            t = json.load(fh)
+        if t.get("kernel_digest") == kernel_digest():
+            traffic = t.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
+                "kernel": "k_cg_spmv<float,float>", "bytes_per_launch": bytes32,
+                "avg_launch_us": avg_s * 1e6, "timed_launches": n32}
+    avg64 = ms64 / max(n64, 1) / 1e3
+    b64 = spmv_bytes(nnz, m, 8, 8)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a window of the workload")
+        cpu = cpu_baseline(prob, args.cpu_window)
+        log(f"oracle: {cpu['value']:.0f} pts/s ({cpu['seconds']:.1f} s)")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "pts/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": dt32 * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "terrain2d", "n_points": int(prob.points.shape[1] +
+                                                            prob.test_points.shape[1]),
+                   "n_train": int(n_train), "n_centers": int(m), "grid": prob.grid,
+                   "phi": prob.phi, "rho": prob.rho, "lambda_rel": LAMBDA_REL, "rtol": RTOL,
+                   "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed": {"ms_per_fit": dt32 * 1e3, "iterations": per32[-1][0]["iterations"],
+                  "reliable_updates": per32[-1][0]["reliable_updates"],
+                  "rel_residual": per32[-1][0]["rel_residual"], "heldout_rmse": rmse32,
+                  "assembly_ms": asm32},
+        "fp64": {"value": n_train / dt64, "ms_per_fit": dt64 * 1e3,
+                 "iterations": per64[-1][0]["iterations"],
+                 "rel_residual": per64[-1][0]["rel_residual"], "heldout_rmse": rmse64,
+                 "assembly_ms": asm64, "spmv_avg_us": avg64 * 1e6,
+                 "spmv_gbps": (b64 / avg64 / 1e9) if avg64 > 0 else None},
+        "speedup_mixed_vs_fp64": dt64 / dt32,
+        "rmse_matched": bool(matched),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,203 @@
+/*
+ * librbf -- compactly-supported RBF least-squares approximation on one MI355X.
+ *
+ * The library fits f(x) = sum_j c_j phi(||x - xi_j|| / rho_j) (Majdisova & Skala,
+ * "Big Geo Data Surface Approximation using Radial Basis Functions", Section 2,
+ * eq. 3) to N scattered samples (x_i, h_i) with M << N reference points xi_j,
+ * by forming the normal equations of the overdetermined system A c = h
+ * (Section 2, eq. 4-5):
+ *
+ *     B = A^T A  (sparse, symmetric; Section 5, eq. 11-12)      g = A^T h
+ *
+ * with A_ij = phi(||x_i - xi_j|| / rho_j) a Wendland CS-RBF (Table 2), and
+ * solving (B + lambda I) c = g by Jacobi-preconditioned conjugate gradients.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers documented "device" are HIP device allocations owned by the
+ *    caller; the library only reads or writes them on the plan's stream and
+ *    keeps no reference after the call returns unless stated.  "_h" pointers
+ *    are host memory owned by the caller.
+ *  - Coordinates are SoA float64: component d of point i at ptr[d * n + i].
+ *  - Indices of reference points ("centres") are the caller's order 0..M-1.
+ *  - Every call returns an int status: 0 (RBF_OK), a negative error or a
+ *    positive warning.  No call aborts or throws; rbf_last_error() gives the
+ *    text of the last failure on the calling thread.
+ *  - A plan is not thread-safe; distinct plans are independent.  All GPU work
+ *    of a plan is ordered on the stream passed to rbf_fit_plan.  Calls block
+ *    the host only where stated.
+ *  - The support predicate is the strict range query of Algorithm 1:
+ *    point x is in the support of centre j iff s < rho_j * rho_j, where
+ *    s = (dx*dx + dy*dy) [+ dz*dz] with dx = x - xi in float64 and every
+ *    operation rounded separately (no fused multiply-add).  The sparsity
+ *    pattern is therefore reproducible bit for bit on any IEEE-754 machine.
+ *  - Limits: dim in {2, 3}; 1 <= N < 2^31; 1 <= M < 2^31.
+ */
+#ifndef RBF_H_
+#define RBF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define RBF_OK 0
+#define RBF_WARN_MAXITER 1   /* solver stopped at max_iter; best iterate returned */
+#define RBF_WARN_FALLBACK 2  /* mixed-precision solve gave up; finished in FP64 */
+#define RBF_ERR_INVALID (-1)     /* bad argument, size or call order */
+#define RBF_ERR_NONFINITE (-2)   /* NaN/Inf in coordinates, radii or values */
+#define RBF_ERR_SINGULAR (-3)    /* system not positive definite at set-up */
+#define RBF_ERR_BREAKDOWN (-4)   /* CG breakdown: p^T B p <= 0 or NaN */
+#define RBF_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define RBF_ERR_OOM (-6)         /* device allocation failed */
+
+/* Wendland CS-RBFs phi_{3,s}, Table 2 (s = 0, 1, 3) and the same family's s = 2:
+ *   W30 (1-r)^2_+   W31 (1-r)^4_+(4r+1)   W32 (1-r)^6_+(35r^2+18r+3)
+ *   W33 (1-r)^8_+(32r^3+25r^2+8r+1)       with r = ||x - xi|| / rho.        */
+typedef enum { RBF_PHI_W30 = 0, RBF_PHI_W31 = 1, RBF_PHI_W32 = 2, RBF_PHI_W33 = 3 } rbf_phi;
+
+/* FP64: float64 basis values, assembly, matrix and CG.
+ * FP32_REFINE: float32 basis values with compensated (Kahan) assembly, a
+ * float32 matrix and float32 CG vectors; float64 dot products, float64
+ * residual recomputation and float64 solution updates (reliable updates). */
+typedef enum { RBF_PREC_FP64 = 0, RBF_PREC_FP32_REFINE = 1 } rbf_precision;
+
+typedef struct rbf_plan rbf_plan;
+
+/* Optional device allocator for every buffer the plan owns.  alloc returns a
+ * device pointer (NULL on failure); release gives it back.  NULL allocator:
+ * hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, size_t bytes, void* ctx);
+  void* ctx;
+} rbf_allocator;
+
+typedef struct {
+  int32_t dim;                  /* 2 or 3 */
+  int64_t n_points;             /* N */
+  int64_t n_centers;            /* M */
+  const double* points;         /* device, SoA [dim][N]; read during the call */
+  const double* centers;        /* device, SoA [dim][M]; copied into the plan */
+  double rho;                   /* support radius (= 1/alpha of eq. 18), > 0,
+                                   used when rho_per_center is NULL */
+  const double* rho_per_center; /* device [M] radii > 0, or NULL; copied */
+  int32_t min_support;          /* centres with fewer supported points are
+                                   inactive: no row/column, c_j = 0 (>= 1) */
+  double lambda_rel;            /* ridge: lambda = lambda_rel * mean diag(B) over
+                                   active centres, added to the diagonal (>= 0) */
+} rbf_plan_desc;
+
+typedef struct {
+  int32_t dim;
+  int32_t grid[3];              /* hash grid cells per dimension */
+  int64_t n_points, n_centers;
+  int64_t n_points_in_box;      /* points within reach of some centre's cell */
+  int64_t n_active;             /* centres with >= min_support points */
+  int64_t nnz_upper;            /* stored entries of B, diagonal and above */
+  int64_t nnz_full;             /* entries of the full symmetric B */
+  double density;               /* nnz_full / M^2 (Table 4 "density of LSE matrix") */
+  int64_t support_total;        /* sum_j n_j = nonzeros of A */
+  int32_t support_max;          /* max_j n_j */
+  int32_t row_max;              /* max entries in a full row of B */
+  double cell_size;
+} rbf_plan_stats;
+
+typedef struct {
+  double rtol;          /* stop when ||g - (B + lambda I) c||_2 <= rtol ||g||_2 */
+  int64_t max_iter;     /* CG iteration cap (> 0) */
+  int32_t warm_start;   /* nonzero: coeffs holds the initial guess on entry */
+  int32_t check_every;  /* iterations between host reads of the residual (>= 1) */
+  double reliable_delta;/* FP32_REFINE: float64 residual recomputation when the
+                           iterated residual fell by this factor (0 < d < 1) */
+} rbf_solve_opts;
+
+typedef struct {
+  int64_t iterations;        /* CG iterations performed */
+  int64_t reliable_updates;  /* float64 residual recomputations */
+  double rel_residual;       /* final ||g - (B+lambda I)c|| / ||g||, recomputed in FP64 */
+  double lambda;             /* ridge on the diagonal */
+  int32_t precision;         /* rbf_precision actually used */
+  int32_t status;            /* same as the return value */
+} rbf_solve_info;
+
+/* Build the neighbour structure and the sparsity pattern of B (Section 5:
+ * upper triangle of the symmetric matrix; Algorithm 1: strict range query).
+ * Hashes points and centres into a uniform grid of cell size >= max rho,
+ * counts each centre's supported points, marks active centres and builds the
+ * structural pattern: (j, l) is stored iff some point lies in both supports.
+ * stream: a hipStream_t (NULL = default stream).  Blocks the host to read the
+ * pattern size.  Errors: INVALID (sizes, dim, rho <= 0, min_support < 1,
+ * lambda_rel < 0, NULL pointers), NONFINITE (NaN/Inf coordinates or radii),
+ * OOM, HIP.  On error *out is NULL. */
+int rbf_fit_plan(const rbf_plan_desc* desc, const rbf_allocator* allocator, void* stream,
+                 rbf_plan** out);
+
+/* Sizes of the plan (host struct); reads the per-centre counts back, so it
+ * blocks the host. */
+int rbf_plan_info(const rbf_plan* plan, rbf_plan_stats* out);
+
+/* Copy the upper-triangular CSR pattern of B (diagonal included, columns
+ * ascending, caller's centre numbering) and the support counts n_j to host
+ * arrays of sizes M+1, nnz_upper and M.  Any pointer may be NULL to skip it.
+ * Blocks the host. */
+int rbf_plan_pattern(const rbf_plan* plan, int64_t* row_ptr_h, int32_t* col_h,
+                     int32_t* support_count_h);
+
+/* Assemble the values of B and g = A^T h for samples `values` (device [N],
+ * caller's point order) with basis `phi` in precision `prec` (Section 5,
+ * eq. 11-12: b_jl = sum_k phi_kj phi_kl over the points in both supports),
+ * then add the ridge and form the Jacobi preconditioner.  Stream-ordered, does
+ * not block.  Errors: INVALID (bad phi/prec, NULL values), HIP. */
+int rbf_assemble(rbf_plan* plan, rbf_phi phi, rbf_precision prec, const double* values);
+
+/* Copy the assembled system to host memory: the upper-CSR values of
+ * B + lambda I in the pattern's order (nnz_upper; float32 values widened when
+ * assembled in FP32_REFINE), g (M) and lambda (scalar).  Any pointer may be
+ * NULL.  Blocks the host.  Errors: INVALID if nothing was assembled. */
+int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, double* lambda_h);
+
+/* Solve (B + lambda I) c = g by Jacobi-preconditioned CG in the precision of
+ * the last rbf_assemble.  coeffs: device [M] float64 output (input too when
+ * opts->warm_start); inactive centres get 0.  opts NULL: rtol 1e-10,
+ * max_iter 100000, check_every 32, reliable_delta 0.1.  Blocks the host every
+ * check_every iterations to read the residual.  Returns OK, WARN_MAXITER
+ * (best iterate kept), WARN_FALLBACK (mixed precision stalled and FP64 took
+ * over), ERR_BREAKDOWN, ERR_INVALID (not assembled), ERR_HIP.  info may be
+ * NULL. */
+int rbf_solve(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info);
+
+/* Evaluate the approximant (eq. 3) at n_query points: out[q] =
+ * sum_j coeffs[j] phi(||y_q - xi_j|| / rho_j) over centres with y_q in their
+ * support, basis of the last rbf_assemble (or W31 if none).  queries: device
+ * SoA [dim][n_query]; coeffs: device [M]; out: device [n_query].  When
+ * values is not NULL (device [n_query]) the root-mean-square of out - values
+ * is written to *rmse_h (blocks the host); otherwise stream-ordered. */
+int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
+             const double* coeffs, double* out, const double* values, double* rmse_h);
+
+/* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
+ * starts bracketing, with HIP events on the plan's stream, the assembly launch
+ * and every fourth CG matrix-vector launch (launches that returned at entry
+ * after convergence are not counted); rbf_profile(plan, 0) stops.
+ * rbf_profile_read returns the number of timed launches of `kernel` and their
+ * summed duration in milliseconds.  Both block the host (stream sync).
+ * Kernel ids: */
+#define RBF_KERNEL_SPMV 0      /* CG: p update, q = (B + lambda I) p, p . q */
+#define RBF_KERNEL_ASSEMBLE 2  /* numeric assembly of B and g */
+int rbf_profile(rbf_plan* plan, int32_t enable);
+int rbf_profile_read(rbf_plan* plan, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Release every buffer of the plan (after the plan's stream work finished). */
+void rbf_plan_destroy(rbf_plan* plan);
+
+const char* rbf_status_string(int status);
+const char* rbf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBF_H_ */

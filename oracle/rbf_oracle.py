@@ -334,9 +334,10 @@ class Row:
     g: float                  # g_j = sum_q phi_qj h_q
 
 
-def sample_row(points, values, centers, rho, phi: str, j: int) -> Row:
-    """Row j of the upper pattern and values of B, plus g_j, straight from eq. 12.
+def sample_row(points, values, centers, rho, phi: str, j: int, lower: bool = False) -> Row:
+    """Row j of the pattern and values of B, plus g_j, straight from eq. 12.
 
+    Columns l >= j (the stored upper triangle), or every column when ``lower``.
     Active set is taken as min_support = 1: a column l that shares a point with
     row j has a nonempty support, so every column found here is active.
     """
@@ -352,7 +353,7 @@ def sample_row(points, values, centers, rho, phi: str, j: int) -> Row:
     # any column sharing a point lies within rho_j + rho_l of centre j
     cdist2 = sqdist(centers, centers[:, j])
     reach = (rv[j] + rv) * (1.0 + 1e-6)
-    cand = np.nonzero((cdist2 <= reach * reach) & (np.arange(m) >= j))[0]
+    cand = np.nonzero((cdist2 <= reach * reach) & ((np.arange(m) >= j) | lower))[0]
     pts = points[:, q]
     cols, vals, cnt = [], [], []
     for l in cand:

@@ -1,0 +1,14 @@
+"""CS-RBF least-squares approximation of big scattered data on one MI355X.
+
+Python entry points with the names of the C-ABI in include/rbf.h; they only
+marshal arguments (torch tensors give device memory and the stream) and every
+step of the computation runs in the HIP kernels of librbf.so:
+
+    plan = rbf_fit_plan(points, centers, rho, lambda_rel=1e-4)
+    rbf_assemble(plan, "w31", "fp32", values)
+    coeffs, info = rbf_solve(plan, rtol=1e-10)
+    f, rmse = rbf_eval(plan, queries, coeffs, values=heldout_values)
+"""
+from .binding import (Plan, rbf_assemble, rbf_eval, rbf_fit_plan, rbf_plan_info,  # noqa: F401
+                      rbf_plan_pattern, rbf_solve, rbf_system_export, rbf_plan_destroy,
+                      rbf_profile, rbf_profile_read)

@@ -1,0 +1,125 @@
+"""ctypes declarations of librbf's C-ABI (see include/rbf.h).
+
+Loading fails loudly when the HIP library has not been built: there is no
+fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librbf.so")
+
+RBF_OK = 0
+RBF_WARN_MAXITER = 1
+RBF_WARN_FALLBACK = 2
+RBF_ERR_INVALID = -1
+RBF_ERR_NONFINITE = -2
+RBF_ERR_SINGULAR = -3
+RBF_ERR_BREAKDOWN = -4
+RBF_ERR_HIP = -5
+RBF_ERR_OOM = -6
+
+KERNEL = {"spmv": 0, "assemble": 2}
+PHI = {"w30": 0, "w31": 1, "w32": 2, "w33": 3}
+PREC = {"fp64": 0, "fp32": 1}
+
+c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_points", ctypes.c_int64),
+                ("n_centers", ctypes.c_int64), ("points", ctypes.c_void_p),
+                ("centers", ctypes.c_void_p), ("rho", ctypes.c_double),
+                ("rho_per_center", ctypes.c_void_p), ("min_support", ctypes.c_int32),
+                ("lambda_rel", ctypes.c_double)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
+                ("n_points", ctypes.c_int64), ("n_centers", ctypes.c_int64),
+                ("n_points_in_box", ctypes.c_int64), ("n_active", ctypes.c_int64),
+                ("nnz_upper", ctypes.c_int64), ("nnz_full", ctypes.c_int64),
+                ("density", ctypes.c_double), ("support_total", ctypes.c_int64),
+                ("support_max", ctypes.c_int32), ("row_max", ctypes.c_int32),
+                ("cell_size", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int64),
+                ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("reliable_delta", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("reliable_updates", ctypes.c_int64),
+                ("rel_residual", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("ctx", ctypes.c_void_p)]
+
+
+# exported symbol -> (restype, argtypes); also the list the load test checks
+SIGNATURES = {
+    "rbf_fit_plan": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.POINTER(Allocator),
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanStats)]),
+    "rbf_plan_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "rbf_assemble": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p]),
+    "rbf_system_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "rbf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
+                                 ctypes.POINTER(SolveInfo)]),
+    "rbf_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_double)]),
+    "rbf_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rbf_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "rbf_plan_destroy": (None, [ctypes.c_void_p]),
+    "rbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rbf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librbf.so; raises when it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_1806_07884_amd.build)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class RbfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        msg = L.rbf_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {L.rbf_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> int:
+    if status < 0:
+        raise RbfError(status, where)
+    return status

@@ -1,0 +1,206 @@
+"""Thin torch-facing binding of librbf (argument marshalling only).
+
+Device buffers come from torch tensors (float64, CUDA/HIP, contiguous); the
+stream is torch's current stream unless one is given; every buffer the plan
+owns is taken from torch's caching allocator through the C allocator hooks.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _need(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError(f"{name} must be a float64 GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Plan:
+    """Owner of one rbf_plan handle (and of the allocator callbacks it uses)."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p()
+        self.dim = self.n = self.m = 0
+        self.device = None
+        self.stream = None
+        self._alloc = None
+        self._keep = []       # inputs the stream may still read
+
+    def _stream_handle(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def close(self):
+        if self.handle and self.handle.value:
+            with torch.cuda.device(self.device):
+                L.lib().rbf_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_allocator(device: torch.device, stream: torch.cuda.Stream):
+    def _alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=stream)
+        except Exception:
+            return None
+
+    def _release(ptr, _nbytes, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = L.Allocator(L.ALLOC_FN(_alloc), L.RELEASE_FN(_release), None)
+    return a
+
+
+def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[float] = None,
+                 rho_per_center: Optional[torch.Tensor] = None, min_support: int = 1,
+                 lambda_rel: float = 0.0, stream: Optional[torch.cuda.Stream] = None) -> Plan:
+    """Hash, support counts and the sparsity pattern of B (rbf_fit_plan)."""
+    _need(points, "points")
+    if points.dim() != 2:
+        raise ValueError("points must be (dim, N)")
+    dim, n = points.shape
+    _need(centers, "centers")
+    if centers.dim() != 2 or centers.shape[0] != dim:
+        raise ValueError("centers must be (dim, M)")
+    m = centers.shape[1]
+    if rho_per_center is not None:
+        _need(rho_per_center, "rho_per_center", (m,))
+    elif rho is None:
+        raise ValueError("give rho or rho_per_center")
+    plan = Plan()
+    plan.dim, plan.n, plan.m = int(dim), int(n), int(m)
+    plan.device = points.device
+    plan.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
+    plan._alloc = _make_allocator(plan.device, plan.stream)
+    desc = L.PlanDesc(int(dim), int(n), int(m), points.data_ptr(), centers.data_ptr(),
+                      float(rho) if rho is not None else 0.0,
+                      rho_per_center.data_ptr() if rho_per_center is not None else None,
+                      int(min_support), float(lambda_rel))
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_fit_plan(ctypes.byref(desc), ctypes.byref(plan._alloc),
+                                  plan._stream_handle(), ctypes.byref(plan.handle))
+    L.check(st, "rbf_fit_plan")
+    return plan
+
+
+def rbf_plan_info(plan: Plan) -> dict:
+    s = L.PlanStats()
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_plan_info(plan.handle, ctypes.byref(s)), "rbf_plan_info")
+    out = {k: getattr(s, k) for k, _ in L.PlanStats._fields_}
+    out["grid"] = list(s.grid)
+    return out
+
+
+def rbf_plan_pattern(plan: Plan):
+    """(row_ptr int64 [M+1], col int32 [nnz_upper], support int32 [M]) on the host."""
+    info = rbf_plan_info(plan)
+    rp = np.zeros(plan.m + 1, np.int64)
+    col = np.zeros(max(1, info["nnz_upper"]), np.int32)
+    sup = np.zeros(plan.m, np.int32)
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_plan_pattern(plan.handle, rp.ctypes.data, col.ctypes.data,
+                                         sup.ctypes.data), "rbf_plan_pattern")
+    return rp, col[:info["nnz_upper"]], sup
+
+
+def rbf_assemble(plan: Plan, phi: str, prec: str, values: torch.Tensor) -> None:
+    """Values of B (+ ridge) and g = A^T h in precision 'fp64' or 'fp32' (rbf_assemble)."""
+    _need(values, "values", (plan.n,))
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_assemble(plan.handle, L.PHI[phi], L.PREC[prec], values.data_ptr())
+    L.check(st, "rbf_assemble")
+    plan._keep = [values]
+
+
+def rbf_system_export(plan: Plan):
+    """(upper values of B + lambda I [nnz_upper], g [M], lambda) on the host."""
+    info = rbf_plan_info(plan)
+    val = np.zeros(max(1, info["nnz_upper"]))
+    g = np.zeros(plan.m)
+    lam = ctypes.c_double()
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_system_export(plan.handle, val.ctypes.data, g.ctypes.data,
+                                          ctypes.byref(lam)), "rbf_system_export")
+    return val[:info["nnz_upper"]], g, lam.value
+
+
+def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1e-10,
+              max_iter: int = 100000, warm_start: bool = False, check_every: int = 32,
+              reliable_delta: float = 0.1):
+    """Jacobi-PCG solve of (B + lambda I) c = g (rbf_solve).  Returns (coeffs, info)."""
+    if coeffs is None:
+        coeffs = torch.zeros(plan.m, dtype=torch.float64, device=plan.device)
+    _need(coeffs, "coeffs", (plan.m,))
+    opts = L.SolveOpts(float(rtol), int(max_iter), int(bool(warm_start)), int(check_every),
+                       float(reliable_delta))
+    info = L.SolveInfo()
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_solve(plan.handle, ctypes.byref(opts), coeffs.data_ptr(),
+                               ctypes.byref(info))
+    L.check(st, "rbf_solve")
+    return coeffs, {"iterations": info.iterations, "reliable_updates": info.reliable_updates,
+                    "rel_residual": info.rel_residual, "lambda": info.lambda_,
+                    "precision": "fp64" if info.precision == 0 else "fp32",
+                    "status": info.status}
+
+
+def rbf_eval(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
+             out: Optional[torch.Tensor] = None, values: Optional[torch.Tensor] = None):
+    """f at the query points (eq. 3), and the RMSE against `values` when given."""
+    _need(queries, "queries")
+    if queries.dim() != 2 or queries.shape[0] != plan.dim:
+        raise ValueError("queries must be (dim, Q)")
+    nq = int(queries.shape[1])
+    _need(coeffs, "coeffs", (plan.m,))
+    if out is None:
+        out = torch.empty(nq, dtype=torch.float64, device=plan.device)
+    _need(out, "out", (nq,))
+    rmse = ctypes.c_double(float("nan"))
+    if values is not None:
+        _need(values, "values", (nq,))
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_eval(plan.handle, nq, queries.data_ptr(), coeffs.data_ptr(),
+                              out.data_ptr(), values.data_ptr() if values is not None else None,
+                              ctypes.byref(rmse))
+    L.check(st, "rbf_eval")
+    plan._keep = [queries, coeffs]
+    return out, (rmse.value if values is not None else None)
+
+
+def rbf_profile(plan: Plan, enable: bool) -> None:
+    """Start (reset) or stop event timing of the assembly and CG SpMV launches."""
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_profile(plan.handle, int(bool(enable))), "rbf_profile")
+
+
+def rbf_profile_read(plan: Plan, kernel: str):
+    """(timed launches, summed milliseconds) of 'spmv' or 'assemble'."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_profile_read(plan.handle, L.KERNEL[kernel], ctypes.byref(n),
+                                         ctypes.byref(ms)), "rbf_profile_read")
+    return n.value, ms.value
+
+
+def rbf_plan_destroy(plan: Plan) -> None:
+    plan.close()

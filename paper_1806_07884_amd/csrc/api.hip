@@ -1,0 +1,812 @@
+// Host side of the C-ABI: plan object, device workspace, and the call
+// sequences of set-up, assembly, solve and evaluation.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "plan_kernels.h"
+#include "rbf.h"
+#include "solver.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIPCHK(...)                                                                    \
+  do {                                                                                 \
+    hipError_t e_ = (__VA_ARGS__);                                                     \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RBF_ERR_HIP, "%s failed: %s", #__VA_ARGS__, hipGetErrorString(e_));  \
+  } while (0)
+
+constexpr int64_t kMaxCells = int64_t(1) << 26;
+
+}  // namespace
+
+struct rbf_plan {
+  rbf_allocator alloc{};
+  bool custom_alloc = false;
+  hipStream_t stream = nullptr;
+  struct Buf {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Buf> bufs;
+
+  int32_t dim = 2;
+  int64_t n = 0, m = 0;
+  int32_t min_support = 1;
+  double lambda_rel = 0.0;
+  rbf::Grid grid{};
+  double cell_size = 0.0;
+
+  // hash of points and centres
+  double* ps = nullptr;
+  int32_t* pperm = nullptr;
+  int32_t* pcs = nullptr;
+  double* ctr = nullptr;
+  double* ctr_s = nullptr;
+  int32_t* cperm = nullptr;
+  int32_t* ccs = nullptr;
+  double* rho = nullptr;
+  double* rho2 = nullptr;
+  double* irho = nullptr;
+  double* rho2_s = nullptr;
+  double* irho_s = nullptr;
+  // pattern
+  int32_t* support = nullptr;
+  uint8_t* active = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* lower_cnt = nullptr;
+  int32_t* col = nullptr;
+  int64_t nnz_full = 0;
+  int32_t group = 16;
+  // system
+  double* hs = nullptr;
+  double* g = nullptr;
+  double* diag = nullptr;
+  double* lam = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  int phi = -1;
+  int prec = -1;
+  // solver workspace
+  double* xhi = nullptr;
+  double* r64 = nullptr;
+  rbf::CgScalars* sc = nullptr;
+  double* part_spmv = nullptr;
+  double* part_upd = nullptr;
+  void* vec64[6] = {};
+  void* vec32[6] = {};
+  double* cs_sorted = nullptr;
+  double* eval_part = nullptr;
+  rbf::CgScalars* host_sc = nullptr;  // pinned
+  double* host_small = nullptr;       // pinned
+
+  // optional kernel timing: HIP events bracketing sampled launches
+  struct Pending {
+    int kernel;
+    int64_t iter;  // CG iteration index of the launch, -1 outside CG
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Pending> pending;
+  int64_t prof_launches[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
+
+  hipEvent_t event() {
+    if (!ev_free.empty()) {
+      hipEvent_t e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // folds every finished pair into the totals; CG launches at or beyond
+  // `cg_done` iterations returned at entry and are dropped
+  void resolve(int64_t cg_done) {
+    for (const Pending& q : pending) {
+      float ms = 0.f;
+      if ((q.iter < 0 || q.iter < cg_done) && hipEventSynchronize(q.b) == hipSuccess &&
+          hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+        prof_launches[q.kernel] += 1;
+        prof_ms[q.kernel] += ms;
+      }
+      ev_free.push_back(q.a);
+      ev_free.push_back(q.b);
+    }
+    pending.clear();
+  }
+
+  void* alloc_bytes(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (custom_alloc) {
+      p = alloc.alloc(bytes, alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) bufs.push_back({p, bytes});
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < bufs.size(); ++i) {
+      if (bufs[i].p == p) {
+        if (custom_alloc)
+          alloc.release(p, bufs[i].bytes, alloc.ctx);
+        else
+          (void)hipFree(p);
+        bufs.erase(bufs.begin() + (long)i);
+        return;
+      }
+    }
+  }
+  template <typename T>
+  bool get(T** out, int64_t count) {
+    *out = static_cast<T*>(alloc_bytes((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+    return *out != nullptr;
+  }
+  rbf::PlanView view() const {
+    rbf::PlanView v;
+    v.dim = dim;
+    v.n = n;
+    v.m = m;
+    v.grid = grid;
+    v.ps = ps;
+    v.pcs = pcs;
+    v.pperm = pperm;
+    v.ctr = ctr;
+    v.ctr_s = ctr_s;
+    v.cperm = cperm;
+    v.ccs = ccs;
+    v.rho = rho;
+    v.rho2 = rho2;
+    v.irho = irho;
+    v.active = active;
+    return v;
+  }
+  ~rbf_plan() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    while (!bufs.empty()) release(bufs.back().p);
+    if (host_sc) (void)hipHostFree(host_sc);
+    if (host_small) (void)hipHostFree(host_small);
+    for (const Pending& q : pending) {
+      (void)hipEventDestroy(q.a);
+      (void)hipEventDestroy(q.b);
+    }
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+  }
+};
+
+#define GET(ptr, count)                                                                        \
+  do {                                                                                         \
+    if (!P->get(&(ptr), (count)))                                                              \
+      return fail(RBF_ERR_OOM, "device allocation of %lld elements for " #ptr " failed",       \
+                  (long long)(count));                                                         \
+  } while (0)
+
+namespace {
+
+int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, int32_t* perm,
+              int32_t* cell_start) {
+  uint32_t *ka, *kb;
+  int32_t *va, *vb;
+  void* tmp;
+  const size_t tb = rbf::radix_temp_bytes(count);
+  if (!P->get(&ka, count) || !P->get(&kb, count) || !P->get(&va, count) || !P->get(&vb, count) ||
+      !(tmp = P->alloc_bytes(tb)))
+    return fail(RBF_ERR_OOM, "hash workspace allocation failed");
+  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, ka, va, P->stream));
+  int bits = 1;
+  while ((int64_t(1) << bits) <= (int64_t)P->grid.ncell) ++bits;
+  bool in_alt = false;
+  HIPCHK(rbf::radix_sort_pairs(ka, va, kb, vb, count, bits, tmp, P->stream, &in_alt));
+  const uint32_t* keys = in_alt ? kb : ka;
+  const int32_t* vals = in_alt ? vb : va;
+  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, cell_start, P->stream));
+  HIPCHK(hipMemcpyAsync(perm, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                        P->stream));
+  HIPCHK(rbf::launch_gather_soa(coords, perm, count, P->dim, sorted, P->stream));
+  // the temporaries go back once the stream has consumed them
+  HIPCHK(hipStreamSynchronize(P->stream));
+  P->release(tmp);
+  P->release(vb);
+  P->release(va);
+  P->release(kb);
+  P->release(ka);
+  return RBF_OK;
+}
+
+int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
+  const int64_t n = P->n, m = P->m;
+  const int dim = P->dim;
+  hipStream_t s = P->stream;
+  GET(P->ctr, dim * m);
+  HIPCHK(hipMemcpyAsync(P->ctr, d->centers, sizeof(double) * dim * m, hipMemcpyDeviceToDevice, s));
+  GET(P->rho, m);
+  GET(P->rho2, m);
+  GET(P->irho, m);
+  HIPCHK(rbf::launch_radius_tables(d->rho_per_center, d->rho, m, P->rho, P->rho2, P->irho, s));
+
+  // ranges and finiteness of centres, points and radii: one host read
+  const int nred = 2 * dim + 1;
+  const int nb = 256;
+  double *pmin, *pmax, *res;
+  int* pbad;
+  GET(pmin, nb);
+  GET(pmax, nb);
+  GET(pbad, nb);
+  GET(res, 3 * nred);
+  for (int k = 0; k < dim; ++k) {
+    HIPCHK(rbf::launch_minmax(P->ctr + k * m, m, pmin, pmax, pbad, nb, res + 3 * k, s));
+    HIPCHK(rbf::launch_minmax(d->points + k * n, n, pmin, pmax, pbad, nb, res + 3 * (dim + k), s));
+  }
+  HIPCHK(rbf::launch_minmax(P->rho, m, pmin, pmax, pbad, nb, res + 3 * (2 * dim), s));
+  double host[3 * 7];
+  HIPCHK(hipMemcpyAsync(host, res, sizeof(double) * 3 * nred, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(res);
+  P->release(pbad);
+  P->release(pmax);
+  P->release(pmin);
+  for (int k = 0; k < nred; ++k)
+    if (host[3 * k + 2] != 0.0)
+      return fail(RBF_ERR_NONFINITE, "non-finite %s", k < dim ? "centre coordinate"
+                                                      : k < 2 * dim ? "point coordinate"
+                                                                    : "support radius");
+  const double rho_min = host[3 * 2 * dim], rho_max = host[3 * 2 * dim + 1];
+  if (!(rho_min > 0.0)) return fail(RBF_ERR_INVALID, "support radius must be > 0");
+
+  // grid: cells of size >= max radius over the centres' box widened by 1.5 cells
+  double cs = rho_max * (1.0 + 1e-6);
+  for (int it = 0; it < 64; ++it) {
+    int64_t cells = 1;
+    for (int k = 0; k < dim; ++k) {
+      const double ext = (host[3 * k + 1] - host[3 * k]) + 3.0 * cs;
+      cells *= (int64_t)ceil(ext / cs) + 1;
+    }
+    if (cells <= kMaxCells) break;
+    cs *= 1.25;
+  }
+  P->cell_size = cs;
+  P->grid.inv_cs = 1.0 / cs;
+  int64_t ncell = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < dim) {
+      P->grid.lo[k] = host[3 * k] - 1.5 * cs;
+      const double ext = (host[3 * k + 1] - host[3 * k]) + 3.0 * cs;
+      P->grid.g[k] = (int32_t)ceil(ext / cs) + 1;
+    } else {
+      P->grid.lo[k] = 0.0;
+      P->grid.g[k] = 1;
+    }
+    ncell *= P->grid.g[k];
+  }
+  if (ncell > kMaxCells) return fail(RBF_ERR_INVALID, "hash grid too large");
+  P->grid.ncell = (int32_t)ncell;
+
+  GET(P->ps, dim * n);
+  GET(P->pperm, n);
+  GET(P->pcs, ncell + 2);
+  int rc = hash_into(P, d->points, n, P->ps, P->pperm, P->pcs);
+  if (rc) return rc;
+  GET(P->ctr_s, dim * m);
+  GET(P->cperm, m);
+  GET(P->ccs, ncell + 2);
+  rc = hash_into(P, P->ctr, m, P->ctr_s, P->cperm, P->ccs);
+  if (rc) return rc;
+  GET(P->rho2_s, m);
+  GET(P->irho_s, m);
+  HIPCHK(rbf::launch_gather(P->rho2, P->cperm, m, P->rho2_s, s));
+  HIPCHK(rbf::launch_gather(P->irho, P->cperm, m, P->irho_s, s));
+
+  GET(P->support, m);
+  GET(P->active, m);
+  rbf::PlanView v = P->view();
+  HIPCHK(rbf::launch_support_count(v, P->min_support, P->support, P->active, s));
+
+  int64_t* cnt;
+  int32_t* err;
+  GET(cnt, m + 1);
+  GET(P->lower_cnt, m);
+  GET(P->row_ptr, m + 1);
+  GET(err, 1);
+  HIPCHK(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
+  HIPCHK(rbf::launch_symbolic(v, false, cnt, P->lower_cnt, nullptr, nullptr, err, s));
+  void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
+  if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
+  int64_t nnz = 0;
+  int32_t herr = 0;
+  HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(stmp);
+  P->release(cnt);
+  if (herr)
+    return fail(RBF_ERR_INVALID,
+                "a centre has more than %d neighbouring centres within two support radii",
+                rbf::kMaxCand);
+  if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
+  P->nnz_full = nnz;
+  GET(P->col, nnz);
+  HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, s));
+  P->release(err);
+  P->group = rbf::cg_group_size((double)nnz / (double)std::max<int64_t>(m, 1));
+  return RBF_OK;
+}
+
+template <typename XT>
+rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
+  rbf::CgArgs<XT> a;
+  a.m = P->m;
+  a.p[0] = (XT*)vec[0];
+  a.p[1] = (XT*)vec[1];
+  a.q = (XT*)vec[2];
+  a.r = (XT*)vec[3];
+  a.z = (XT*)vec[4];
+  a.xlo = (XT*)vec[5];
+  a.dinv = dinv;
+  a.xhi = P->xhi;
+  a.r64 = P->r64;
+  a.sc = P->sc;
+  a.part_spmv = P->part_spmv;
+  a.part_upd = P->part_upd;
+  a.spmv_blocks = rbf::cg_grid_blocks(P->m, P->group);
+  a.update_blocks = rbf::cg_update_blocks(P->m);
+  return a;
+}
+
+int ensure_solver(rbf_plan* P, bool fp32) {
+  const int64_t m = P->m;
+  if (!P->xhi) {
+    GET(P->xhi, m);
+    GET(P->r64, m);
+    GET(P->sc, 1);
+    GET(P->part_spmv, rbf::kCgMaxBlocks);
+    GET(P->part_upd, 2 * rbf::kCgMaxBlocks);
+  }
+  void** vec = fp32 ? P->vec32 : P->vec64;
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  for (int k = 0; k < 6; ++k) {
+    if (!vec[k]) {
+      vec[k] = P->alloc_bytes(es * (size_t)m);
+      if (!vec[k]) return fail(RBF_ERR_OOM, "solver vector allocation failed");
+    }
+  }
+  if (!P->host_sc) {
+    HIPCHK(hipHostMalloc((void**)&P->host_sc, sizeof(rbf::CgScalars), hipHostMallocDefault));
+  }
+  return RBF_OK;
+}
+
+int read_scalars(rbf_plan* P) {
+  HIPCHK(hipMemcpyAsync(P->host_sc, P->sc, sizeof(rbf::CgScalars), hipMemcpyDeviceToHost,
+                        P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return RBF_OK;
+}
+
+int assemble_into(rbf_plan* P, int phi, bool fp32) {
+  hipStream_t s = P->stream;
+  rbf::PlanView v = P->view();
+  if (fp32) {
+    if (!P->val32) GET(P->val32, P->nnz_full);
+    if (!P->dinv32) GET(P->dinv32, P->m);
+  } else {
+    if (!P->val64) GET(P->val64, P->nnz_full);
+  }
+  void* val = fp32 ? (void*)P->val32 : (void*)P->val64;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->prof_on) {
+    e0 = P->event();
+    e1 = P->event();
+    if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(e0, s));
+  }
+  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->hs, P->row_ptr, P->lower_cnt, P->col, val, P->g,
+                              P->diag, s));
+  if (P->prof_on) {
+    HIPCHK(hipEventRecord(e1, s));
+    P->pending.push_back({2, -1, e0, e1});
+  }
+  void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
+  HIPCHK(rbf::launch_finalize(P->m, P->active, P->row_ptr, P->lower_cnt, P->diag, P->lambda_rel,
+                              P->lam, fp32, val, dinv, P->dinv64, s));
+  return RBF_OK;
+}
+
+// Reliable-update Jacobi-PCG (see cg_kernels.hip).  Returns a status; the
+// float64 solution is left in P->xhi.
+template <typename VT, typename XT>
+int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_solve_opts& o,
+           int64_t* iters, int64_t* updates, bool allow_stall_exit) {
+  hipStream_t s = P->stream;
+  rbf::CgArgs<XT> a = make_args<XT>(P, vec, dinv);
+  HIPCHK(rbf::cg_setup<XT>(a, P->active, P->g, o.rtol, o.reliable_delta, s));
+  HIPCHK(rbf::cg_true_residual<VT, XT>(a, P->row_ptr, P->col, val, P->g, P->group, 1, 0, s));
+  const int64_t base_iter = *iters;
+  bool fixed_beta = true;  // the next spmv takes beta from the float64 residual
+  double last_true = -1.0;
+  int stalls = 0;
+  for (;;) {
+    int rc = read_scalars(P);
+    if (rc) return rc;
+    const rbf::CgScalars h = *P->host_sc;
+    *iters = base_iter + h.iter;
+    // the buffer holding the latest direction follows the executed iteration
+    // count (launches after a raised flag return at entry)
+    const int parity = (int)(h.iter & 1);
+    if (P->prof_on) P->resolve(*iters);
+    if (h.done == 3) return RBF_OK;
+    if (h.done == 2) return fail(RBF_ERR_BREAKDOWN, "CG breakdown after %lld iterations",
+                                 (long long)h.iter);
+    if (h.done == 1) {
+      if (last_true >= 0.0 && h.rr_true > 0.25 * last_true) {
+        if (++stalls >= 8 && allow_stall_exit) return RBF_WARN_FALLBACK;
+      } else {
+        stalls = 0;
+      }
+      last_true = h.rr_true;
+      HIPCHK(rbf::cg_true_residual<VT, XT>(a, P->row_ptr, P->col, val, P->g, P->group, 0, parity,
+                                           s));
+      *updates += 1;
+      fixed_beta = true;
+      continue;
+    }
+    if (*iters >= o.max_iter) {
+      HIPCHK(rbf::cg_true_residual<VT, XT>(a, P->row_ptr, P->col, val, P->g, P->group, 1, parity,
+                                           s));
+      rc = read_scalars(P);
+      if (rc) return rc;
+      return P->host_sc->done == 3 ? RBF_OK : RBF_WARN_MAXITER;
+    }
+    const int64_t left = o.max_iter - *iters;
+    const int chunk = (int)std::min<int64_t>(left, o.check_every);
+    for (int it = 0; it < chunk; ++it) {
+      const int par = (int)((h.iter + it) & 1);
+      // every fourth launch is bracketed by events when timing is on
+      const bool timed = P->prof_on && (it & 3) == 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = P->event();
+        e1 = P->event();
+        if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(e0, s));
+      }
+      HIPCHK(rbf::cg_spmv<VT, XT>(a, P->row_ptr, P->col, val, P->group, par,
+                                  (fixed_beta && it == 0) ? 1 : 0, s));
+      if (timed) {
+        HIPCHK(hipEventRecord(e1, s));
+        P->pending.push_back({0, *iters + it, e0, e1});
+      }
+      HIPCHK(rbf::cg_update<XT>(a, par, s));
+    }
+    fixed_beta = false;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rbf_last_error(void) { return g_last_error.c_str(); }
+
+const char* rbf_status_string(int status) {
+  switch (status) {
+    case RBF_OK: return "ok";
+    case RBF_WARN_MAXITER: return "warning: iteration limit reached";
+    case RBF_WARN_FALLBACK: return "warning: mixed precision fell back to float64";
+    case RBF_ERR_INVALID: return "invalid argument";
+    case RBF_ERR_NONFINITE: return "non-finite input";
+    case RBF_ERR_SINGULAR: return "singular system";
+    case RBF_ERR_BREAKDOWN: return "conjugate-gradient breakdown";
+    case RBF_ERR_HIP: return "HIP runtime error";
+    case RBF_ERR_OOM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* stream,
+                 rbf_plan** out) {
+  if (!out) return fail(RBF_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(RBF_ERR_INVALID, "desc is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(RBF_ERR_INVALID, "dim must be 2 or 3");
+  if (d->n_points < 1 || d->n_points >= (int64_t(1) << 31))
+    return fail(RBF_ERR_INVALID, "n_points must be in [1, 2^31)");
+  if (d->n_centers < 1 || d->n_centers >= (int64_t(1) << 31))
+    return fail(RBF_ERR_INVALID, "n_centers must be in [1, 2^31)");
+  if (!d->points || !d->centers) return fail(RBF_ERR_INVALID, "points/centers is NULL");
+  if (!d->rho_per_center && !(d->rho > 0.0 && isfinite(d->rho)))
+    return fail(d->rho > 0.0 ? RBF_ERR_NONFINITE : RBF_ERR_INVALID,
+                "rho must be finite and > 0");
+  if (d->min_support < 1) return fail(RBF_ERR_INVALID, "min_support must be >= 1");
+  if (!(d->lambda_rel >= 0.0 && isfinite(d->lambda_rel)))
+    return fail(RBF_ERR_INVALID, "lambda_rel must be finite and >= 0");
+  if (allocator && (!allocator->alloc || !allocator->release))
+    return fail(RBF_ERR_INVALID, "allocator callbacks are NULL");
+  rbf_plan* P = new rbf_plan();
+  if (allocator) {
+    P->alloc = *allocator;
+    P->custom_alloc = true;
+  }
+  P->stream = (hipStream_t)stream;
+  P->dim = d->dim;
+  P->n = d->n_points;
+  P->m = d->n_centers;
+  P->min_support = d->min_support;
+  P->lambda_rel = d->lambda_rel;
+  const int rc = build_plan(P, d);
+  if (rc != RBF_OK) {
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return RBF_OK;
+}
+
+int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
+  if (!P || !o) return fail(RBF_ERR_INVALID, "NULL argument");
+  memset(o, 0, sizeof *o);
+  o->dim = P->dim;
+  for (int k = 0; k < 3; ++k) o->grid[k] = P->grid.g[k];
+  o->n_points = P->n;
+  o->n_centers = P->m;
+  o->nnz_full = P->nnz_full;
+  o->cell_size = P->cell_size;
+  std::vector<int32_t> sup(P->m), low(P->m);
+  std::vector<int64_t> rp(P->m + 1);
+  std::vector<uint8_t> act(P->m);
+  int32_t in_box = 0;
+  HIPCHK(hipMemcpyAsync(sup.data(), P->support, sizeof(int32_t) * P->m, hipMemcpyDeviceToHost,
+                        P->stream));
+  HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (P->m + 1),
+                        hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipMemcpyAsync(act.data(), P->active, P->m, hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipMemcpyAsync(&in_box, P->pcs + P->grid.ncell, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  int64_t na = 0, tot = 0;
+  int32_t smax = 0, rmax = 0;
+  for (int64_t j = 0; j < P->m; ++j) {
+    na += act[j] ? 1 : 0;
+    tot += sup[j];
+    smax = std::max(smax, sup[j]);
+    rmax = std::max<int32_t>(rmax, (int32_t)(rp[j + 1] - rp[j]));
+  }
+  o->n_active = na;
+  o->support_total = tot;
+  o->support_max = smax;
+  o->row_max = rmax;
+  o->nnz_upper = (P->nnz_full + na) / 2;
+  o->n_points_in_box = in_box;
+  o->density = (double)P->nnz_full / ((double)P->m * (double)P->m);
+  return RBF_OK;
+}
+
+int rbf_plan_pattern(const rbf_plan* P, int64_t* row_ptr_h, int32_t* col_h,
+                     int32_t* support_count_h) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  const int64_t m = P->m;
+  std::vector<int64_t> rp(m + 1);
+  std::vector<int32_t> low(m), colf(P->nnz_full);
+  HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost,
+                        P->stream));
+  HIPCHK(hipMemcpyAsync(low.data(), P->lower_cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                        P->stream));
+  if (col_h && P->nnz_full)
+    HIPCHK(hipMemcpyAsync(colf.data(), P->col, sizeof(int32_t) * P->nnz_full,
+                          hipMemcpyDeviceToHost, P->stream));
+  if (support_count_h)
+    HIPCHK(hipMemcpyAsync(support_count_h, P->support, sizeof(int32_t) * m,
+                          hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  int64_t pos = 0;
+  if (row_ptr_h) row_ptr_h[0] = 0;
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t a = rp[j] + low[j], b = rp[j + 1];
+    if (col_h)
+      for (int64_t e = a; e < b; ++e) col_h[pos + (e - a)] = colf[e];
+    pos += b - a;
+    if (row_ptr_h) row_ptr_h[j + 1] = pos;
+  }
+  return RBF_OK;
+}
+
+int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* values) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if ((int)phi < 0 || (int)phi > 3) return fail(RBF_ERR_INVALID, "unknown basis function");
+  if ((int)prec < 0 || (int)prec > 1) return fail(RBF_ERR_INVALID, "unknown precision");
+  if (!values) return fail(RBF_ERR_INVALID, "values is NULL");
+  if (!P->hs) GET(P->hs, P->n);
+  if (!P->g) {
+    GET(P->g, P->m);
+    GET(P->diag, P->m);
+    GET(P->lam, 1);
+    GET(P->dinv64, P->m);
+  }
+  HIPCHK(rbf::launch_gather(values, P->pperm, P->n, P->hs, P->stream));
+  const int rc = assemble_into(P, (int)phi, prec == RBF_PREC_FP32_REFINE);
+  if (rc) return rc;
+  P->phi = (int)phi;
+  P->prec = (int)prec;
+  return RBF_OK;
+}
+
+int rbf_system_export(const rbf_plan* P, double* val_upper_h, double* g_h, double* lambda_h) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (P->prec < 0) return fail(RBF_ERR_INVALID, "nothing assembled");
+  const int64_t m = P->m;
+  if (val_upper_h) {
+    std::vector<int64_t> rp(m + 1);
+    std::vector<int32_t> low(m);
+    std::vector<double> v64;
+    std::vector<float> v32;
+    HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (m + 1),
+                          hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipMemcpyAsync(low.data(), P->lower_cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                          P->stream));
+    if (P->prec == RBF_PREC_FP64) {
+      v64.resize(P->nnz_full);
+      HIPCHK(hipMemcpyAsync(v64.data(), P->val64, sizeof(double) * P->nnz_full,
+                            hipMemcpyDeviceToHost, P->stream));
+    } else {
+      v32.resize(P->nnz_full);
+      HIPCHK(hipMemcpyAsync(v32.data(), P->val32, sizeof(float) * P->nnz_full,
+                            hipMemcpyDeviceToHost, P->stream));
+    }
+    HIPCHK(hipStreamSynchronize(P->stream));
+    int64_t pos = 0;
+    for (int64_t j = 0; j < m; ++j)
+      for (int64_t e = rp[j] + low[j]; e < rp[j + 1]; ++e)
+        val_upper_h[pos++] = P->prec == RBF_PREC_FP64 ? v64[e] : (double)v32[e];
+  }
+  if (g_h) HIPCHK(hipMemcpyAsync(g_h, P->g, sizeof(double) * m, hipMemcpyDeviceToHost, P->stream));
+  if (lambda_h) HIPCHK(hipMemcpyAsync(lambda_h, P->lam, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return RBF_OK;
+}
+
+int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!coeffs) return fail(RBF_ERR_INVALID, "coeffs is NULL");
+  if (P->prec < 0) return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_solve");
+  rbf_solve_opts o;
+  o.rtol = 1e-10;
+  o.max_iter = 100000;
+  o.warm_start = 0;
+  o.check_every = 32;
+  o.reliable_delta = 0.1;
+  if (opts) o = *opts;
+  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 ||
+      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0))
+    return fail(RBF_ERR_INVALID, "bad solve options");
+  const bool fp32 = P->prec == RBF_PREC_FP32_REFINE;
+  int rc = ensure_solver(P, fp32);
+  if (rc) return rc;
+  hipStream_t s = P->stream;
+  if (o.warm_start)
+    HIPCHK(hipMemcpyAsync(P->xhi, coeffs, sizeof(double) * P->m, hipMemcpyDeviceToDevice, s));
+  else
+    HIPCHK(hipMemsetAsync(P->xhi, 0, sizeof(double) * P->m, s));
+  int64_t iters = 0, updates = 0;
+  int used = P->prec;
+  if (fp32) {
+    rc = run_cg<float, float>(P, P->val32, P->dinv32, P->vec32, o, &iters, &updates, true);
+    if (rc == RBF_WARN_FALLBACK || rc == RBF_ERR_BREAKDOWN || rc == RBF_WARN_MAXITER) {
+      // finish in float64 from the current float64 solution
+      const int rc2 = ensure_solver(P, false);
+      if (rc2) return rc2;
+      const int rc3 = assemble_into(P, P->phi, false);
+      if (rc3) return rc3;
+      const int64_t left = o.max_iter - iters;
+      if (left > 0) {
+        rbf_solve_opts o2 = o;
+        o2.max_iter = iters + left;
+        const int rc4 = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o2, &iters,
+                                               &updates, false);
+        rc = rc4 == RBF_OK ? RBF_WARN_FALLBACK : rc4;
+        used = RBF_PREC_FP64;
+      }
+    }
+  } else {
+    rc = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters, &updates, false);
+  }
+  if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;
+  HIPCHK(hipMemcpyAsync(coeffs, P->xhi, sizeof(double) * P->m, hipMemcpyDeviceToDevice, s));
+  const int rcr = read_scalars(P);
+  if (rcr) return rcr;
+  double lam = 0.0;
+  HIPCHK(hipMemcpyAsync(&lam, P->lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    info->iterations = iters;
+    info->reliable_updates = updates;
+    const double gg = P->host_sc->gg;
+    info->rel_residual = gg > 0 ? sqrt(P->host_sc->rr_true / gg) : 0.0;
+    info->lambda = lam;
+    info->precision = used;
+    info->status = rc;
+  }
+  return rc;
+}
+
+int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,
+             double* out, const double* values, double* rmse_h) {
+  rbf_plan* P = const_cast<rbf_plan*>(Pc);
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (nq < 0) return fail(RBF_ERR_INVALID, "n_query < 0");
+  if (nq > 0 && (!queries || !coeffs || !out)) return fail(RBF_ERR_INVALID, "NULL pointer");
+  if (values && !rmse_h) return fail(RBF_ERR_INVALID, "rmse_h is NULL");
+  hipStream_t s = P->stream;
+  if (!P->cs_sorted) GET(P->cs_sorted, P->m);
+  if (nq > 0) {
+    HIPCHK(rbf::launch_gather(coeffs, P->cperm, P->m, P->cs_sorted, s));
+    HIPCHK(rbf::launch_eval(P->view(), P->phi < 0 ? 1 : P->phi, nq, queries, P->cs_sorted,
+                            P->rho2_s, P->irho_s, out, s));
+  }
+  if (values) {
+    if (nq == 0) {
+      *rmse_h = 0.0;
+      return RBF_OK;
+    }
+    if (!P->eval_part) GET(P->eval_part, 1025);
+    const int nb = rbf::sq_err_blocks(nq);
+    HIPCHK(rbf::launch_sq_err(out, values, nq, P->eval_part, nb, P->eval_part + 1024, s));
+    double sum = 0.0;
+    HIPCHK(hipMemcpyAsync(&sum, P->eval_part + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *rmse_h = sqrt(sum / (double)nq);
+  }
+  return RBF_OK;
+}
+
+int rbf_profile(rbf_plan* P, int32_t enable) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  HIPCHK(hipStreamSynchronize(P->stream));
+  P->resolve(INT64_MAX);
+  for (int k = 0; k < 3; ++k) {
+    P->prof_launches[k] = 0;
+    P->prof_ms[k] = 0.0;
+  }
+  P->prof_on = enable != 0;
+  return RBF_OK;
+}
+
+int rbf_profile_read(rbf_plan* P, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!P || kernel < 0 || kernel > 2) return fail(RBF_ERR_INVALID, "bad plan or kernel id");
+  HIPCHK(hipStreamSynchronize(P->stream));
+  P->resolve(INT64_MAX);
+  if (launches) *launches = P->prof_launches[kernel];
+  if (total_ms) *total_ms = P->prof_ms[kernel];
+  return RBF_OK;
+}
+
+void rbf_plan_destroy(rbf_plan* P) { delete P; }
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+// Numeric assembly of the normal equations (Section 5, eq. 11-12):
+//
+//     b_jl = sum_{k in supp(j) and supp(l)} phi_kj * phi_kl      (l >= j)
+//     g_j  = sum_{k in supp(j)} phi_kj * h_k
+//
+// One wave owns one row j: it streams the points of supp(j) through LDS in the
+// sorted order of the hash, and every lane owns up to kSlots columns of the
+// upper part of the row.  Each accumulator has exactly one writer (no atomics),
+// so the summation order is fixed and the result is deterministic.  The upper
+// value is also written to its mirror position (l, j) of the full CSR, which
+// the solver reads, so the stored matrix is exactly symmetric.  A is never
+// materialised: phi is evaluated on the fly.
+//
+// FP64 variant: float64 phi and float64 accumulation.
+// FP32 variant: squared distance and support test in float64 (the pattern is
+// fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
+#include "plan_kernels.h"
+
+namespace rbf {
+namespace {
+
+constexpr int kAsmChunk = 256;
+constexpr int kSlots = 4;  // columns per lane in one pass: 256 per pass
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  double s = 0.0;
+  __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct Acc<float> {
+  Kahan32 k;
+  __device__ __forceinline__ void add(float v) { k.add(v); }
+  __device__ __forceinline__ float value() const { return k.s; }
+};
+
+template <typename T>
+__device__ __forceinline__ T scaled_r(double s, double irho);
+template <>
+__device__ __forceinline__ double scaled_r<double>(double s, double irho) {
+  return __builtin_sqrt(s) * irho;
+}
+template <>
+__device__ __forceinline__ float scaled_r<float>(double s, double irho) {
+  return __builtin_sqrtf((float)s) * (float)irho;
+}
+
+template <int DIM, int PHI, typename T>
+__global__ __launch_bounds__(kWave) void k_assemble(PlanView P, const double* __restrict__ hs,
+                                                    const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ lower_cnt,
+                                                    const int32_t* __restrict__ col,
+                                                    T* __restrict__ val, double* __restrict__ g,
+                                                    double* __restrict__ diag) {
+  __shared__ double sp[DIM][kAsmChunk];
+  __shared__ int32_t sidx[kAsmChunk];
+  __shared__ T sphi[kAsmChunk];
+  const int lane = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  if (!P.active[j]) {
+    if (lane == 0) {
+      g[j] = 0.0;
+      diag[j] = 0.0;
+    }
+    return;
+  }
+  double xj[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xj[d] = P.ctr[d * P.m + j];
+  const double r2j = P.rho2[j], irj = P.irho[j];
+  const int64_t e0 = row_ptr[j] + lower_cnt[j];
+  const int64_t e1 = row_ptr[j + 1];
+  const int64_t R = e1 - e0;
+  Acc<T> gacc;
+  for (int64_t cb = 0; cb < R; cb += (int64_t)kWave * kSlots) {
+    const int nslot = (int)((R - cb + kWave - 1) / kWave) < kSlots
+                          ? (int)((R - cb + kWave - 1) / kWave)
+                          : kSlots;
+    double xl[kSlots][DIM];
+    double r2l[kSlots], irl[kSlots];
+    int32_t lcol[kSlots];
+    bool ok[kSlots];
+    Acc<T> acc[kSlots];
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) {
+      const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
+      ok[t] = t < nslot && e < e1;
+      lcol[t] = ok[t] ? col[e] : 0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) xl[t][d] = ok[t] ? P.ctr[d * P.m + lcol[t]] : 0.0;
+      r2l[t] = ok[t] ? P.rho2[lcol[t]] : 0.0;
+      irl[t] = ok[t] ? P.irho[lcol[t]] : 0.0;
+    }
+    const bool first = cb == 0;
+    stream_support<DIM, kAsmChunk>(P, xj, r2j, sp, sidx, [&](int np) {
+      // phi_kj of the chunk's points, and their share of g_j
+      for (int q = lane; q < np; q += kWave) {
+        double p[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) p[d] = sp[d][q];
+        const T phij = wendland<PHI, T>(scaled_r<T>(sqdist<DIM>(p, xj), irj));
+        sphi[q] = phij;
+        if (first) gacc.add(phij * (T)hs[sidx[q]]);
+      }
+      __syncthreads();
+      for (int q = 0; q < np; ++q) {
+        double p[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) p[d] = sp[d][q];
+        const T phij = sphi[q];
+#pragma unroll
+        for (int t = 0; t < kSlots; ++t) {
+          if (t < nslot && ok[t]) {
+            const double s = sqdist<DIM>(p, xl[t]);
+            if (s < r2l[t]) acc[t].add(phij * wendland<PHI, T>(scaled_r<T>(s, irl[t])));
+          }
+        }
+      }
+    });
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) {
+      if (!ok[t]) continue;
+      const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
+      const T v = acc[t].value();
+      val[e] = v;
+      const int32_t l = lcol[t];
+      if (l == (int32_t)j) {
+        diag[j] = (double)v;
+      } else {
+        // mirror (l, j): j sits in the lower part of row l, columns ascending
+        int64_t lo = row_ptr[l], hi = row_ptr[l] + lower_cnt[l];
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
+        }
+        val[lo] = v;
+      }
+    }
+  }
+  double gl;
+  if constexpr (sizeof(T) == 8) {
+    gl = gacc.value();
+  } else {
+    gl = (double)gacc.k.s - (double)gacc.k.c;
+  }
+  gl = wave_sum(gl);
+  if (lane == 0) g[j] = gl;
+}
+
+constexpr int kRed = 256;
+
+// lambda = lambda_rel * mean(diag over active centres), written to lam[0].
+__global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__ diag,
+                                                      const uint8_t* __restrict__ active,
+                                                      int64_t m, double lambda_rel,
+                                                      double* __restrict__ lam) {
+  __shared__ double ws[kRed / kWave];
+  __shared__ int64_t wc[kRed / kWave];
+  double s = 0.0;
+  int64_t c = 0;
+  for (int64_t j = threadIdx.x; j < m; j += kRed) {
+    if (active[j]) {
+      s += diag[j];
+      c += 1;
+    }
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor((long long)c, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    ws[threadIdx.x / kWave] = s;
+    wc[threadIdx.x / kWave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ts = 0.0;
+    int64_t tc = 0;
+    for (int w = 0; w < kRed / kWave; ++w) {
+      ts += ws[w];
+      tc += wc[w];
+    }
+    lam[0] = tc > 0 ? lambda_rel * (ts / (double)tc) : 0.0;
+  }
+}
+
+// Adds lambda to the stored diagonal and forms the Jacobi inverse diagonal
+// from the value actually stored.
+template <typename T>
+__global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
+                            const int64_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ lower_cnt, const double* __restrict__ lam,
+                            T* __restrict__ val, T* __restrict__ dinv,
+                            double* __restrict__ dinv64) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  if (!active[j]) {
+    dinv[j] = (T)0;
+    dinv64[j] = 0.0;
+    return;
+  }
+  const int64_t e = row_ptr[j] + lower_cnt[j];
+  const T v = (T)((double)val[e] + lam[0]);
+  val[e] = v;
+  dinv[j] = (T)1 / v;
+  dinv64[j] = 1.0 / (double)v;
+}
+
+template <int DIM, typename T>
+hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int64_t* row_ptr,
+                        const int32_t* lower_cnt, const int32_t* col, T* val, double* g,
+                        double* diag, hipStream_t s) {
+  const dim3 grid((unsigned)P.m), block(kWave);
+  switch (phi) {
+    case 0:
+      hipLaunchKernelGGL((k_assemble<DIM, 0, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
+                         col, val, g, diag);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_assemble<DIM, 1, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
+                         col, val, g, diag);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_assemble<DIM, 2, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
+                         col, val, g, diag);
+      break;
+    default:
+      hipLaunchKernelGGL((k_assemble<DIM, 3, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
+                         col, val, g, diag);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
+                           const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
+                           void* val, double* g, double* diag, hipStream_t s) {
+  if (P.m <= 0) return hipSuccess;
+  if (P.dim == 2) {
+    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, (float*)val, g, diag, s)
+                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, (double*)val, g, diag, s);
+  }
+  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, (float*)val, g, diag, s)
+              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, (double*)val, g, diag, s);
+}
+
+hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* row_ptr,
+                           const int32_t* lower_cnt, const double* diag, double lambda_rel,
+                           double* lam, bool fp32, void* val, void* dinv, double* dinv64,
+                           hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ridge_value, dim3(1), dim3(kRed), 0, s, diag, active, m, lambda_rel, lam);
+  const int bs = 256;
+  const dim3 grid((unsigned)((m + bs - 1) / bs));
+  if (fp32)
+    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, row_ptr, lower_cnt,
+                       (const double*)lam, (float*)val, (float*)dinv, dinv64);
+  else
+    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, row_ptr, lower_cnt,
+                       (const double*)lam, (double*)val, (double*)dinv, dinv64);
+  return hipGetLastError();
+}
+
+}  // namespace rbf

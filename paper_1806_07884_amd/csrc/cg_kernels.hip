@@ -1,0 +1,382 @@
+// Jacobi-preconditioned conjugate gradients on the assembled normal equations.
+//
+// One CG iteration k is two kernels, with every cross-block scalar carried
+// from one kernel to the next through plain per-block partial sums:
+//
+//   spmv(k):   every block reduces the previous update's partials of r.z and
+//              r.r (same fixed order in every block, so all blocks agree),
+//              checks the trigger, forms beta = rz_k / rz_{k-1}, then
+//              p_new = z + beta p_old (on the fly for every column it reads),
+//              q = (B + lambda I) p_new and a partial of p_new . q.
+//   update(k): every block reduces the partials of p . q, forms
+//              alpha = rz_k / (p . q); x += alpha p; r -= alpha q;
+//              z = D^-1 r; partials of r . z and r . r.
+//
+// Kernel boundaries make the partials of one kernel visible to every block of
+// the next on all XCDs, so no device-scope fence (an L2 write-back per block
+// on this chip) is ever executed.  Scalars the host reads are written by block
+// 0 of each kernel.  Once a flag is raised the remaining launched kernels
+// return at entry.
+//
+// Precision: the matrix and the iterated vectors are VT / XT (float64, or
+// float32 for the mixed path); every dot product is accumulated in float64.
+// The solution is kept in float64; at a reliable update the float64 residual
+// g - (B + lambda I) x is recomputed and replaces the iterated one.
+#include "plan_kernels.h"
+#include "solver.h"
+
+namespace rbf {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int G>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block-wide sum of one double per thread in a fixed order; every thread gets it.
+__device__ __forceinline__ double block_sum(double v, double* ws) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) t += ws[w];
+  return t;
+}
+
+// Sum of n partials part[stride * k + off], identical in every block.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n,
+                                                  int stride, int off, double* ws) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += kBlock) s += part[stride * k + off];
+  return block_sum(s, ws);
+}
+
+template <typename VT, typename XT, int G>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(
+    int64_t m, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const VT* __restrict__ val, const XT* __restrict__ z, const XT* __restrict__ pold,
+    XT* __restrict__ pnew, XT* __restrict__ q, CgScalars* __restrict__ sc,
+    const double* __restrict__ part_in, int n_in, double* __restrict__ part_out, int parity,
+    int fixed_beta) {
+  __shared__ double ws[kBlock / kWave];
+  if (sc->done) return;
+  const double rz = reduce_partials(part_in, n_in, 2, 0, ws);
+  const double rr = reduce_partials(part_in, n_in, 2, 1, ws);
+  if (!__builtin_isfinite(rz) || !__builtin_isfinite(rr)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
+    return;
+  }
+  if (rr <= sc->trigger2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rr = rr;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double beta_d = fixed_beta ? sc->beta_fixed : rz / sc->rzh[parity ^ 1];
+  const XT beta = (XT)beta_d;
+  double contrib = 0.0;
+  const int sub = threadIdx.x & (G - 1);
+  for (int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; row < m;
+       row += (int64_t)gridDim.x * (kBlock / G)) {
+    XT acc = (XT)0;
+    const int64_t e1 = row_ptr[row + 1];
+    for (int64_t e = row_ptr[row] + sub; e < e1; e += G) {
+      const int32_t l = col[e];
+      acc += (XT)val[e] * (z[l] + beta * pold[l]);
+    }
+    acc = group_sum<XT, G>(acc);
+    if (sub == 0) {
+      const XT pj = z[row] + beta * pold[row];
+      pnew[row] = pj;
+      q[row] = acc;
+      contrib += (double)pj * (double)acc;
+    }
+  }
+  const double bs = block_sum(contrib, ws);
+  if (threadIdx.x == 0) {
+    part_out[blockIdx.x] = bs;
+    if (blockIdx.x == 0) {
+      sc->rzh[parity] = rz;
+      sc->rr = rr;
+      sc->beta = beta_d;
+    }
+  }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_cg_update(
+    int64_t m, const XT* __restrict__ p, const XT* __restrict__ q, XT* __restrict__ x,
+    XT* __restrict__ r, XT* __restrict__ z, const XT* __restrict__ dinv,
+    CgScalars* __restrict__ sc, const double* __restrict__ part_in, int n_in,
+    double* __restrict__ part_out, int parity) {
+  __shared__ double ws[kBlock / kWave];
+  if (sc->done) return;
+  const double pq = reduce_partials(part_in, n_in, 1, 0, ws);
+  if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
+    return;
+  }
+  const double alpha_d = sc->rzh[parity] / pq;
+  const XT alpha = (XT)alpha_d;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * kBlock) {
+    const XT xj = x[j] + alpha * p[j];
+    const XT rj = r[j] - alpha * q[j];
+    const XT zj = dinv[j] * rj;
+    x[j] = xj;
+    r[j] = rj;
+    z[j] = zj;
+    rz += (double)rj * (double)zj;
+    rr += (double)rj * (double)rj;
+  }
+  const double brz = block_sum(rz, ws);
+  const double brr = block_sum(rr, ws);
+  if (threadIdx.x == 0) {
+    part_out[2 * blockIdx.x] = brz;
+    part_out[2 * blockIdx.x + 1] = brr;
+    if (blockIdx.x == 0) {
+      sc->alpha = alpha_d;
+      sc->pq = pq;
+      sc->iter += 1;
+    }
+  }
+}
+
+// x_hi += x_lo; x_lo = 0 (x_lo is the iterated correction).
+template <typename XT>
+__global__ void k_fold_solution(int64_t m, double* __restrict__ xhi, XT* __restrict__ xlo) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  xhi[j] += (double)xlo[j];
+  xlo[j] = (XT)0;
+}
+
+// Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, then
+// r = (XT) r64 and z = D^-1 r, row by row (G lanes per row).
+template <typename VT, typename XT, int G>
+__global__ __launch_bounds__(kBlock) void k_true_residual(
+    int64_t m, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const VT* __restrict__ val, const double* __restrict__ xhi, const double* __restrict__ g,
+    const XT* __restrict__ dinv, double* __restrict__ r64, XT* __restrict__ r,
+    XT* __restrict__ z) {
+  const int sub = threadIdx.x & (G - 1);
+  for (int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; row < m;
+       row += (int64_t)gridDim.x * (kBlock / G)) {
+    double acc = 0.0;
+    const int64_t e1 = row_ptr[row + 1];
+    for (int64_t e = row_ptr[row] + sub; e < e1; e += G) acc += (double)val[e] * xhi[col[e]];
+    acc = group_sum<double, G>(acc);
+    if (sub == 0) {
+      const double rv = g[row] - acc;
+      const XT ri = (XT)rv;
+      r64[row] = rv;
+      r[row] = ri;
+      z[row] = dinv[row] * ri;
+    }
+  }
+}
+
+// Partials of r.z and r64.r64 in the update kernel's layout.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void k_residual_dots(int64_t m, const double* __restrict__ r64,
+                                                          const XT* __restrict__ r,
+                                                          const XT* __restrict__ z,
+                                                          double* __restrict__ part_out) {
+  __shared__ double ws[kBlock / kWave];
+  double rz = 0.0, rr = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * kBlock) {
+    rz += (double)r[j] * (double)z[j];
+    rr += r64[j] * r64[j];
+  }
+  const double brz = block_sum(rz, ws);
+  const double brr = block_sum(rr, ws);
+  if (threadIdx.x == 0) {
+    part_out[2 * blockIdx.x] = brz;
+    part_out[2 * blockIdx.x + 1] = brr;
+  }
+}
+
+// After a float64 residual: sets the true residual norm, the convergence flag,
+// the next trigger, and the beta the next spmv takes (0 on a restart,
+// rz_true / rz_{k-1} on a reliable update).
+__global__ __launch_bounds__(kBlock) void k_residual_scalars(CgScalars* __restrict__ sc,
+                                                             const double* __restrict__ part,
+                                                             int n, int restart, int parity) {
+  __shared__ double ws[kBlock / kWave];
+  const double rz = reduce_partials(part, n, 2, 0, ws);
+  const double rr = reduce_partials(part, n, 2, 1, ws);
+  if (threadIdx.x == 0) {
+    sc->rr_true = rr;
+    sc->rr = rr;
+    sc->beta_fixed = restart ? 0.0 : rz / sc->rzh[parity ^ 1];
+    const double trig = sc->delta2 * rr;
+    sc->trigger2 = trig > sc->tol2 ? trig : sc->tol2;
+    if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
+      sc->done = 2;
+    } else if (rr <= sc->tol2) {
+      sc->done = 3;
+    } else {
+      sc->done = 0;
+    }
+  }
+}
+
+template <typename XT>
+__global__ void k_zero_inactive(int64_t m, const uint8_t* __restrict__ active,
+                                double* __restrict__ xhi, XT* __restrict__ xlo,
+                                XT* __restrict__ p0, XT* __restrict__ p1) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  if (!active[j]) xhi[j] = 0.0;
+  xlo[j] = (XT)0;
+  p0[j] = (XT)0;
+  p1[j] = (XT)0;
+}
+
+// ||g||^2 and the initial state of the scalars (single block, fixed order).
+__global__ __launch_bounds__(kBlock) void k_cg_init(int64_t m, const double* __restrict__ g,
+                                                    CgScalars* __restrict__ sc, double rtol,
+                                                    double delta) {
+  __shared__ double ws[kBlock / kWave];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < m; j += kBlock) s += g[j] * g[j];
+  s = block_sum(s, ws);
+  if (threadIdx.x == 0) {
+    sc->gg = s;
+    sc->tol2 = rtol * rtol * s;
+    sc->delta2 = delta * delta;
+    sc->trigger2 = sc->tol2;
+    sc->done = 0;
+    sc->iter = 0;
+    sc->rzh[0] = sc->rzh[1] = 1.0;
+    sc->beta = sc->beta_fixed = 0.0;
+    sc->alpha = sc->pq = 0.0;
+  }
+}
+
+template <typename VT, typename XT, int G>
+void launch_spmv_g(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
+                   int parity, int fixed_beta, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_spmv<VT, XT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
+                     row_ptr, col, val, (const XT*)a.z, (const XT*)a.p[parity],
+                     a.p[parity ^ 1], a.q, a.sc, (const double*)a.part_upd, a.update_blocks,
+                     a.part_spmv, parity, fixed_beta);
+}
+
+template <typename VT, typename XT, int G>
+void launch_true_residual_g(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
+                            const VT* val, const double* g, hipStream_t s) {
+  hipLaunchKernelGGL((k_true_residual<VT, XT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
+                     row_ptr, col, val, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r,
+                     a.z);
+}
+
+bool grids_ok(int spmv_blocks, int update_blocks) {
+  return spmv_blocks >= 1 && spmv_blocks <= kCgMaxBlocks && update_blocks >= 1 &&
+         update_blocks <= kCgMaxBlocks;
+}
+
+}  // namespace
+
+int cg_group_size(double mean_row) {
+  if (mean_row > 192) return 64;
+  if (mean_row > 96) return 32;
+  if (mean_row > 24) return 16;
+  return 8;
+}
+
+int cg_grid_blocks(int64_t m, int group) {
+  const int64_t rows_per_block = kBlock / group;
+  const int64_t b = (m + rows_per_block - 1) / rows_per_block;
+  return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
+}
+
+int cg_update_blocks(int64_t m) {
+  const int64_t b = (m + kBlock - 1) / kBlock;
+  return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
+}
+
+template <typename VT, typename XT>
+hipError_t cg_spmv(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
+                   int group, int parity, int fixed_beta, hipStream_t s) {
+  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+  switch (group) {
+    case 8: launch_spmv_g<VT, XT, 8>(a, row_ptr, col, val, parity, fixed_beta, s); break;
+    case 16: launch_spmv_g<VT, XT, 16>(a, row_ptr, col, val, parity, fixed_beta, s); break;
+    case 32: launch_spmv_g<VT, XT, 32>(a, row_ptr, col, val, parity, fixed_beta, s); break;
+    default: launch_spmv_g<VT, XT, 64>(a, row_ptr, col, val, parity, fixed_beta, s); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s) {
+  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+  // the direction written by the preceding spmv sits in p[parity ^ 1]
+  hipLaunchKernelGGL(k_cg_update<XT>, dim3(a.update_blocks), dim3(kBlock), 0, s, a.m,
+                     (const XT*)a.p[parity ^ 1], (const XT*)a.q, a.xlo, a.r, a.z,
+                     (const XT*)a.dinv, a.sc, (const double*)a.part_spmv, a.spmv_blocks,
+                     a.part_upd, parity);
+  return hipGetLastError();
+}
+
+template <typename VT, typename XT>
+hipError_t cg_true_residual(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
+                            const VT* val, const double* g, int group, int restart, int parity,
+                            hipStream_t s) {
+  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+  const int bs = 256;
+  const dim3 eg((unsigned)((a.m + bs - 1) / bs));
+  hipLaunchKernelGGL(k_fold_solution<XT>, eg, dim3(bs), 0, s, a.m, a.xhi, a.xlo);
+  switch (group) {
+    case 8: launch_true_residual_g<VT, XT, 8>(a, row_ptr, col, val, g, s); break;
+    case 16: launch_true_residual_g<VT, XT, 16>(a, row_ptr, col, val, g, s); break;
+    case 32: launch_true_residual_g<VT, XT, 32>(a, row_ptr, col, val, g, s); break;
+    default: launch_true_residual_g<VT, XT, 64>(a, row_ptr, col, val, g, s); break;
+  }
+  hipLaunchKernelGGL(k_residual_dots<XT>, dim3(a.update_blocks), dim3(kBlock), 0, s, a.m,
+                     (const double*)a.r64, (const XT*)a.r, (const XT*)a.z, a.part_upd);
+  hipLaunchKernelGGL(k_residual_scalars, dim3(1), dim3(kBlock), 0, s, a.sc,
+                     (const double*)a.part_upd, a.update_blocks, restart, parity);
+  return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
+                    double delta, hipStream_t s) {
+  const int bs = 256;
+  const dim3 eg((unsigned)((a.m + bs - 1) / bs));
+  hipLaunchKernelGGL(k_zero_inactive<XT>, eg, dim3(bs), 0, s, a.m, active, a.xhi, a.xlo, a.p[0],
+                     a.p[1]);
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kBlock), 0, s, a.m, g, a.sc, rtol, delta);
+  return hipGetLastError();
+}
+
+template hipError_t cg_spmv<double, double>(const CgArgs<double>&, const int64_t*,
+                                            const int32_t*, const double*, int, int, int,
+                                            hipStream_t);
+template hipError_t cg_spmv<float, float>(const CgArgs<float>&, const int64_t*, const int32_t*,
+                                          const float*, int, int, int, hipStream_t);
+template hipError_t cg_update<double>(const CgArgs<double>&, int, hipStream_t);
+template hipError_t cg_update<float>(const CgArgs<float>&, int, hipStream_t);
+template hipError_t cg_true_residual<double, double>(const CgArgs<double>&, const int64_t*,
+                                                     const int32_t*, const double*, const double*,
+                                                     int, int, int, hipStream_t);
+template hipError_t cg_true_residual<float, float>(const CgArgs<float>&, const int64_t*,
+                                                   const int32_t*, const float*, const double*,
+                                                   int, int, int, hipStream_t);
+template hipError_t cg_setup<double>(const CgArgs<double>&, const uint8_t*, const double*, double,
+                                     double, hipStream_t);
+template hipError_t cg_setup<float>(const CgArgs<float>&, const uint8_t*, const double*, double,
+                                    double, hipStream_t);
+
+}  // namespace rbf

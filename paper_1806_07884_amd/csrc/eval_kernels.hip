@@ -1,0 +1,129 @@
+// Evaluation of the approximant (Section 2, eq. 3):
+//     f(y) = sum_j c_j phi(||y - xi_j|| / rho_j)   over centres with y in supp(j),
+// one thread per query point, centres found through the centre hash, plus
+// the root-mean-square error against given values.
+#include "plan_kernels.h"
+
+namespace rbf {
+namespace {
+
+template <int DIM, int PHI>
+__global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const double* __restrict__ y,
+                                              const double* __restrict__ cs,
+                                              const double* __restrict__ rho2_s,
+                                              const double* __restrict__ irho_s,
+                                              double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  double p[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) p[d] = y[d * nq + q];
+  int c[3];
+  double acc = 0.0;
+  if (cell_of<DIM>(P.grid, p, c)) {
+    NbrWalk<DIM> walk(P.grid, c, 1);
+    for (int k = 0; k < walk.rows(); ++k) {
+      int lo_id, hi_id;
+      if (!walk.range(k, lo_id, hi_id)) continue;
+      const int lo = P.ccs[lo_id], hi = P.ccs[hi_id + 1];
+      for (int i = lo; i < hi; ++i) {
+        double xl[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
+        const double s = sqdist<DIM>(p, xl);
+        if (s < rho2_s[i]) acc += cs[i] * wendland<PHI, double>(__builtin_sqrt(s) * irho_s[i]);
+      }
+    }
+  }
+  out[q] = acc;
+}
+
+__global__ void k_gather(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                         int64_t n, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+constexpr int kRed = 256;
+
+__global__ __launch_bounds__(kRed) void k_sq_err(const double* __restrict__ f,
+                                                 const double* __restrict__ h, int64_t n,
+                                                 double* __restrict__ part) {
+  __shared__ double ws[kRed / kWave];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRed + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRed) {
+    const double d = f[i] - h[i];
+    s += d * d;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kRed / kWave; ++w) t += ws[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kRed) void k_sum_final(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ out) {
+  __shared__ double ws[kRed / kWave];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kRed) s += part[k];
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kRed / kWave; ++w) t += ws[w];
+    out[0] = t;
+  }
+}
+
+template <int DIM>
+void eval_dim(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
+              const double* rho2_s, const double* irho_s, double* out, hipStream_t s) {
+  const int bs = 256;
+  const dim3 grid((unsigned)((nq + bs - 1) / bs));
+  switch (phi) {
+    case 0: hipLaunchKernelGGL((k_eval<DIM, 0>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
+    case 1: hipLaunchKernelGGL((k_eval<DIM, 1>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
+    case 2: hipLaunchKernelGGL((k_eval<DIM, 2>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
+    default: hipLaunchKernelGGL((k_eval<DIM, 3>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, double* dst,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, src, perm, n,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
+                       const double* rho2_s, const double* irho_s, double* out, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  if (P.dim == 2)
+    eval_dim<2>(P, phi, nq, y, cs, rho2_s, irho_s, out, s);
+  else
+    eval_dim<3>(P, phi, nq, y, cs, rho2_s, irho_s, out, s);
+  return hipGetLastError();
+}
+
+int sq_err_blocks(int64_t n) {
+  int64_t b = (n + kRed - 1) / kRed;
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_sq_err(const double* f, const double* h, int64_t n, double* part, int nb,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sq_err, dim3(nb), dim3(kRed), 0, s, f, h, n, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kRed), 0, s, (const double*)part, nb, out);
+  return hipGetLastError();
+}
+
+}  // namespace rbf

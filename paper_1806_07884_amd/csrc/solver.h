@@ -1,0 +1,67 @@
+// Device scalars and argument bundles of the conjugate-gradient kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace rbf {
+
+// Most blocks of any CG kernel; bounds the partial-sum arrays.
+constexpr int kCgMaxBlocks = 1024;
+
+// Scalars of one CG solve, kept in device memory.  Each is written by block 0
+// of one kernel and read by later kernels (or the host) only.
+struct CgScalars {
+  double rzh[2];     // r . z of iterate k at [k & 1]
+  double beta_fixed; // beta of the next spmv after a float64 residual
+  double alpha, beta, pq;
+  double rr;         // ||r||^2 of the iterated residual (last seen)
+  double rr_true;    // ||g - (B + lambda I) x||^2 at the last float64 recomputation
+  double gg;         // ||g||^2
+  double tol2;       // rtol^2 * gg
+  double delta2;     // reliable-update factor squared
+  double trigger2;   // iterated ||r||^2 at which the spmv raises the flag
+  int64_t iter;      // executed iterations
+  int32_t done;      // 0 running, 1 trigger reached, 2 breakdown, 3 converged
+  int32_t pad_;
+};
+
+template <typename XT>
+struct CgArgs {
+  int64_t m;
+  XT* p[2];
+  XT* q;
+  XT* r;
+  XT* z;
+  XT* xlo;            // iterated correction
+  const XT* dinv;
+  double* xhi;        // float64 solution
+  double* r64;        // float64 true residual
+  CgScalars* sc;
+  double* part_spmv;  // [spmv_blocks] partials of p . q
+  double* part_upd;   // [2 * update_blocks] partials of r . z and r . r
+  int spmv_blocks;
+  int update_blocks;
+};
+
+int cg_group_size(double mean_row);
+int cg_grid_blocks(int64_t m, int group);
+int cg_update_blocks(int64_t m);
+
+// Iteration k = cg_spmv(parity = k & 1) then cg_update(parity).  fixed_beta:
+// the spmv takes beta from the last float64 residual (first iteration after
+// set-up or a reliable update).
+template <typename VT, typename XT>
+hipError_t cg_spmv(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
+                   int group, int parity, int fixed_beta, hipStream_t s);
+template <typename XT>
+hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s);
+// x_hi += x_lo; float64 residual; r, z from it; scalars for the next spmv.
+template <typename VT, typename XT>
+hipError_t cg_true_residual(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
+                            const VT* val, const double* g, int group, int restart, int parity,
+                            hipStream_t s);
+template <typename XT>
+hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
+                    double delta, hipStream_t s);
+
+}  // namespace rbf

@@ -296,3 +296,14 @@ def test_density_definition_on_oracle():
     ne = orc.normal_equations(pts, h, ctr, rho, "w31")
     dense = ne.full_matrix(with_ridge=False).toarray()
     assert ne.nnz_full == np.count_nonzero(dense)
+
+
+def test_sample_row_full_equals_full_matrix():
+    pts, h, ctr, rho = _tiny(17, n=1500, m=64, rho=0.2)
+    ne = orc.normal_equations(pts, h, ctr, rho, "w31")
+    full = ne.full_matrix(with_ridge=False).tocsr()
+    for j in (5, 30, 63):
+        row = orc.sample_row(pts, h, ctr, rho, "w31", j, lower=True)
+        a, b = full.indptr[j], full.indptr[j + 1]
+        assert np.array_equal(row.cols, full.indices[a:b])
+        assert np.allclose(row.vals, full.data[a:b], rtol=1e-14, atol=0)
