@@ -3,10 +3,13 @@
 //     b_jl = sum_{k in supp(j) and supp(l)} phi_kj * phi_kl      (l >= j)
 //     g_j  = sum_{k in supp(j)} phi_kj * h_k
 //
-// One wave owns one row j: it streams the points of supp(j) through LDS in the
-// sorted order of the hash, and every lane owns up to kSlots columns of the
-// upper part of the row.  Each accumulator has exactly one writer (no atomics),
-// so the summation order is fixed and the result is deterministic.  The upper
+// One block of kAsmWaves waves owns one row j.  The row's candidate points
+// (the hash cells around centre j, in sorted order) are split into kAsmWaves
+// contiguous pieces; each wave streams the supported points of its piece
+// through its own LDS slab, and every lane owns up to kSlots columns of the
+// upper part of the row.  The waves' partial sums are then added in wave
+// order.  Each accumulator has exactly one writer (no atomics), so the
+// summation order is fixed and the result is deterministic.  The upper
 // value is also written to its mirror position (l, j) of the full CSR, which
 // the solver reads, so the stored matrix is exactly symmetric.  A is never
 // materialised: phi is evaluated on the fly.
@@ -48,20 +51,35 @@ __device__ __forceinline__ float scaled_r<float>(double s, double irho) {
   return __builtin_sqrtf((float)s) * (float)irho;
 }
 
+constexpr int kAsmWaves = 4;
+
+template <typename T>
+__device__ __forceinline__ double partial_value(const Acc<T>& a);
+template <>
+__device__ __forceinline__ double partial_value<double>(const Acc<double>& a) {
+  return a.s;
+}
+template <>
+__device__ __forceinline__ double partial_value<float>(const Acc<float>& a) {
+  return (double)a.k.s - (double)a.k.c;
+}
+
 template <int DIM, int PHI, typename T>
-__global__ __launch_bounds__(kWave) void k_assemble(PlanView P, const double* __restrict__ hs,
-                                                    const int64_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ lower_cnt,
-                                                    const int32_t* __restrict__ col,
-                                                    T* __restrict__ val, double* __restrict__ g,
-                                                    double* __restrict__ diag) {
-  __shared__ double sp[DIM][kAsmChunk];
-  __shared__ int32_t sidx[kAsmChunk];
-  __shared__ T sphi[kAsmChunk];
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
+    PlanView P, const double* __restrict__ hs, const int64_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ lower_cnt, const int32_t* __restrict__ col,
+    const int64_t* __restrict__ rp4, T* __restrict__ val, double* __restrict__ g,
+    double* __restrict__ diag) {
+  __shared__ double sp[kAsmWaves][DIM][kAsmChunk];
+  __shared__ int32_t sidx[kAsmWaves][kAsmChunk];
+  __shared__ T sphi[kAsmWaves][kAsmChunk];
+  __shared__ double red[kAsmWaves][kWave * kSlots];
+  __shared__ double gred[kAsmWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
   if (!P.active[j]) {
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       g[j] = 0.0;
       diag[j] = 0.0;
     }
@@ -95,22 +113,25 @@ __global__ __launch_bounds__(kWave) void k_assemble(PlanView P, const double* __
       irl[t] = ok[t] ? P.irho[lcol[t]] : 0.0;
     }
     const bool first = cb == 0;
-    stream_support<DIM, kAsmChunk>(P, xj, r2j, sp, sidx, [&](int np) {
+    T* wphi = sphi[w];
+    const int32_t* widx = sidx[w];
+    double(*wsp)[kAsmChunk] = sp[w];
+    stream_support_part<DIM, kAsmChunk>(P, xj, r2j, w, kAsmWaves, wsp, sidx[w], [&](int np) {
       // phi_kj of the chunk's points, and their share of g_j
       for (int q = lane; q < np; q += kWave) {
         double p[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = sp[d][q];
+        for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
         const T phij = wendland<PHI, T>(scaled_r<T>(sqdist<DIM>(p, xj), irj));
-        sphi[q] = phij;
-        if (first) gacc.add(phij * (T)hs[sidx[q]]);
+        wphi[q] = phij;
+        if (first) gacc.add(phij * (T)hs[widx[q]]);
       }
-      __syncthreads();
+      wave_sync();
       for (int q = 0; q < np; ++q) {
         double p[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = sp[d][q];
-        const T phij = sphi[q];
+        for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+        const T phij = wphi[q];
 #pragma unroll
         for (int t = 0; t < kSlots; ++t) {
           if (t < nslot && ok[t]) {
@@ -120,34 +141,44 @@ __global__ __launch_bounds__(kWave) void k_assemble(PlanView P, const double* __
         }
       }
     });
+    // add the waves' partial sums in wave order
 #pragma unroll
-    for (int t = 0; t < kSlots; ++t) {
-      if (!ok[t]) continue;
-      const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
-      const T v = acc[t].value();
-      val[e] = v;
-      const int32_t l = lcol[t];
-      if (l == (int32_t)j) {
-        diag[j] = (double)v;
-      } else {
-        // mirror (l, j): j sits in the lower part of row l, columns ascending
-        int64_t lo = row_ptr[l], hi = row_ptr[l] + lower_cnt[l];
-        while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
+    for (int t = 0; t < kSlots; ++t) red[w][lane + kWave * t] = partial_value<T>(acc[t]);
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int t = 0; t < kSlots; ++t) {
+        if (!ok[t]) continue;
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < kAsmWaves; ++u) sum += red[u][lane + kWave * t];
+        const T v = (T)sum;
+        const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
+        val[rp4[j] + (e - row_ptr[j])] = v;
+        const int32_t l = lcol[t];
+        if (l == (int32_t)j) {
+          diag[j] = (double)v;
+        } else {
+          // mirror (l, j): j sits in the lower part of row l, columns ascending
+          int64_t lo = row_ptr[l], hi = row_ptr[l] + lower_cnt[l];
+          while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
+          }
+          val[rp4[l] + (lo - row_ptr[l])] = v;
         }
-        val[lo] = v;
       }
     }
+    __syncthreads();
   }
-  double gl;
-  if constexpr (sizeof(T) == 8) {
-    gl = gacc.value();
-  } else {
-    gl = (double)gacc.k.s - (double)gacc.k.c;
+  const double gl = wave_sum(partial_value<T>(gacc));
+  if (lane == 0) gred[w] = gl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gs = 0.0;
+    for (int u = 0; u < kAsmWaves; ++u) gs += gred[u];
+    g[j] = gs;
   }
-  gl = wave_sum(gl);
-  if (lane == 0) g[j] = gl;
 }
 
 constexpr int kRed = 256;
@@ -190,7 +221,7 @@ __global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__
 // from the value actually stored.
 template <typename T>
 __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
-                            const int64_t* __restrict__ row_ptr,
+                            const int64_t* __restrict__ rp4,
                             const int32_t* __restrict__ lower_cnt, const double* __restrict__ lam,
                             T* __restrict__ val, T* __restrict__ dinv,
                             double* __restrict__ dinv64) {
@@ -201,7 +232,7 @@ __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
     dinv64[j] = 0.0;
     return;
   }
-  const int64_t e = row_ptr[j] + lower_cnt[j];
+  const int64_t e = rp4[j] + lower_cnt[j];
   const T v = (T)((double)val[e] + lam[0]);
   val[e] = v;
   dinv[j] = (T)1 / v;
@@ -210,25 +241,25 @@ __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
 
 template <int DIM, typename T>
 hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int64_t* row_ptr,
-                        const int32_t* lower_cnt, const int32_t* col, T* val, double* g,
-                        double* diag, hipStream_t s) {
-  const dim3 grid((unsigned)P.m), block(kWave);
+                        const int32_t* lower_cnt, const int32_t* col, const int64_t* rp4, T* val,
+                        double* g, double* diag, hipStream_t s) {
+  const dim3 grid((unsigned)P.m), block(kWave * kAsmWaves);
   switch (phi) {
     case 0:
       hipLaunchKernelGGL((k_assemble<DIM, 0, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, val, g, diag);
+                         col, rp4, val, g, diag);
       break;
     case 1:
       hipLaunchKernelGGL((k_assemble<DIM, 1, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, val, g, diag);
+                         col, rp4, val, g, diag);
       break;
     case 2:
       hipLaunchKernelGGL((k_assemble<DIM, 2, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, val, g, diag);
+                         col, rp4, val, g, diag);
       break;
     default:
       hipLaunchKernelGGL((k_assemble<DIM, 3, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, val, g, diag);
+                         col, rp4, val, g, diag);
       break;
   }
   return hipGetLastError();
@@ -238,17 +269,22 @@ hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int6
 
 hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
-                           void* val, double* g, double* diag, hipStream_t s) {
+                           const int64_t* rp4, void* val, double* g, double* diag,
+                           hipStream_t s) {
   if (P.m <= 0) return hipSuccess;
   if (P.dim == 2) {
-    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, (float*)val, g, diag, s)
-                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, (double*)val, g, diag, s);
+    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (float*)val,
+                                         g, diag, s)
+                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, rp4,
+                                          (double*)val, g, diag, s);
   }
-  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, (float*)val, g, diag, s)
-              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, (double*)val, g, diag, s);
+  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (float*)val, g,
+                                       diag, s)
+              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (double*)val,
+                                        g, diag, s);
 }
 
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* row_ptr,
+hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* rp4,
                            const int32_t* lower_cnt, const double* diag, double lambda_rel,
                            double* lam, bool fp32, void* val, void* dinv, double* dinv64,
                            hipStream_t s) {
@@ -257,10 +293,10 @@ hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* row_
   const int bs = 256;
   const dim3 grid((unsigned)((m + bs - 1) / bs));
   if (fp32)
-    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, row_ptr, lower_cnt,
+    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, rp4, lower_cnt,
                        (const double*)lam, (float*)val, (float*)dinv, dinv64);
   else
-    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, row_ptr, lower_cnt,
+    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, rp4, lower_cnt,
                        (const double*)lam, (double*)val, (double*)dinv, dinv64);
   return hipGetLastError();
 }

@@ -57,17 +57,70 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
   return block_sum(s, ws);
 }
 
-template <typename VT, typename XT, int G>
+// Rows handled together by one lane group in one pass.
+template <typename VT>
+constexpr int rows_in_flight() {
+  return 2;
+}
+
+// For the kRowsInFlight rows row0 + i * step (i < kRowsInFlight), the group
+// sums az_i = sum_e b_e z[col_e] and ap_i = sum_e b_e p[col_e]; lane `sub`
+// of the group reads entries sub, sub + G, ... of the row (consecutive lanes,
+// consecutive entries: coalesced value loads, neighbouring gather addresses).
+// Column indices are stored as deltas to the row.
+template <typename VT, typename XT, typename CT, int G, int kRowsInFlight>
+__device__ __forceinline__ void rows_products(int64_t m, int64_t row0, int64_t step,
+                                              const int64_t* __restrict__ rp,
+                                              const CT* __restrict__ col,
+                                              const VT* __restrict__ val, const XT* __restrict__ z,
+                                              const XT* __restrict__ p, XT* az, XT* ap) {
+  const int sub = threadIdx.x & (G - 1);
+#pragma unroll
+  for (int i = 0; i < kRowsInFlight; ++i) {
+    const int64_t row = row0 + i * step;
+    XT a = (XT)0, b = (XT)0;
+    if (row < m) {
+      const int32_t r32 = (int32_t)row;
+      const int64_t e1 = rp[row + 1];
+      for (int64_t e = rp[row] + sub; e < e1; e += G) {
+        const int32_t l = r32 + (int32_t)col[e];
+        const XT v = (XT)val[e];
+        a += v * z[l];
+        b += v * p[l];
+      }
+    }
+    az[i] = group_sum<XT, G>(a);
+    ap[i] = group_sum<XT, G>(b);
+  }
+}
+
+// q = (B + lambda I) p_new with p_new = z + beta p_old, factored as
+// q = B z + beta B p_old so that the matrix is streamed before beta is known.
+template <typename VT, typename XT, typename CT, int G>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(
-    int64_t m, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    int64_t m, const int64_t* __restrict__ rp4, const CT* __restrict__ col,
     const VT* __restrict__ val, const XT* __restrict__ z, const XT* __restrict__ pold,
     XT* __restrict__ pnew, XT* __restrict__ q, CgScalars* __restrict__ sc,
     const double* __restrict__ part_in, int n_in, double* __restrict__ part_out, int parity,
     int fixed_beta) {
+  constexpr int kRowsInFlight = rows_in_flight<VT>();
   __shared__ double ws[kBlock / kWave];
   if (sc->done) return;
-  const double rz = reduce_partials(part_in, n_in, 2, 0, ws);
-  const double rr = reduce_partials(part_in, n_in, 2, 1, ws);
+  // partials of the previous update: loaded first, reduced after the first
+  // rows' matrix loads are in flight
+  double prz = 0.0, prr = 0.0;
+  for (int k = threadIdx.x; k < n_in; k += kBlock) {
+    prz += part_in[2 * k];
+    prr += part_in[2 * k + 1];
+  }
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t step = (int64_t)(kBlock / G);
+  const int64_t pass = (int64_t)gridDim.x * step * kRowsInFlight;
+  int64_t row0 = (int64_t)blockIdx.x * step * kRowsInFlight + threadIdx.x / G;
+  XT az[kRowsInFlight], ap[kRowsInFlight];
+  rows_products<VT, XT, CT, G, kRowsInFlight>(m, row0, step, rp4, col, val, z, pold, az, ap);
+  const double rz = block_sum(prz, ws);
+  const double rr = block_sum(prr, ws);
   if (!__builtin_isfinite(rz) || !__builtin_isfinite(rr)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
     return;
@@ -82,22 +135,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(
   const double beta_d = fixed_beta ? sc->beta_fixed : rz / sc->rzh[parity ^ 1];
   const XT beta = (XT)beta_d;
   double contrib = 0.0;
-  const int sub = threadIdx.x & (G - 1);
-  for (int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; row < m;
-       row += (int64_t)gridDim.x * (kBlock / G)) {
-    XT acc = (XT)0;
-    const int64_t e1 = row_ptr[row + 1];
-    for (int64_t e = row_ptr[row] + sub; e < e1; e += G) {
-      const int32_t l = col[e];
-      acc += (XT)val[e] * (z[l] + beta * pold[l]);
-    }
-    acc = group_sum<XT, G>(acc);
+  for (;;) {
     if (sub == 0) {
-      const XT pj = z[row] + beta * pold[row];
-      pnew[row] = pj;
-      q[row] = acc;
-      contrib += (double)pj * (double)acc;
+#pragma unroll
+      for (int i = 0; i < kRowsInFlight; ++i) {
+        const int64_t row = row0 + i * step;
+        if (row < m) {
+          const XT pj = z[row] + beta * pold[row];
+          const XT qj = az[i] + beta * ap[i];
+          pnew[row] = pj;
+          q[row] = qj;
+          contrib += (double)pj * (double)qj;
+        }
+      }
     }
+    row0 += pass;
+    if (row0 - threadIdx.x / G >= m) break;
+    rows_products<VT, XT, CT, G, kRowsInFlight>(m, row0, step, rp4, col, val, z, pold, az, ap);
   }
   const double bs = block_sum(contrib, ws);
   if (threadIdx.x == 0) {
@@ -118,7 +172,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
     double* __restrict__ part_out, int parity) {
   __shared__ double ws[kBlock / kWave];
   if (sc->done) return;
-  const double pq = reduce_partials(part_in, n_in, 1, 0, ws);
+  double ppq = 0.0;
+  for (int k = threadIdx.x; k < n_in; k += kBlock) ppq += part_in[k];
+  // the first element's operands are loaded before alpha is known
+  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  XT pj = (XT)0, qj = (XT)0, xj = (XT)0, rj = (XT)0, dj = (XT)0;
+  if (j < m) {
+    pj = p[j];
+    qj = q[j];
+    xj = x[j];
+    rj = r[j];
+    dj = dinv[j];
+  }
+  const double pq = block_sum(ppq, ws);
   if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
     return;
@@ -126,16 +193,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
   const double alpha_d = sc->rzh[parity] / pq;
   const XT alpha = (XT)alpha_d;
   double rz = 0.0, rr = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m;
-       j += (int64_t)gridDim.x * kBlock) {
-    const XT xj = x[j] + alpha * p[j];
-    const XT rj = r[j] - alpha * q[j];
-    const XT zj = dinv[j] * rj;
+  while (j < m) {
+    xj += alpha * pj;
+    rj -= alpha * qj;
+    const XT zj = dj * rj;
     x[j] = xj;
     r[j] = rj;
     z[j] = zj;
     rz += (double)rj * (double)zj;
     rr += (double)rj * (double)rj;
+    j += stride;
+    if (j < m) {
+      pj = p[j];
+      qj = q[j];
+      xj = x[j];
+      rj = r[j];
+      dj = dinv[j];
+    }
   }
   const double brz = block_sum(rz, ws);
   const double brr = block_sum(rr, ws);
@@ -160,10 +234,10 @@ __global__ void k_fold_solution(int64_t m, double* __restrict__ xhi, XT* __restr
 }
 
 // Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, then
-// r = (XT) r64 and z = D^-1 r, row by row (G lanes per row).
-template <typename VT, typename XT, int G>
+// r = (XT) r64 and z = D^-1 r, row by row (G lanes per row, CSR4 layout).
+template <typename VT, typename XT, typename CT, int G>
 __global__ __launch_bounds__(kBlock) void k_true_residual(
-    int64_t m, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    int64_t m, const int64_t* __restrict__ rp4, const CT* __restrict__ col,
     const VT* __restrict__ val, const double* __restrict__ xhi, const double* __restrict__ g,
     const XT* __restrict__ dinv, double* __restrict__ r64, XT* __restrict__ r,
     XT* __restrict__ z) {
@@ -171,8 +245,9 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(
   for (int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; row < m;
        row += (int64_t)gridDim.x * (kBlock / G)) {
     double acc = 0.0;
-    const int64_t e1 = row_ptr[row + 1];
-    for (int64_t e = row_ptr[row] + sub; e < e1; e += G) acc += (double)val[e] * xhi[col[e]];
+    const int64_t e1 = rp4[row + 1];
+    for (int64_t e = rp4[row] + sub; e < e1; e += G)
+      acc += (double)val[e] * xhi[(int32_t)row + (int32_t)col[e]];
     acc = group_sum<double, G>(acc);
     if (sub == 0) {
       const double rv = g[row] - acc;
@@ -263,20 +338,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t m, const double* __r
   }
 }
 
-template <typename VT, typename XT, int G>
-void launch_spmv_g(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
+template <typename VT, typename XT, typename CT, int G>
+void launch_spmv_g(const CgArgs<XT>& a, const int64_t* rp4, const CT* col, const VT* val,
                    int parity, int fixed_beta, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_spmv<VT, XT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
-                     row_ptr, col, val, (const XT*)a.z, (const XT*)a.p[parity],
+  hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
+                     rp4, col, val, (const XT*)a.z, (const XT*)a.p[parity],
                      a.p[parity ^ 1], a.q, a.sc, (const double*)a.part_upd, a.update_blocks,
                      a.part_spmv, parity, fixed_beta);
 }
 
-template <typename VT, typename XT, int G>
-void launch_true_residual_g(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
+template <typename VT, typename XT, typename CT, int G>
+void launch_true_residual_g(const CgArgs<XT>& a, const int64_t* rp4, const CT* col,
                             const VT* val, const double* g, hipStream_t s) {
-  hipLaunchKernelGGL((k_true_residual<VT, XT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
-                     row_ptr, col, val, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r,
+  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s,
+                     a.m, rp4, col, val, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r,
                      a.z);
 }
 
@@ -288,14 +363,16 @@ bool grids_ok(int spmv_blocks, int update_blocks) {
 }  // namespace
 
 int cg_group_size(double mean_row) {
-  if (mean_row > 192) return 64;
-  if (mean_row > 96) return 32;
-  if (mean_row > 24) return 16;
+  // four stored entries per lane per step: one step covers 4 G entries
+  if (mean_row > 128) return 64;
+  if (mean_row > 64) return 32;
+  if (mean_row > 32) return 16;
   return 8;
 }
 
-int cg_grid_blocks(int64_t m, int group) {
-  const int64_t rows_per_block = kBlock / group;
+int cg_grid_blocks(int64_t m, int group, bool fp64) {
+  const int64_t rows_per_block =
+      (int64_t)(kBlock / group) * (fp64 ? rows_in_flight<double>() : rows_in_flight<float>());
   const int64_t b = (m + rows_per_block - 1) / rows_per_block;
   return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
 }
@@ -305,16 +382,43 @@ int cg_update_blocks(int64_t m) {
   return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
 }
 
-template <typename VT, typename XT>
-hipError_t cg_spmv(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
-                   int group, int parity, int fixed_beta, hipStream_t s) {
-  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
-  switch (group) {
-    case 8: launch_spmv_g<VT, XT, 8>(a, row_ptr, col, val, parity, fixed_beta, s); break;
-    case 16: launch_spmv_g<VT, XT, 16>(a, row_ptr, col, val, parity, fixed_beta, s); break;
-    case 32: launch_spmv_g<VT, XT, 32>(a, row_ptr, col, val, parity, fixed_beta, s); break;
-    default: launch_spmv_g<VT, XT, 64>(a, row_ptr, col, val, parity, fixed_beta, s); break;
+namespace {
+
+template <typename VT, typename XT, typename CT>
+void spmv_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
+                   hipStream_t s) {
+  const CT* col = static_cast<const CT*>(A.col);
+  const VT* val = static_cast<const VT*>(A.val);
+  switch (A.group) {
+    case 8: launch_spmv_g<VT, XT, CT, 8>(a, A.rp4, col, val, parity, fixed_beta, s); break;
+    case 16: launch_spmv_g<VT, XT, CT, 16>(a, A.rp4, col, val, parity, fixed_beta, s); break;
+    case 32: launch_spmv_g<VT, XT, CT, 32>(a, A.rp4, col, val, parity, fixed_beta, s); break;
+    default: launch_spmv_g<VT, XT, CT, 64>(a, A.rp4, col, val, parity, fixed_beta, s); break;
   }
+}
+
+template <typename VT, typename XT, typename CT>
+void residual_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, hipStream_t s) {
+  const CT* col = static_cast<const CT*>(A.col);
+  const VT* val = static_cast<const VT*>(A.val);
+  switch (A.group) {
+    case 8: launch_true_residual_g<VT, XT, CT, 8>(a, A.rp4, col, val, g, s); break;
+    case 16: launch_true_residual_g<VT, XT, CT, 16>(a, A.rp4, col, val, g, s); break;
+    case 32: launch_true_residual_g<VT, XT, CT, 32>(a, A.rp4, col, val, g, s); break;
+    default: launch_true_residual_g<VT, XT, CT, 64>(a, A.rp4, col, val, g, s); break;
+  }
+}
+
+}  // namespace
+
+template <typename VT, typename XT>
+hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
+                   hipStream_t s) {
+  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+  if (A.col16)
+    spmv_dispatch<VT, XT, int16_t>(a, A, parity, fixed_beta, s);
+  else
+    spmv_dispatch<VT, XT, int32_t>(a, A, parity, fixed_beta, s);
   return hipGetLastError();
 }
 
@@ -330,19 +434,16 @@ hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s) {
 }
 
 template <typename VT, typename XT>
-hipError_t cg_true_residual(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
-                            const VT* val, const double* g, int group, int restart, int parity,
-                            hipStream_t s) {
+hipError_t cg_true_residual(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int restart,
+                            int parity, hipStream_t s) {
   if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
   const int bs = 256;
   const dim3 eg((unsigned)((a.m + bs - 1) / bs));
   hipLaunchKernelGGL(k_fold_solution<XT>, eg, dim3(bs), 0, s, a.m, a.xhi, a.xlo);
-  switch (group) {
-    case 8: launch_true_residual_g<VT, XT, 8>(a, row_ptr, col, val, g, s); break;
-    case 16: launch_true_residual_g<VT, XT, 16>(a, row_ptr, col, val, g, s); break;
-    case 32: launch_true_residual_g<VT, XT, 32>(a, row_ptr, col, val, g, s); break;
-    default: launch_true_residual_g<VT, XT, 64>(a, row_ptr, col, val, g, s); break;
-  }
+  if (A.col16)
+    residual_dispatch<VT, XT, int16_t>(a, A, g, s);
+  else
+    residual_dispatch<VT, XT, int32_t>(a, A, g, s);
   hipLaunchKernelGGL(k_residual_dots<XT>, dim3(a.update_blocks), dim3(kBlock), 0, s, a.m,
                      (const double*)a.r64, (const XT*)a.r, (const XT*)a.z, a.part_upd);
   hipLaunchKernelGGL(k_residual_scalars, dim3(1), dim3(kBlock), 0, s, a.sc,
@@ -361,19 +462,16 @@ hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g,
   return hipGetLastError();
 }
 
-template hipError_t cg_spmv<double, double>(const CgArgs<double>&, const int64_t*,
-                                            const int32_t*, const double*, int, int, int,
+template hipError_t cg_spmv<double, double>(const CgArgs<double>&, const CgMatrix&, int, int,
                                             hipStream_t);
-template hipError_t cg_spmv<float, float>(const CgArgs<float>&, const int64_t*, const int32_t*,
-                                          const float*, int, int, int, hipStream_t);
+template hipError_t cg_spmv<float, float>(const CgArgs<float>&, const CgMatrix&, int, int,
+                                          hipStream_t);
 template hipError_t cg_update<double>(const CgArgs<double>&, int, hipStream_t);
 template hipError_t cg_update<float>(const CgArgs<float>&, int, hipStream_t);
-template hipError_t cg_true_residual<double, double>(const CgArgs<double>&, const int64_t*,
-                                                     const int32_t*, const double*, const double*,
-                                                     int, int, int, hipStream_t);
-template hipError_t cg_true_residual<float, float>(const CgArgs<float>&, const int64_t*,
-                                                   const int32_t*, const float*, const double*,
-                                                   int, int, int, hipStream_t);
+template hipError_t cg_true_residual<double, double>(const CgArgs<double>&, const CgMatrix&,
+                                                     const double*, int, int, hipStream_t);
+template hipError_t cg_true_residual<float, float>(const CgArgs<float>&, const CgMatrix&,
+                                                   const double*, int, int, hipStream_t);
 template hipError_t cg_setup<double>(const CgArgs<double>&, const uint8_t*, const double*, double,
                                      double, hipStream_t);
 template hipError_t cg_setup<float>(const CgArgs<float>&, const uint8_t*, const double*, double,

@@ -26,35 +26,60 @@ struct PlanView {
   const uint8_t* active;  // centre has >= min_support points
 };
 
-// Streams the support of centre j through LDS in chunks of kChunk points,
-// keeping the sorted point order (coordinates in sp, sorted positions in sidx
-// when it is not null), and hands each chunk to `consume(np)`.  One wave per
-// block; every branch around the barriers is wave-uniform.
+// Orders LDS traffic among the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Streams part `part` of `nparts` of the support of centre j through this
+// wave's LDS slab in chunks of kChunk points.  The candidate points (the cells
+// around the centre's cell, in sorted order) are split into nparts contiguous
+// pieces; the points of this piece that lie in the support are compacted in
+// sorted order (coordinates in sp, sorted positions in sidx unless it is
+// null) and handed to
+// `consume(np)`.  Only wave-level synchronisation is used, so the waves of a
+// block may take different numbers of chunks.
 template <int DIM, int kChunk, typename Consume>
-__device__ __forceinline__ void stream_support(const PlanView& P, const double* xj, double r2,
-                                               double (*sp)[kChunk], int32_t* sidx,
-                                               Consume&& consume) {
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void stream_support_part(const PlanView& P, const double* xj, double r2,
+                                                    int part, int nparts,
+                                                    double (*sp)[kChunk], int32_t* sidx,
+                                                    Consume&& consume) {
+  const int lane = threadIdx.x & (kWave - 1);
   const uint64_t lt = lanemask_lt();
   int c[3];
   if (!cell_of<DIM>(P.grid, xj, c)) return;
   NbrWalk<DIM> walk(P.grid, c, 1);
+  int64_t total = 0;
+  for (int k = 0; k < walk.rows(); ++k) {
+    int lo_id, hi_id;
+    if (walk.range(k, lo_id, hi_id)) total += P.pcs[hi_id + 1] - P.pcs[lo_id];
+  }
+  const int64_t my0 = total * part / nparts, my1 = total * (part + 1) / nparts;
+  int64_t off = 0;
   int np = 0;
   for (int k = 0; k < walk.rows(); ++k) {
     int lo_id, hi_id;
     if (!walk.range(k, lo_id, hi_id)) continue;
     const int lo = P.pcs[lo_id], hi = P.pcs[hi_id + 1];
-    for (int i0 = lo; i0 < hi; i0 += kWave) {
+    // this row's slice of the wave's piece [my0, my1) of the virtual range
+    const int64_t a = my0 > off ? my0 - off : 0;
+    const int64_t b = (my1 - off) < (int64_t)(hi - lo) ? (my1 - off) : (int64_t)(hi - lo);
+    off += hi - lo;
+    if (b <= a) continue;
+    const int s0 = lo + (int)a, s1 = lo + (int)b;
+    for (int i0 = s0; i0 < s1; i0 += kWave) {
       if (np > kChunk - kWave) {
-        __syncthreads();
+        wave_sync();
         consume(np);
-        __syncthreads();
+        wave_sync();
         np = 0;
       }
       const int i = i0 + lane;
       double p[DIM];
       bool in = false;
-      if (i < hi) {
+      if (i < s1) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) p[d] = P.ps[d * P.n + i];
         in = sqdist<DIM>(p, xj) < r2;
@@ -70,12 +95,11 @@ __device__ __forceinline__ void stream_support(const PlanView& P, const double* 
     }
   }
   if (np > 0) {
-    __syncthreads();
+    wave_sync();
     consume(np);
-    __syncthreads();
+    wave_sync();
   }
 }
-
 
 hipError_t launch_minmax(const double* a, int64_t n, double* partial_min, double* partial_max,
                          int* partial_bad, int nblocks, double* out3, hipStream_t s);
@@ -87,17 +111,26 @@ hipError_t launch_radius_tables(const double* rho_in, double rho, int64_t m, dou
                                 double* rho2_c, double* irho_c, hipStream_t s);
 hipError_t launch_support_count(const PlanView& P, int32_t min_support, int32_t* count,
                                 uint8_t* active, hipStream_t s);
+// Count pass (fill = false) then fill pass; `marks` (symbolic_marks_words(m)
+// words) carries the candidate marks from the first to the second.
+size_t symbolic_marks_words(int64_t m);
 hipError_t launch_symbolic(const PlanView& P, bool fill, int64_t* full_cnt, int32_t* lower_cnt,
-                           const int64_t* row_ptr, int32_t* col, int32_t* err, hipStream_t s);
+                           const int64_t* row_ptr, int32_t* col, int32_t* err, int32_t* maxdelta,
+                           uint32_t* marks, hipStream_t s);
+hipError_t launch_pad_lengths(const int64_t* row_ptr, int64_t m, int64_t* len4, hipStream_t s);
+hipError_t launch_pad_cols(const int64_t* row_ptr, const int32_t* col, const int64_t* rp4,
+                           int64_t m, bool col16, void* col4, hipStream_t s);
 
 }  // namespace rbf
 
 namespace rbf {
 // assemble_kernels.hip
+// Values go to the CSR4 layout: entry e of row j (unpadded CSR) sits at
+// rp4[j] + (e - row_ptr[j]).
 hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
-                           void* val, double* g, double* diag, hipStream_t s);
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* row_ptr,
+                           const int64_t* rp4, void* val, double* g, double* diag, hipStream_t s);
+hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* rp4,
                            const int32_t* lower_cnt, const double* diag, double lambda_rel,
                            double* lam, bool fp32, void* val, void* dinv, double* dinv64,
                            hipStream_t s);

@@ -143,25 +143,37 @@ __global__ __launch_bounds__(256) void k_support_count(PlanView P, int32_t min_s
   }
 }
 
+constexpr int kSymWaves = 4;
 constexpr int kSymChunk = 256;
+constexpr int kCandWords = kMaxCand / 32;
 
-// Pattern of row j.  Count mode writes the full-row and lower-part sizes; fill
-// mode writes the sorted columns of the full row.
+// Pattern of row j (one block of kSymWaves waves per row).
+//
+// Candidates: active centres whose ball can meet centre j's ball, gathered
+// from the centre hash in a fixed order.  Count mode: the row's candidate
+// points are split among the waves (as in the assembly); each wave streams
+// the supported points of its piece and marks every candidate with one of
+// them in its support (LDS bit set, order-independent).  A wave stops once
+// every candidate is marked.  The marks are saved as a bitmask per row, and
+// the full-row and lower-part sizes and the largest |l - j| are written.
+// Fill mode rebuilds the same candidate list, reads the saved marks and
+// writes the marked columns in ascending order.
 template <int DIM, bool FILL>
-__global__ __launch_bounds__(kWave) void k_symbolic(PlanView P, int64_t* __restrict__ full_cnt,
-                                                    int32_t* __restrict__ lower_cnt,
-                                                    const int64_t* __restrict__ row_ptr,
-                                                    int32_t* __restrict__ col,
-                                                    int32_t* __restrict__ err) {
+__global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
+    PlanView P, int64_t* __restrict__ full_cnt, int32_t* __restrict__ lower_cnt,
+    const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col, int32_t* __restrict__ err,
+    int32_t* __restrict__ maxdelta, uint32_t* __restrict__ marks) {
   __shared__ int32_t cand[kMaxCand];
   __shared__ int32_t surv[kMaxCand];
-  __shared__ uint8_t flag[kMaxCand];
-  __shared__ double sp[DIM][kSymChunk];
-  const int lane = threadIdx.x;
+  __shared__ uint32_t word[kCandWords];
+  __shared__ double sp[kSymWaves][DIM][kSymChunk];
+  __shared__ int nc_s;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
   const uint64_t lt = lanemask_lt();
   if (!P.active[j]) {
-    if (!FILL && lane == 0) {
+    if (!FILL && threadIdx.x == 0) {
       full_cnt[j] = 0;
       lower_cnt[j] = 0;
     }
@@ -174,9 +186,8 @@ __global__ __launch_bounds__(kWave) void k_symbolic(PlanView P, int64_t* __restr
   int c[3];
   cell_of<DIM>(P.grid, xj, c);  // centres always lie inside the box
 
-  // candidate columns: active centres whose ball can meet centre j's ball
-  int nc = 0;
-  {
+  if (w == 0) {
+    int nc = 0;
     NbrWalk<DIM> walk(P.grid, c, 2);
     for (int k = 0; k < walk.rows(); ++k) {
       int lo_id, hi_id;
@@ -202,56 +213,79 @@ __global__ __launch_bounds__(kWave) void k_symbolic(PlanView P, int64_t* __restr
         nc += __popcll(m);
       }
     }
+    if (lane == 0) nc_s = nc;
   }
+  if (threadIdx.x < kCandWords) word[threadIdx.x] = FILL ? marks[j * kCandWords + threadIdx.x] : 0u;
+  __syncthreads();
+  const int nc = nc_s;
   if (nc > kMaxCand) {
-    if (lane == 0) atomicExch(err, 1);
-    if (!FILL && lane == 0) {
-      full_cnt[j] = 0;
-      lower_cnt[j] = 0;
+    if (threadIdx.x == 0) {
+      atomicExch(err, 1);
+      if (!FILL) {
+        full_cnt[j] = 0;
+        lower_cnt[j] = 0;
+      }
     }
     return;
   }
-  for (int t = lane; t < nc; t += kWave) flag[t] = 0;
-  __syncthreads();
 
-  // a candidate survives when one supported point of j lies in its support
-  stream_support<DIM, kSymChunk>(P, xj, P.rho2[j], sp, nullptr, [&](int np) {
-    for (int t = lane; t < nc; t += kWave) {
-      if (flag[t]) continue;
-      const int l = cand[t];
-      double xl[DIM];
+  if (!FILL) {
+    stream_support_part<DIM, kSymChunk>(P, xj, P.rho2[j], w, kSymWaves, sp[w], nullptr,
+                                        [&](int np) {
+      int open = 0;
+      for (int t = lane; t < nc; t += kWave) {
+        if ((word[t >> 5] >> (t & 31)) & 1u) continue;
+        const int l = cand[t];
+        double xl[DIM];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
-      const double r2l = P.rho2[l];
-      for (int q = 0; q < np; ++q) {
-        double p[DIM];
+        for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
+        const double r2l = P.rho2[l];
+        bool hit = false;
+        for (int q = 0; q < np; ++q) {
+          double p[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = sp[d][q];
-        if (sqdist<DIM>(p, xl) < r2l) {
-          flag[t] = 1;
-          break;
+          for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q];
+          if (sqdist<DIM>(p, xl) < r2l) {
+            hit = true;
+            break;
+          }
         }
+        if (hit) atomicOr(&word[t >> 5], 1u << (t & 31)); else ++open;
       }
-    }
-  });
-  __syncthreads();
+      return wave_sum_int(open) == 0;
+    });
+    __syncthreads();
+    if (threadIdx.x < kCandWords) marks[j * kCandWords + threadIdx.x] = word[threadIdx.x];
+  }
+  if (w != 0) return;
 
-  // compact the survivors, keeping candidate order
-  int ns = 0, nlow = 0;
+  // compact the marked candidates, keeping candidate order
+  int ns = 0, nlow = 0, dmax = 0;
   for (int t0 = 0; t0 < nc; t0 += kWave) {
     const int t = t0 + lane;
-    const bool s = t < nc && flag[t];
-    const uint64_t m = __ballot(s);
-    const uint64_t ml = __ballot(s && cand[t] < j);
-    if (s) surv[ns + __popcll(m & lt)] = cand[t];
+    const bool hit = t < nc && ((word[t >> 5] >> (t & 31)) & 1u);
+    const int l = hit ? cand[t] : 0;
+    const uint64_t m = __ballot(hit);
+    const uint64_t ml = __ballot(hit && l < j);
+    if (hit) {
+      surv[ns + __popcll(m & lt)] = l;
+      const int d = l > j ? l - (int)j : (int)j - l;
+      dmax = d > dmax ? d : dmax;
+    }
     ns += __popcll(m);
     nlow += __popcll(ml);
   }
-  __syncthreads();
+  wave_sync();
   if (!FILL) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int o = __shfl_xor(dmax, off, kWave);
+      dmax = o > dmax ? o : dmax;
+    }
     if (lane == 0) {
       full_cnt[j] = ns;
       lower_cnt[j] = nlow;
+      if (dmax > 0) atomicMax(maxdelta, dmax);
     }
     return;
   }
@@ -265,7 +299,48 @@ __global__ __launch_bounds__(kWave) void k_symbolic(PlanView P, int64_t* __restr
   }
 }
 
+// Padded row lengths: every row of the CSR4 layout is a multiple of 4 entries.
+__global__ void k_pad_lengths(const int64_t* __restrict__ row_ptr, int64_t m,
+                              int64_t* __restrict__ len4) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  len4[j] = j == m ? 0 : ((row_ptr[j + 1] - row_ptr[j] + 3) & ~int64_t(3));
+}
+
+// Column deltas l - j in the CSR4 layout, one wave per row; padding gets 0.
+template <typename CT>
+__global__ __launch_bounds__(256) void k_pad_cols(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const int64_t* __restrict__ rp4, int64_t m,
+                                                  CT* __restrict__ col4) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (j >= m) return;
+  const int64_t a = row_ptr[j], n = row_ptr[j + 1] - a, b = rp4[j], n4 = rp4[j + 1] - b;
+  for (int64_t t = lane; t < n4; t += kWave) col4[b + t] = t < n ? (CT)(col[a + t] - (int32_t)j) : (CT)0;
+}
+
 }  // namespace
+
+hipError_t launch_pad_lengths(const int64_t* row_ptr, int64_t m, int64_t* len4, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_pad_lengths, dim3((unsigned)((m + 1 + bs - 1) / bs)), dim3(bs), 0, s,
+                     row_ptr, m, len4);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_cols(const int64_t* row_ptr, const int32_t* col, const int64_t* rp4,
+                           int64_t m, bool col16, void* col4, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + 3) / 4));
+  if (col16)
+    hipLaunchKernelGGL(k_pad_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, rp4, m,
+                       (int16_t*)col4);
+  else
+    hipLaunchKernelGGL(k_pad_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, rp4, m,
+                       (int32_t*)col4);
+  return hipGetLastError();
+}
 
 hipError_t launch_minmax(const double* a, int64_t n, double* partial_min, double* partial_max,
                          int* partial_bad, int nblocks, double* out3, hipStream_t s) {
@@ -318,23 +393,27 @@ hipError_t launch_support_count(const PlanView& P, int32_t min_support, int32_t*
   return hipGetLastError();
 }
 
+size_t symbolic_marks_words(int64_t m) { return (size_t)m * kCandWords; }
+
 hipError_t launch_symbolic(const PlanView& P, bool fill, int64_t* full_cnt, int32_t* lower_cnt,
-                           const int64_t* row_ptr, int32_t* col, int32_t* err, hipStream_t s) {
+                           const int64_t* row_ptr, int32_t* col, int32_t* err, int32_t* maxdelta,
+                           uint32_t* marks, hipStream_t s) {
   const dim3 grid((unsigned)P.m);
+  const dim3 block(kWave * kSymWaves);
   if (P.dim == 2) {
     if (fill)
-      hipLaunchKernelGGL((k_symbolic<2, true>), grid, dim3(kWave), 0, s, P, full_cnt, lower_cnt,
-                         row_ptr, col, err);
+      hipLaunchKernelGGL((k_symbolic<2, true>), grid, block, 0, s, P, full_cnt, lower_cnt,
+                         row_ptr, col, err, maxdelta, marks);
     else
-      hipLaunchKernelGGL((k_symbolic<2, false>), grid, dim3(kWave), 0, s, P, full_cnt, lower_cnt,
-                         row_ptr, col, err);
+      hipLaunchKernelGGL((k_symbolic<2, false>), grid, block, 0, s, P, full_cnt, lower_cnt,
+                         row_ptr, col, err, maxdelta, marks);
   } else {
     if (fill)
-      hipLaunchKernelGGL((k_symbolic<3, true>), grid, dim3(kWave), 0, s, P, full_cnt, lower_cnt,
-                         row_ptr, col, err);
+      hipLaunchKernelGGL((k_symbolic<3, true>), grid, block, 0, s, P, full_cnt, lower_cnt,
+                         row_ptr, col, err, maxdelta, marks);
     else
-      hipLaunchKernelGGL((k_symbolic<3, false>), grid, dim3(kWave), 0, s, P, full_cnt, lower_cnt,
-                         row_ptr, col, err);
+      hipLaunchKernelGGL((k_symbolic<3, false>), grid, block, 0, s, P, full_cnt, lower_cnt,
+                         row_ptr, col, err, maxdelta, marks);
   }
   return hipGetLastError();
 }

@@ -6,7 +6,7 @@
 namespace rbf {
 
 // Most blocks of any CG kernel; bounds the partial-sum arrays.
-constexpr int kCgMaxBlocks = 1024;
+constexpr int kCgMaxBlocks = 2048;
 
 // Scalars of one CG solve, kept in device memory.  Each is written by block 0
 // of one kernel and read by later kernels (or the host) only.
@@ -43,23 +43,34 @@ struct CgArgs {
   int update_blocks;
 };
 
+// The stored matrix in the solver's CSR layout: row j occupies
+// [rp4[j], rp4[j+1]), padded to a multiple of 4 entries; columns are stored
+// as l - j (int16 when every |l - j| fits, else int32); padding entries have
+// delta 0 and value 0.
+struct CgMatrix {
+  const int64_t* rp4;
+  const void* col;
+  bool col16;
+  const void* val;  // VT
+  int group;        // lanes per row
+};
+
 int cg_group_size(double mean_row);
-int cg_grid_blocks(int64_t m, int group);
+int cg_grid_blocks(int64_t m, int group, bool fp64);
 int cg_update_blocks(int64_t m);
 
 // Iteration k = cg_spmv(parity = k & 1) then cg_update(parity).  fixed_beta:
 // the spmv takes beta from the last float64 residual (first iteration after
 // set-up or a reliable update).
 template <typename VT, typename XT>
-hipError_t cg_spmv(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col, const VT* val,
-                   int group, int parity, int fixed_beta, hipStream_t s);
+hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
+                   hipStream_t s);
 template <typename XT>
 hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s);
 // x_hi += x_lo; float64 residual; r, z from it; scalars for the next spmv.
 template <typename VT, typename XT>
-hipError_t cg_true_residual(const CgArgs<XT>& a, const int64_t* row_ptr, const int32_t* col,
-                            const VT* val, const double* g, int group, int restart, int parity,
-                            hipStream_t s);
+hipError_t cg_true_residual(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int restart,
+                            int parity, hipStream_t s);
 template <typename XT>
 hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
                     double delta, hipStream_t s);
