@@ -75,12 +75,14 @@ struct rbf_plan {
   int32_t* lower_cnt = nullptr;
   int32_t* col = nullptr;
   int64_t nnz_full = 0;
-  // solver layout (padded CSR4, column deltas)
-  int64_t* rp4 = nullptr;
-  void* col4 = nullptr;
+  // solver layout (sliced ELL, column deltas; see CgMatrix)
+  int64_t* sptr = nullptr;
+  int32_t* slen = nullptr;
+  int64_t nslices = 0;
+  int32_t lanes = 4;
+  void* scol = nullptr;
   bool col16 = false;
-  int64_t nnz4 = 0;
-  int32_t group = 16;
+  int64_t nsell = 0;
   // system
   double* hs = nullptr;
   double* g = nullptr;
@@ -333,13 +335,11 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   rbf::PlanView v = P->view();
   HIPCHK(rbf::launch_support_count(v, P->min_support, P->support, P->active, s));
 
-  int64_t *cnt, *len4;
+  int64_t* cnt;
   int32_t *err, *maxd;
   GET(cnt, m + 1);
-  GET(len4, m + 1);
   GET(P->lower_cnt, m);
   GET(P->row_ptr, m + 1);
-  GET(P->rp4, m + 1);
   GET(err, 2);
   maxd = err + 1;
   HIPCHK(hipMemsetAsync(err, 0, 2 * sizeof(int32_t), s));
@@ -350,36 +350,50 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
   if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
   HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
-  HIPCHK(rbf::launch_pad_lengths(P->row_ptr, m, len4, s));
-  HIPCHK(rbf::exclusive_scan(len4, P->rp4, m + 1, stmp, s));
-  int64_t sizes[2] = {0, 0};
+  int64_t nnz = 0;
   int32_t flags[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(&sizes[0], P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&sizes[1], P->rp4 + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(flags, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  P->release(stmp);
-  P->release(len4);
   P->release(cnt);
   if (flags[0])
     return fail(RBF_ERR_INVALID,
                 "a centre has more than %d neighbouring centres within two support radii",
                 rbf::kMaxCand);
-  const int64_t nnz = sizes[0];
-  if (nnz >= (int64_t(1) << 31) || sizes[1] >= (int64_t(1) << 31))
-    return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
+  if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
   P->nnz_full = nnz;
-  P->nnz4 = sizes[1];
   P->col16 = flags[1] <= 32767;
   GET(P->col, nnz);
   HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, maxd, marks,
                               s));
+
+  // solver layout: sliced ELL with L lanes per row
+  P->lanes = rbf::sell_lanes((double)nnz / (double)std::max<int64_t>(m, 1));
+  const int64_t rows_per_slice = 64 / P->lanes;
+  P->nslices = (m + rows_per_slice - 1) / rows_per_slice;
+  int64_t* ssize;
+  GET(P->slen, P->nslices);
+  GET(P->sptr, P->nslices + 1);
+  GET(ssize, P->nslices + 1);
+  void* stmp2 = P->alloc_bytes(rbf::scan_temp_bytes(P->nslices + 1));
+  if (!stmp2) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, m, P->lanes, P->nslices, P->slen, ssize, s));
+  HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(stmp2);
+  P->release(ssize);
+  P->release(stmp);
   P->release(err);
   P->release(marks);
-  P->col4 = P->alloc_bytes((size_t)std::max<int64_t>(P->nnz4, 1) * (P->col16 ? 2 : 4));
-  if (!P->col4) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
-  HIPCHK(rbf::launch_pad_cols(P->row_ptr, P->col, P->rp4, m, P->col16, P->col4, s));
-  P->group = rbf::cg_group_size((double)P->nnz4 / (double)std::max<int64_t>(m, 1));
+  if (total >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "solver layout exceeds 2^31 entries");
+  P->nsell = total;
+  const size_t cbytes = (size_t)std::max<int64_t>(total, 1) * (P->col16 ? 2 : 4);
+  P->scol = P->alloc_bytes(cbytes);
+  if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
+  HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
+  HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, m, P->sptr, P->lanes, P->col16, P->scol, s));
   return RBF_OK;
 }
 
@@ -399,7 +413,7 @@ rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   a.sc = P->sc;
   a.part_spmv = P->part_spmv;
   a.part_upd = P->part_upd;
-  a.spmv_blocks = rbf::cg_grid_blocks(P->m, P->group, sizeof(XT) == 8);
+  a.spmv_blocks = rbf::cg_grid_blocks(P->nslices);
   a.update_blocks = rbf::cg_update_blocks(P->m);
   return a;
 }
@@ -437,17 +451,17 @@ int read_scalars(rbf_plan* P) {
 int assemble_into(rbf_plan* P, int phi, bool fp32) {
   hipStream_t s = P->stream;
   rbf::PlanView v = P->view();
-  // padding entries of the CSR4 layout are never written: zero them once
+  // padding entries of the sliced-ELL layout are never written: zero them once
   if (fp32) {
     if (!P->val32) {
-      GET(P->val32, P->nnz4);
-      HIPCHK(hipMemsetAsync(P->val32, 0, sizeof(float) * std::max<int64_t>(P->nnz4, 1), s));
+      GET(P->val32, P->nsell);
+      HIPCHK(hipMemsetAsync(P->val32, 0, sizeof(float) * std::max<int64_t>(P->nsell, 1), s));
     }
     if (!P->dinv32) GET(P->dinv32, P->m);
   } else {
     if (!P->val64) {
-      GET(P->val64, P->nnz4);
-      HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * std::max<int64_t>(P->nnz4, 1), s));
+      GET(P->val64, P->nsell);
+      HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * std::max<int64_t>(P->nsell, 1), s));
     }
   }
   void* val = fp32 ? (void*)P->val32 : (void*)P->val64;
@@ -458,14 +472,15 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
     HIPCHK(hipEventRecord(e0, s));
   }
-  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->hs, P->row_ptr, P->lower_cnt, P->col, P->rp4, val,
-                              P->g, P->diag, s));
+  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->hs, P->row_ptr, P->lower_cnt, P->col, P->sptr,
+                              P->lanes, val, P->g, P->diag, s));
   if (P->prof_on) {
     HIPCHK(hipEventRecord(e1, s));
     P->pending.push_back({2, -1, e0, e1});
   }
   void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
-  HIPCHK(rbf::launch_finalize(P->m, P->active, P->rp4, P->lower_cnt, P->diag, P->lambda_rel,
+  HIPCHK(rbf::launch_finalize(P->m, P->active, P->sptr, P->lanes, P->lower_cnt, P->diag,
+                              P->lambda_rel,
                               P->lam, fp32, val, dinv, P->dinv64, s));
   return RBF_OK;
 }
@@ -478,11 +493,13 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   hipStream_t s = P->stream;
   rbf::CgArgs<XT> a = make_args<XT>(P, vec, dinv);
   rbf::CgMatrix A;
-  A.rp4 = P->rp4;
-  A.col = P->col4;
+  A.sptr = P->sptr;
+  A.slen = P->slen;
+  A.nslices = P->nslices;
+  A.col = P->scol;
   A.col16 = P->col16;
   A.val = val;
-  A.group = P->group;
+  A.lanes = P->lanes;
   HIPCHK(rbf::cg_setup<XT>(a, P->active, P->g, o.rtol, o.reliable_delta, s));
   HIPCHK(rbf::cg_true_residual<VT, XT>(a, A, P->g, 1, 0, s));
   const int64_t base_iter = *iters;
@@ -696,30 +713,30 @@ int rbf_system_export(const rbf_plan* P, double* val_upper_h, double* g_h, doubl
   if (P->prec < 0) return fail(RBF_ERR_INVALID, "nothing assembled");
   const int64_t m = P->m;
   if (val_upper_h) {
-    std::vector<int64_t> rp(m + 1), r4(m + 1);
+    std::vector<int64_t> rp(m + 1), sp(P->nslices + 1);
     std::vector<int32_t> low(m);
     std::vector<double> v64;
     std::vector<float> v32;
     HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (m + 1),
                           hipMemcpyDeviceToHost, P->stream));
-    HIPCHK(hipMemcpyAsync(r4.data(), P->rp4, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost,
-                          P->stream));
+    HIPCHK(hipMemcpyAsync(sp.data(), P->sptr, sizeof(int64_t) * (P->nslices + 1),
+                          hipMemcpyDeviceToHost, P->stream));
     HIPCHK(hipMemcpyAsync(low.data(), P->lower_cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
                           P->stream));
     if (P->prec == RBF_PREC_FP64) {
-      v64.resize(std::max<int64_t>(P->nnz4, 1));
-      HIPCHK(hipMemcpyAsync(v64.data(), P->val64, sizeof(double) * P->nnz4,
+      v64.resize(std::max<int64_t>(P->nsell, 1));
+      HIPCHK(hipMemcpyAsync(v64.data(), P->val64, sizeof(double) * P->nsell,
                             hipMemcpyDeviceToHost, P->stream));
     } else {
-      v32.resize(std::max<int64_t>(P->nnz4, 1));
-      HIPCHK(hipMemcpyAsync(v32.data(), P->val32, sizeof(float) * P->nnz4,
+      v32.resize(std::max<int64_t>(P->nsell, 1));
+      HIPCHK(hipMemcpyAsync(v32.data(), P->val32, sizeof(float) * P->nsell,
                             hipMemcpyDeviceToHost, P->stream));
     }
     HIPCHK(hipStreamSynchronize(P->stream));
     int64_t pos = 0;
     for (int64_t j = 0; j < m; ++j)
       for (int64_t e = rp[j] + low[j]; e < rp[j + 1]; ++e) {
-        const int64_t e4 = r4[j] + (e - rp[j]);
+        const int64_t e4 = rbf::sell_pos(sp.data(), P->lanes, j, e - rp[j]);
         val_upper_h[pos++] = P->prec == RBF_PREC_FP64 ? v64[e4] : (double)v32[e4];
       }
   }

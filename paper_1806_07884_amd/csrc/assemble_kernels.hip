@@ -18,6 +18,7 @@
 // FP32 variant: squared distance and support test in float64 (the pattern is
 // fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
 #include "plan_kernels.h"
+#include "solver.h"
 
 namespace rbf {
 namespace {
@@ -68,7 +69,7 @@ template <int DIM, int PHI, typename T>
 __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
     PlanView P, const double* __restrict__ hs, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ lower_cnt, const int32_t* __restrict__ col,
-    const int64_t* __restrict__ rp4, T* __restrict__ val, double* __restrict__ g,
+    const int64_t* __restrict__ sptr, int lanes, T* __restrict__ val, double* __restrict__ g,
     double* __restrict__ diag) {
   __shared__ double sp[kAsmWaves][DIM][kAsmChunk];
   __shared__ int32_t sidx[kAsmWaves][kAsmChunk];
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
         for (int u = 0; u < kAsmWaves; ++u) sum += red[u][lane + kWave * t];
         const T v = (T)sum;
         const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
-        val[rp4[j] + (e - row_ptr[j])] = v;
+        val[sell_pos(sptr, lanes, j, e - row_ptr[j])] = v;
         const int32_t l = lcol[t];
         if (l == (int32_t)j) {
           diag[j] = (double)v;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
             const int64_t mid = (lo + hi) >> 1;
             if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
           }
-          val[rp4[l] + (lo - row_ptr[l])] = v;
+          val[sell_pos(sptr, lanes, l, lo - row_ptr[l])] = v;
         }
       }
     }
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__
 // from the value actually stored.
 template <typename T>
 __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
-                            const int64_t* __restrict__ rp4,
+                            const int64_t* __restrict__ sptr, int lanes,
                             const int32_t* __restrict__ lower_cnt, const double* __restrict__ lam,
                             T* __restrict__ val, T* __restrict__ dinv,
                             double* __restrict__ dinv64) {
@@ -232,7 +233,7 @@ __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
     dinv64[j] = 0.0;
     return;
   }
-  const int64_t e = rp4[j] + lower_cnt[j];
+  const int64_t e = sell_pos(sptr, lanes, j, lower_cnt[j]);
   const T v = (T)((double)val[e] + lam[0]);
   val[e] = v;
   dinv[j] = (T)1 / v;
@@ -241,25 +242,25 @@ __global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
 
 template <int DIM, typename T>
 hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int64_t* row_ptr,
-                        const int32_t* lower_cnt, const int32_t* col, const int64_t* rp4, T* val,
-                        double* g, double* diag, hipStream_t s) {
+                        const int32_t* lower_cnt, const int32_t* col, const int64_t* sptr,
+                        int lanes, T* val, double* g, double* diag, hipStream_t s) {
   const dim3 grid((unsigned)P.m), block(kWave * kAsmWaves);
   switch (phi) {
     case 0:
       hipLaunchKernelGGL((k_assemble<DIM, 0, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, rp4, val, g, diag);
+                         col, sptr, lanes, val, g, diag);
       break;
     case 1:
       hipLaunchKernelGGL((k_assemble<DIM, 1, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, rp4, val, g, diag);
+                         col, sptr, lanes, val, g, diag);
       break;
     case 2:
       hipLaunchKernelGGL((k_assemble<DIM, 2, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, rp4, val, g, diag);
+                         col, sptr, lanes, val, g, diag);
       break;
     default:
       hipLaunchKernelGGL((k_assemble<DIM, 3, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, rp4, val, g, diag);
+                         col, sptr, lanes, val, g, diag);
       break;
   }
   return hipGetLastError();
@@ -269,22 +270,22 @@ hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int6
 
 hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
-                           const int64_t* rp4, void* val, double* g, double* diag,
+                           const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s) {
   if (P.m <= 0) return hipSuccess;
   if (P.dim == 2) {
-    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (float*)val,
+    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (float*)val,
                                          g, diag, s)
-                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, rp4,
+                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes,
                                           (double*)val, g, diag, s);
   }
-  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (float*)val, g,
+  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (float*)val, g,
                                        diag, s)
-              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, rp4, (double*)val,
+              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (double*)val,
                                         g, diag, s);
 }
 
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* rp4,
+hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* sptr, int lanes,
                            const int32_t* lower_cnt, const double* diag, double lambda_rel,
                            double* lam, bool fp32, void* val, void* dinv, double* dinv64,
                            hipStream_t s) {
@@ -293,10 +294,10 @@ hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* rp4,
   const int bs = 256;
   const dim3 grid((unsigned)((m + bs - 1) / bs));
   if (fp32)
-    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, rp4, lower_cnt,
+    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, sptr, lanes, lower_cnt,
                        (const double*)lam, (float*)val, (float*)dinv, dinv64);
   else
-    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, rp4, lower_cnt,
+    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, sptr, lanes, lower_cnt,
                        (const double*)lam, (double*)val, (double*)dinv, dinv64);
   return hipGetLastError();
 }

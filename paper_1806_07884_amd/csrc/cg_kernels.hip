@@ -57,68 +57,87 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
   return block_sum(s, ws);
 }
 
-// Rows handled together by one lane group in one pass.
-template <typename VT>
-constexpr int rows_in_flight() {
-  return 2;
-}
+constexpr int kWavesPerBlock = kBlock / kWave;
 
-// For the kRowsInFlight rows row0 + i * step (i < kRowsInFlight), the group
-// sums az_i = sum_e b_e z[col_e] and ap_i = sum_e b_e p[col_e]; lane `sub`
-// of the group reads entries sub, sub + G, ... of the row (consecutive lanes,
-// consecutive entries: coalesced value loads, neighbouring gather addresses).
-// Column indices are stored as deltas to the row.
-template <typename VT, typename XT, typename CT, int G, int kRowsInFlight>
-__device__ __forceinline__ void rows_products(int64_t m, int64_t row0, int64_t step,
-                                              const int64_t* __restrict__ rp,
-                                              const CT* __restrict__ col,
-                                              const VT* __restrict__ val, const XT* __restrict__ z,
-                                              const XT* __restrict__ p, XT* az, XT* ap) {
-  const int sub = threadIdx.x & (G - 1);
-#pragma unroll
-  for (int i = 0; i < kRowsInFlight; ++i) {
-    const int64_t row = row0 + i * step;
-    XT a = (XT)0, b = (XT)0;
-    if (row < m) {
-      const int32_t r32 = (int32_t)row;
-      const int64_t e1 = rp[row + 1];
-      for (int64_t e = rp[row] + sub; e < e1; e += G) {
-        const int32_t l = r32 + (int32_t)col[e];
-        const XT v = (XT)val[e];
-        a += v * z[l];
-        b += v * p[l];
-      }
-    }
-    az[i] = group_sum<XT, G>(a);
-    ap[i] = group_sum<XT, G>(b);
+// For the slice of S = 64 / L rows owned by this wave, the row sums
+// az = sum_e b_e z[col_e] and ap = sum_e b_e p[col_e], complete in the lane
+// with (lane % L) == 0 of every row.  Four independent loads per lane are in
+// flight per step; rows past m gather from row m - 1 with value 0.
+template <typename VT, typename XT, typename CT, int L>
+__device__ __forceinline__ void slice_products(int64_t m, int64_t slice, const CgMatrix& A,
+                                               const XT* __restrict__ z,
+                                               const XT* __restrict__ p, XT* az, XT* ap,
+                                               int64_t* row_out) {
+  constexpr int S = kWave / L;
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t row = slice * S + lane / L;
+  const int32_t rowc = (int32_t)(row < m ? row : m - 1);
+  const int64_t base = A.sptr[slice] + lane;
+  const int steps = A.slen[slice] / L;
+  XT a0 = (XT)0, a1 = (XT)0, a2 = (XT)0, a3 = (XT)0;
+  XT b0 = (XT)0, b1 = (XT)0, b2 = (XT)0, b3 = (XT)0;
+  int st = 0;
+  for (; st + 3 < steps; st += 4) {
+    const int64_t o = base + (int64_t)st * kWave;
+    const int32_t l0 = rowc + (int32_t)col[o];
+    const int32_t l1 = rowc + (int32_t)col[o + kWave];
+    const int32_t l2 = rowc + (int32_t)col[o + 2 * kWave];
+    const int32_t l3 = rowc + (int32_t)col[o + 3 * kWave];
+    const XT v0 = (XT)val[o], v1 = (XT)val[o + kWave];
+    const XT v2 = (XT)val[o + 2 * kWave], v3 = (XT)val[o + 3 * kWave];
+    a0 += v0 * z[l0];
+    b0 += v0 * p[l0];
+    a1 += v1 * z[l1];
+    b1 += v1 * p[l1];
+    a2 += v2 * z[l2];
+    b2 += v2 * p[l2];
+    a3 += v3 * z[l3];
+    b3 += v3 * p[l3];
   }
+  for (; st < steps; ++st) {
+    const int64_t o = base + (int64_t)st * kWave;
+    const int32_t l0 = rowc + (int32_t)col[o];
+    const XT v0 = (XT)val[o];
+    a0 += v0 * z[l0];
+    b0 += v0 * p[l0];
+  }
+  XT a = (a0 + a1) + (a2 + a3), b = (b0 + b1) + (b2 + b3);
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+  }
+  *az = a;
+  *ap = b;
+  *row_out = row;
 }
 
 // q = (B + lambda I) p_new with p_new = z + beta p_old, factored as
 // q = B z + beta B p_old so that the matrix is streamed before beta is known.
-template <typename VT, typename XT, typename CT, int G>
+// One wave per slice (grid-stride over slices).
+template <typename VT, typename XT, typename CT, int L>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(
-    int64_t m, const int64_t* __restrict__ rp4, const CT* __restrict__ col,
-    const VT* __restrict__ val, const XT* __restrict__ z, const XT* __restrict__ pold,
+    int64_t m, CgMatrix A, const XT* __restrict__ z, const XT* __restrict__ pold,
     XT* __restrict__ pnew, XT* __restrict__ q, CgScalars* __restrict__ sc,
     const double* __restrict__ part_in, int n_in, double* __restrict__ part_out, int parity,
     int fixed_beta) {
-  constexpr int kRowsInFlight = rows_in_flight<VT>();
   __shared__ double ws[kBlock / kWave];
   if (sc->done) return;
   // partials of the previous update: loaded first, reduced after the first
-  // rows' matrix loads are in flight
+  // slice's matrix loads are in flight
   double prz = 0.0, prr = 0.0;
   for (int k = threadIdx.x; k < n_in; k += kBlock) {
     prz += part_in[2 * k];
     prr += part_in[2 * k + 1];
   }
-  const int sub = threadIdx.x & (G - 1);
-  const int64_t step = (int64_t)(kBlock / G);
-  const int64_t pass = (int64_t)gridDim.x * step * kRowsInFlight;
-  int64_t row0 = (int64_t)blockIdx.x * step * kRowsInFlight + threadIdx.x / G;
-  XT az[kRowsInFlight], ap[kRowsInFlight];
-  rows_products<VT, XT, CT, G, kRowsInFlight>(m, row0, step, rp4, col, val, z, pold, az, ap);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  int64_t slice = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  XT az = (XT)0, ap = (XT)0;
+  int64_t row = m;
+  if (slice < A.nslices) slice_products<VT, XT, CT, L>(m, slice, A, z, pold, &az, &ap, &row);
   const double rz = block_sum(prz, ws);
   const double rr = block_sum(prr, ws);
   if (!__builtin_isfinite(rz) || !__builtin_isfinite(rr)) {
@@ -135,23 +154,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(
   const double beta_d = fixed_beta ? sc->beta_fixed : rz / sc->rzh[parity ^ 1];
   const XT beta = (XT)beta_d;
   double contrib = 0.0;
-  for (;;) {
-    if (sub == 0) {
-#pragma unroll
-      for (int i = 0; i < kRowsInFlight; ++i) {
-        const int64_t row = row0 + i * step;
-        if (row < m) {
-          const XT pj = z[row] + beta * pold[row];
-          const XT qj = az[i] + beta * ap[i];
-          pnew[row] = pj;
-          q[row] = qj;
-          contrib += (double)pj * (double)qj;
-        }
-      }
+  while (slice < A.nslices) {
+    if ((lane & (L - 1)) == 0 && row < m) {
+      const XT pj = z[row] + beta * pold[row];
+      const XT qj = az + beta * ap;
+      pnew[row] = pj;
+      q[row] = qj;
+      contrib += (double)pj * (double)qj;
     }
-    row0 += pass;
-    if (row0 - threadIdx.x / G >= m) break;
-    rows_products<VT, XT, CT, G, kRowsInFlight>(m, row0, step, rp4, col, val, z, pold, az, ap);
+    slice += wstride;
+    if (slice < A.nslices) slice_products<VT, XT, CT, L>(m, slice, A, z, pold, &az, &ap, &row);
   }
   const double bs = block_sum(contrib, ws);
   if (threadIdx.x == 0) {
@@ -234,22 +246,32 @@ __global__ void k_fold_solution(int64_t m, double* __restrict__ xhi, XT* __restr
 }
 
 // Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, then
-// r = (XT) r64 and z = D^-1 r, row by row (G lanes per row, CSR4 layout).
-template <typename VT, typename XT, typename CT, int G>
-__global__ __launch_bounds__(kBlock) void k_true_residual(
-    int64_t m, const int64_t* __restrict__ rp4, const CT* __restrict__ col,
-    const VT* __restrict__ val, const double* __restrict__ xhi, const double* __restrict__ g,
-    const XT* __restrict__ dinv, double* __restrict__ r64, XT* __restrict__ r,
-    XT* __restrict__ z) {
-  const int sub = threadIdx.x & (G - 1);
-  for (int64_t row = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G; row < m;
-       row += (int64_t)gridDim.x * (kBlock / G)) {
+// r = (XT) r64 and z = D^-1 r (one wave per slice).
+template <typename VT, typename XT, typename CT, int L>
+__global__ __launch_bounds__(kBlock) void k_true_residual(int64_t m, CgMatrix A,
+                                                          const double* __restrict__ xhi,
+                                                          const double* __restrict__ g,
+                                                          const XT* __restrict__ dinv,
+                                                          double* __restrict__ r64,
+                                                          XT* __restrict__ r, XT* __restrict__ z) {
+  constexpr int S = kWave / L;
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t slice = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+       slice < A.nslices; slice += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t row = slice * S + lane / L;
+    const int32_t rowc = (int32_t)(row < m ? row : m - 1);
+    const int64_t base = A.sptr[slice] + lane;
+    const int steps = A.slen[slice] / L;
     double acc = 0.0;
-    const int64_t e1 = rp4[row + 1];
-    for (int64_t e = rp4[row] + sub; e < e1; e += G)
-      acc += (double)val[e] * xhi[(int32_t)row + (int32_t)col[e]];
-    acc = group_sum<double, G>(acc);
-    if (sub == 0) {
+    for (int st = 0; st < steps; ++st) {
+      const int64_t o = base + (int64_t)st * kWave;
+      acc += (double)val[o] * xhi[rowc + (int32_t)col[o]];
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if ((lane & (L - 1)) == 0 && row < m) {
       const double rv = g[row] - acc;
       const XT ri = (XT)rv;
       r64[row] = rv;
@@ -338,21 +360,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t m, const double* __r
   }
 }
 
-template <typename VT, typename XT, typename CT, int G>
-void launch_spmv_g(const CgArgs<XT>& a, const int64_t* rp4, const CT* col, const VT* val,
-                   int parity, int fixed_beta, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
-                     rp4, col, val, (const XT*)a.z, (const XT*)a.p[parity],
-                     a.p[parity ^ 1], a.q, a.sc, (const double*)a.part_upd, a.update_blocks,
-                     a.part_spmv, parity, fixed_beta);
+template <typename VT, typename XT, typename CT, int L>
+void launch_spmv_l(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m, A,
+                     (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1], a.q, a.sc,
+                     (const double*)a.part_upd, a.update_blocks, a.part_spmv, parity,
+                     fixed_beta);
 }
 
-template <typename VT, typename XT, typename CT, int G>
-void launch_true_residual_g(const CgArgs<XT>& a, const int64_t* rp4, const CT* col,
-                            const VT* val, const double* g, hipStream_t s) {
-  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, G>), dim3(a.spmv_blocks), dim3(kBlock), 0, s,
-                     a.m, rp4, col, val, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r,
-                     a.z);
+template <typename VT, typename XT, typename CT, int L>
+void launch_true_residual_l(const CgArgs<XT>& a, const CgMatrix& A, const double* g,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s,
+                     a.m, A, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r, a.z);
 }
 
 bool grids_ok(int spmv_blocks, int update_blocks) {
@@ -362,18 +383,14 @@ bool grids_ok(int spmv_blocks, int update_blocks) {
 
 }  // namespace
 
-int cg_group_size(double mean_row) {
-  // four stored entries per lane per step: one step covers 4 G entries
-  if (mean_row > 128) return 64;
-  if (mean_row > 64) return 32;
-  if (mean_row > 32) return 16;
-  return 8;
+int sell_lanes(double mean_row) {
+  if (mean_row > 192) return 8;
+  if (mean_row > 24) return 4;
+  return 2;
 }
 
-int cg_grid_blocks(int64_t m, int group, bool fp64) {
-  const int64_t rows_per_block =
-      (int64_t)(kBlock / group) * (fp64 ? rows_in_flight<double>() : rows_in_flight<float>());
-  const int64_t b = (m + rows_per_block - 1) / rows_per_block;
+int cg_grid_blocks(int64_t nslices) {
+  const int64_t b = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
   return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
 }
 
@@ -387,25 +404,19 @@ namespace {
 template <typename VT, typename XT, typename CT>
 void spmv_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
                    hipStream_t s) {
-  const CT* col = static_cast<const CT*>(A.col);
-  const VT* val = static_cast<const VT*>(A.val);
-  switch (A.group) {
-    case 8: launch_spmv_g<VT, XT, CT, 8>(a, A.rp4, col, val, parity, fixed_beta, s); break;
-    case 16: launch_spmv_g<VT, XT, CT, 16>(a, A.rp4, col, val, parity, fixed_beta, s); break;
-    case 32: launch_spmv_g<VT, XT, CT, 32>(a, A.rp4, col, val, parity, fixed_beta, s); break;
-    default: launch_spmv_g<VT, XT, CT, 64>(a, A.rp4, col, val, parity, fixed_beta, s); break;
+  switch (A.lanes) {
+    case 2: launch_spmv_l<VT, XT, CT, 2>(a, A, parity, fixed_beta, s); break;
+    case 4: launch_spmv_l<VT, XT, CT, 4>(a, A, parity, fixed_beta, s); break;
+    default: launch_spmv_l<VT, XT, CT, 8>(a, A, parity, fixed_beta, s); break;
   }
 }
 
 template <typename VT, typename XT, typename CT>
 void residual_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, hipStream_t s) {
-  const CT* col = static_cast<const CT*>(A.col);
-  const VT* val = static_cast<const VT*>(A.val);
-  switch (A.group) {
-    case 8: launch_true_residual_g<VT, XT, CT, 8>(a, A.rp4, col, val, g, s); break;
-    case 16: launch_true_residual_g<VT, XT, CT, 16>(a, A.rp4, col, val, g, s); break;
-    case 32: launch_true_residual_g<VT, XT, CT, 32>(a, A.rp4, col, val, g, s); break;
-    default: launch_true_residual_g<VT, XT, CT, 64>(a, A.rp4, col, val, g, s); break;
+  switch (A.lanes) {
+    case 2: launch_true_residual_l<VT, XT, CT, 2>(a, A, g, s); break;
+    case 4: launch_true_residual_l<VT, XT, CT, 4>(a, A, g, s); break;
+    default: launch_true_residual_l<VT, XT, CT, 8>(a, A, g, s); break;
   }
 }
 

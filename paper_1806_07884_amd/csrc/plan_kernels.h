@@ -117,20 +117,25 @@ size_t symbolic_marks_words(int64_t m);
 hipError_t launch_symbolic(const PlanView& P, bool fill, int64_t* full_cnt, int32_t* lower_cnt,
                            const int64_t* row_ptr, int32_t* col, int32_t* err, int32_t* maxdelta,
                            uint32_t* marks, hipStream_t s);
-hipError_t launch_pad_lengths(const int64_t* row_ptr, int64_t m, int64_t* len4, hipStream_t s);
-hipError_t launch_pad_cols(const int64_t* row_ptr, const int32_t* col, const int64_t* rp4,
-                           int64_t m, bool col16, void* col4, hipStream_t s);
+// Sliced-ELL layout of the solver (see CgMatrix): slice lengths and sizes,
+// then the column deltas at their positions.
+hipError_t launch_slice_lengths(const int64_t* row_ptr, int64_t m, int lanes, int64_t nslices,
+                                int32_t* slen, int64_t* ssize, hipStream_t s);
+hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, int64_t m,
+                            const int64_t* sptr, int lanes, bool col16, void* cols,
+                            hipStream_t s);
 
 }  // namespace rbf
 
 namespace rbf {
 // assemble_kernels.hip
-// Values go to the CSR4 layout: entry e of row j (unpadded CSR) sits at
-// rp4[j] + (e - row_ptr[j]).
+// Values go to the solver's sliced-ELL layout (sptr, lanes): entry e of row j
+// of the CSR pattern sits at sell_pos(sptr, lanes, j, e - row_ptr[j]).
 hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
-                           const int64_t* rp4, void* val, double* g, double* diag, hipStream_t s);
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* rp4,
+                           const int64_t* sptr, int lanes, void* val, double* g, double* diag,
+                           hipStream_t s);
+hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* sptr, int lanes,
                            const int32_t* lower_cnt, const double* diag, double lambda_rel,
                            double* lam, bool fp32, void* val, void* dinv, double* dinv64,
                            hipStream_t s);

@@ -7,6 +7,7 @@
 // the suffix l >= j of each sorted row):
 //     { l active : supp(j) and supp(l) share a point }.
 #include "plan_kernels.h"
+#include "solver.h"
 
 namespace rbf {
 namespace {
@@ -299,46 +300,66 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   }
 }
 
-// Padded row lengths: every row of the CSR4 layout is a multiple of 4 entries.
-__global__ void k_pad_lengths(const int64_t* __restrict__ row_ptr, int64_t m,
-                              int64_t* __restrict__ len4) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > m) return;
-  len4[j] = j == m ? 0 : ((row_ptr[j + 1] - row_ptr[j] + 3) & ~int64_t(3));
+// Sliced-ELL geometry: entries per row of every slice (longest row of the
+// slice rounded up to a multiple of L) and the slice's size S * slen.
+__global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr, int64_t m, int lanes,
+                                int64_t nslices, int32_t* __restrict__ slen,
+                                int64_t* __restrict__ ssize) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nslices) return;
+  if (s == nslices) {
+    ssize[s] = 0;
+    return;
+  }
+  const int64_t rows = kWave / lanes;
+  int64_t mx = 0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const int64_t j = s * rows + i;
+    if (j < m) {
+      const int64_t len = row_ptr[j + 1] - row_ptr[j];
+      mx = len > mx ? len : mx;
+    }
+  }
+  mx = (mx + lanes - 1) / lanes * lanes;
+  slen[s] = (int32_t)mx;
+  ssize[s] = mx * rows;
 }
 
-// Column deltas l - j in the CSR4 layout, one wave per row; padding gets 0.
+// Column deltas l - j of every stored entry at its sliced-ELL position, one
+// wave per row (padding stays 0 from the allocation).
 template <typename CT>
-__global__ __launch_bounds__(256) void k_pad_cols(const int64_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const int64_t* __restrict__ rp4, int64_t m,
-                                                  CT* __restrict__ col4) {
+__global__ __launch_bounds__(256) void k_sell_cols(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, int64_t m,
+                                                   const int64_t* __restrict__ sptr, int lanes,
+                                                   CT* __restrict__ cols) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (j >= m) return;
-  const int64_t a = row_ptr[j], n = row_ptr[j + 1] - a, b = rp4[j], n4 = rp4[j + 1] - b;
-  for (int64_t t = lane; t < n4; t += kWave) col4[b + t] = t < n ? (CT)(col[a + t] - (int32_t)j) : (CT)0;
+  const int64_t a = row_ptr[j], n = row_ptr[j + 1] - a;
+  for (int64_t k = lane; k < n; k += kWave) cols[sell_pos(sptr, lanes, j, k)] = (CT)(col[a + k] - (int32_t)j);
 }
 
 }  // namespace
 
-hipError_t launch_pad_lengths(const int64_t* row_ptr, int64_t m, int64_t* len4, hipStream_t s) {
+hipError_t launch_slice_lengths(const int64_t* row_ptr, int64_t m, int lanes, int64_t nslices,
+                                int32_t* slen, int64_t* ssize, hipStream_t s) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_pad_lengths, dim3((unsigned)((m + 1 + bs - 1) / bs)), dim3(bs), 0, s,
-                     row_ptr, m, len4);
+  hipLaunchKernelGGL(k_slice_lengths, dim3((unsigned)((nslices + 1 + bs - 1) / bs)), dim3(bs), 0,
+                     s, row_ptr, m, lanes, nslices, slen, ssize);
   return hipGetLastError();
 }
 
-hipError_t launch_pad_cols(const int64_t* row_ptr, const int32_t* col, const int64_t* rp4,
-                           int64_t m, bool col16, void* col4, hipStream_t s) {
+hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, int64_t m,
+                            const int64_t* sptr, int lanes, bool col16, void* cols,
+                            hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((unsigned)((m + 3) / 4));
   if (col16)
-    hipLaunchKernelGGL(k_pad_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, rp4, m,
-                       (int16_t*)col4);
+    hipLaunchKernelGGL(k_sell_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, m, sptr, lanes,
+                       (int16_t*)cols);
   else
-    hipLaunchKernelGGL(k_pad_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, rp4, m,
-                       (int32_t*)col4);
+    hipLaunchKernelGGL(k_sell_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, m, sptr, lanes,
+                       (int32_t*)cols);
   return hipGetLastError();
 }
 

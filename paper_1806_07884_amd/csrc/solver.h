@@ -43,20 +43,32 @@ struct CgArgs {
   int update_blocks;
 };
 
-// The stored matrix in the solver's CSR layout: row j occupies
-// [rp4[j], rp4[j+1]), padded to a multiple of 4 entries; columns are stored
-// as l - j (int16 when every |l - j| fits, else int32); padding entries have
+// The stored matrix in the solver's sliced-ELL layout.  Rows are taken in
+// slices of S = 64 / L consecutive rows; each row of a slice gets L lanes of a
+// wave.  Slice s starts at sptr[s] and holds slen[s] entries per row (the
+// longest row of the slice, rounded up to a multiple of L); entry k of row
+// i = j - s S sits at sptr[s] + (k / L) * 64 + i * L + (k % L), so every
+// wave-wide load is one contiguous 64-entry run.  Columns are stored as
+// l - j (int16 when every |l - j| fits, else int32); padding entries have
 // delta 0 and value 0.
 struct CgMatrix {
-  const int64_t* rp4;
+  const int64_t* sptr;
+  const int32_t* slen;
+  int64_t nslices;
   const void* col;
   bool col16;
   const void* val;  // VT
-  int group;        // lanes per row
+  int lanes;        // L: lanes per row (2, 4 or 8)
 };
 
-int cg_group_size(double mean_row);
-int cg_grid_blocks(int64_t m, int group, bool fp64);
+__host__ __device__ inline int64_t sell_pos(const int64_t* sptr, int lanes, int64_t j, int64_t k) {
+  const int64_t rows = 64 / lanes;
+  const int64_t s = j / rows, i = j - s * rows;
+  return sptr[s] + (k / lanes) * 64 + i * lanes + (k % lanes);
+}
+
+int sell_lanes(double mean_row);
+int cg_grid_blocks(int64_t nslices);
 int cg_update_blocks(int64_t m);
 
 // Iteration k = cg_spmv(parity = k & 1) then cg_update(parity).  fixed_beta:
