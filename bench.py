@@ -39,19 +39,23 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(nnz_full: int, m: int, val_bytes: int, vec_bytes: int) -> int:
-    """Algorithmic HBM bytes of one CG SpMV launch: every stored value and column
-    index once, the row pointers once, and four length-M vectors (z and p_old
-    read, p_new and q written)."""
-    return nnz_full * (val_bytes + 4) + (m + 1) * 8 + 4 * m * vec_bytes
+def spmv_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int) -> int:
+    """Algorithmic HBM bytes of one CG SpMV launch: every nonzero of B once
+    (value and column index, padding excluded) and four length-M vectors
+    (z and p_old read, p_new and q written)."""
+    return nnz_full * (val_bytes + col_bytes) + 4 * m * vec_bytes
 
 
 def kernel_digest() -> str:
-    h = hashlib.sha256()
-    for f in ("cg_kernels.hip", "solver.h", "common.h"):
-        with open(os.path.join(ROOT, "paper_1806_07884_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Digest of the SpMV kernel's source (its device code and layout struct)."""
+    csrc = os.path.join(ROOT, "paper_1806_07884_amd", "csrc")
+    src = open(os.path.join(csrc, "cg_kernels.hip")).read()
+    a = src.index("// For the slice of S = 64 / L rows owned by this wave")
+    b = src.index("template <typename XT>\n__global__ __launch_bounds__(kBlock) void k_cg_update(")
+    hdr = open(os.path.join(csrc, "solver.h")).read()
+    c = hdr.index("struct CgMatrix {")
+    d = hdr.index("};", c)
+    return hashlib.sha256((src[a:b] + hdr[c:d]).encode()).hexdigest()[:16]
 
 
 def cpu_baseline(prob, frac: float):
@@ -90,7 +94,7 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="timed float64 fits for the comparison (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=float, default=0.5)
+    ap.add_argument("--cpu-window", type=float, default=0.7)
     ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -153,21 +157,23 @@ def main() -> int:
             plan.close()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        avg = spmv_ms / max(spmv_n, 1) * 1e3
         log(f"{prec}: {dt * 1e3:.1f} ms/fit, iters {per[-1][0]['iterations']}, "
-            f"rmse {per[-1][1]:.6e}, spmv avg {spmv_ms / max(spmv_n, 1) * 1e3:.2f} us")
-        return dt, per, stats, spmv_n, spmv_ms, asm_ms / steps
+            f"rmse {per[-1][1]:.6e}, spmv kernel {avg:.2f} us")
+        return dt, per, stats, spmv_n, avg, asm_ms / steps
 
     steps = max(1, args.steps)
-    dt32, per32, stats, n32, ms32, asm32 = timed("fp32", steps, args.warmup)
-    dt64, per64, _, n64, ms64, asm64 = timed("fp64", args.fp64_steps or steps, args.warmup)
+    dt32, per32, stats, n32, avg32, asm32 = timed("fp32", steps, args.warmup)
+    dt64, per64, _, n64, avg64, asm64 = timed("fp64", args.fp64_steps or steps, args.warmup)
     value = n_train / dt32
     rmse32, rmse64 = per32[-1][1], per64[-1][1]
     matched = abs(rmse32 - rmse64) <= 1e-3 * rmse64
 
-    nnz, m = stats["nnz_full"], stats["n_centers"]
-    avg_s = ms32 / max(n32, 1) / 1e3
-    bytes32 = spmv_bytes(nnz, m, 4, 4)
-    achieved = bytes32 / avg_s if avg_s > 0 else 0.0
+    nnz, m, cb = stats["nnz_full"], stats["n_centers"], stats["solver_col_bytes"]
+    # kernel time from start/stop events of sampled launches on the plan's stream
+    kern32 = max(avg32, 1e-3) * 1e-6
+    bytes32 = spmv_bytes(nnz, m, 4, cb, 4)
+    achieved = bytes32 / kern32
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "spmv_fp32_terrain2d_traffic.json")
     if os.path.exists(tfile):
@@ -177,10 +183,11 @@ def main() -> int:
             traffic = t.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "kernel": "k_cg_spmv<float,float>", "bytes_per_launch": bytes32,
-                "avg_launch_us": avg_s * 1e6, "timed_launches": n32}
-    avg64 = ms64 / max(n64, 1) / 1e3
-    b64 = spmv_bytes(nnz, m, 8, 8)
+                "kernel": "k_cg_spmv<float,float,int16,L>", "bytes_per_launch": bytes32,
+                "avg_kernel_us": kern32 * 1e6, "timed_launches": n32,
+                "solver_entries": stats["solver_entries"], "solver_lanes": stats["solver_lanes"]}
+    kern64 = max(avg64, 1e-3) * 1e-6
+    b64 = spmv_bytes(nnz, m, 8, cb, 8)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,8 +213,8 @@ def main() -> int:
         "fp64": {"value": n_train / dt64, "ms_per_fit": dt64 * 1e3,
                  "iterations": per64[-1][0]["iterations"],
                  "rel_residual": per64[-1][0]["rel_residual"], "heldout_rmse": rmse64,
-                 "assembly_ms": asm64, "spmv_avg_us": avg64 * 1e6,
-                 "spmv_gbps": (b64 / avg64 / 1e9) if avg64 > 0 else None},
+                 "assembly_ms": asm64, "spmv_kernel_us": kern64 * 1e6,
+                 "spmv_gbps": b64 / kern64 / 1e9},
         "speedup_mixed_vs_fp64": dt64 / dt32,
         "rmse_matched": bool(matched),
     }

@@ -104,6 +104,9 @@ typedef struct {
   int32_t support_max;          /* max_j n_j */
   int32_t row_max;              /* max entries in a full row of B */
   double cell_size;
+  int64_t solver_entries;       /* stored entries of the solver layout (with padding) */
+  int32_t solver_col_bytes;     /* bytes per stored column index (2 or 4) */
+  int32_t solver_lanes;         /* lanes per row of the solver layout */
 } rbf_plan_stats;
 
 typedef struct {
@@ -180,9 +183,11 @@ int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
              const double* coeffs, double* out, const double* values, double* rmse_h);
 
 /* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
- * starts bracketing, with HIP events on the plan's stream, the assembly launch
- * and every fourth CG matrix-vector launch (launches that returned at entry
- * after convergence are not counted); rbf_profile(plan, 0) stops.
+ * starts timing, with HIP events on the plan's stream, the assembly launch
+ * (events recorded around it) and every fourth CG matrix-vector launch
+ * (events stamped at the kernel's own start and end by the extended launch;
+ * launches that returned at entry after convergence are not counted);
+ * rbf_profile(plan, 0) stops.
  * rbf_profile_read returns the number of timed launches of `kernel` and their
  * summed duration in milliseconds.  Both block the host (stream sync).
  * Kernel ids: */
@@ -190,6 +195,69 @@ int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
 #define RBF_KERNEL_ASSEMBLE 2  /* numeric assembly of B and g */
 int rbf_profile(rbf_plan* plan, int32_t enable);
 int rbf_profile_read(rbf_plan* plan, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* ---- learned support radius -------------------------------------------- *
+ * The paper observes that CS-RBF approximation is sensitive to data density
+ * and to the shape parameter, chooses alpha = 1/rho experimentally (Section 6,
+ * Table 3) and leaves optimal shape parameters to future work (Section 7).
+ * These calls predict a radius per block of centres from the local density:
+ * density features -> MLP 16-64-64-1 (tanh) -> log(rho / spacing) -> rho_j.
+ * Blocks: a uniform blocks_per_dim^dim partition of the centres' bounding box,
+ * t = (xi - min) / (max - min), b = min(nb - 1, floor(t nb)) per dimension,
+ * first coordinate fastest (queries outside the box go to the nearest block). */
+#define RBF_MLP_INPUTS 16
+#define RBF_MLP_PARAMS 5313  /* W1[16][64] input-major, b1[64], W2[64][64], b2[64], W3[64], b3 */
+#define RBF_MAX_RADII 8
+
+typedef struct rbf_mlp rbf_mlp;
+
+/* feats (device float32 [nblocks][2 n_radii]): for block b and radius s, the
+ * mean and the population standard deviation over the block's centres of
+ * log(1 + n_j(radii_h[s])), n_j = points in the support of centre j at that
+ * radius (strict predicate as above).  1 <= n_radii <= 8; every radius at
+ * most four hash cells (build the plan with rho = the largest radius).
+ * Blocks the host.  Errors: INVALID. */
+int rbf_density_features(rbf_plan* plan, int32_t n_radii, const double* radii_h,
+                         int32_t blocks_per_dim, float* feats);
+
+/* Per block: sums_h[b] = sum of (f - h)^2 and counts_h[b] = number of the
+ * n_query points (device SoA [dim][n_query]; f, h device [n_query]) in block
+ * b; for held-out scoring of radius sweeps.  Blocks the host. */
+int rbf_block_sq_err(rbf_plan* plan, int64_t n_query, const double* queries, const double* f,
+                     const double* h, int32_t blocks_per_dim, double* sums_h, int64_t* counts_h);
+
+/* rho_out[j] (device [M]) = clamp(spacing exp(pred_log[block(j)]), rho_min,
+ * rho_max), or rho_fallback where the prediction is not finite; pred_log is
+ * device float32 [nblocks].  Blocks the host. */
+int rbf_radius_broadcast(rbf_plan* plan, const float* pred_log, int32_t blocks_per_dim,
+                         double spacing, double rho_min, double rho_max, double rho_fallback,
+                         double* rho_out);
+
+/* An MLP with the given float32 parameters (host [RBF_MLP_PARAMS]) and zero
+ * Adam moments; its work runs on `stream`.  The object owns its device
+ * memory.  Blocks the host. */
+int rbf_mlp_create(const float* params_h, void* stream, rbf_mlp** out);
+int rbf_mlp_params(const rbf_mlp* mlp, float* params_h);  /* copy out; blocks */
+
+/* Gradient (host [RBF_MLP_PARAMS]) and value (host scalar) of the mean
+ * squared error of the float32 network over n rows x (device [n][16]) with
+ * targets y (device [n]).  Blocks the host. */
+int rbf_mlp_grad(rbf_mlp* mlp, const float* x, const float* y, int64_t n, float* grad_h,
+                 float* loss_h);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * mini-batches of `batch` rows: step k uses rows order[k*batch .. ) (device
+ * int32 [steps*batch], each in [0, n_rows)), float32 forward and backward in
+ * one workgroup.  losses_h (host [steps], may be NULL) gets every batch loss.
+ * The row indices are checked on the host first.  Blocks the host. */
+int rbf_mlp_train(rbf_mlp* mlp, const float* x, const float* y, int64_t n_rows,
+                  const int32_t* order, int32_t steps, int32_t batch, float lr, float* losses_h);
+
+/* out (device float32 [n]) = network(x) with weights, inputs and hidden
+ * activations rounded to bfloat16 (nearest even) and float32 accumulation.
+ * Stream-ordered. */
+int rbf_mlp_infer_bf16(const rbf_mlp* mlp, const float* x, int64_t n, float* out);
+void rbf_mlp_destroy(rbf_mlp* mlp);
 
 /* Release every buffer of the plan (after the plan's stream work finished). */
 void rbf_plan_destroy(rbf_plan* plan);

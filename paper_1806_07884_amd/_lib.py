@@ -22,6 +22,9 @@ RBF_ERR_HIP = -5
 RBF_ERR_OOM = -6
 
 KERNEL = {"spmv": 0, "assemble": 2}
+MLP_PARAMS = 5313
+MLP_INPUTS = 16
+MAX_RADII = 8
 PHI = {"w30": 0, "w31": 1, "w32": 2, "w33": 3}
 PREC = {"fp64": 0, "fp32": 1}
 
@@ -43,7 +46,8 @@ class PlanStats(ctypes.Structure):
                 ("nnz_upper", ctypes.c_int64), ("nnz_full", ctypes.c_int64),
                 ("density", ctypes.c_double), ("support_total", ctypes.c_int64),
                 ("support_max", ctypes.c_int32), ("row_max", ctypes.c_int32),
-                ("cell_size", ctypes.c_double)]
+                ("cell_size", ctypes.c_double), ("solver_entries", ctypes.c_int64),
+                ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -87,6 +91,25 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]),
     "rbf_plan_destroy": (None, [ctypes.c_void_p]),
+    "rbf_density_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p]),
+    "rbf_block_sq_err": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_radius_broadcast": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_void_p]),
+    "rbf_mlp_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_mlp_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_mlp_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_mlp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_float, ctypes.c_void_p]),
+    "rbf_mlp_infer_bf16": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "rbf_mlp_destroy": (None, [ctypes.c_void_p]),
     "rbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbf_last_error": (ctypes.c_char_p, []),
 }

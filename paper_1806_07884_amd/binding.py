@@ -202,5 +202,123 @@ def rbf_profile_read(plan: Plan, kernel: str):
     return n.value, ms.value
 
 
+def _need32(t, name, shape=None):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda \
+            or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def rbf_density_features(plan: Plan, radii, blocks_per_dim: int) -> torch.Tensor:
+    """Per-block density features [nblocks, 2 len(radii)] (float32, on the GPU)."""
+    r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
+    nblk = blocks_per_dim ** plan.dim
+    out = torch.empty((nblk, 2 * len(r)), dtype=torch.float32, device=plan.device)
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_density_features(plan.handle, len(r), r.ctypes.data, blocks_per_dim,
+                                             out.data_ptr()), "rbf_density_features")
+    return out
+
+
+def rbf_block_sq_err(plan: Plan, queries: torch.Tensor, f: torch.Tensor, h: torch.Tensor,
+                     blocks_per_dim: int):
+    """(sum of squared errors, count) per block of the centres' box, on the host."""
+    _need(queries, "queries")
+    nq = int(queries.shape[1])
+    _need(f, "f", (nq,))
+    _need(h, "h", (nq,))
+    nblk = blocks_per_dim ** plan.dim
+    sums = np.zeros(nblk)
+    cnt = np.zeros(nblk, np.int64)
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_block_sq_err(plan.handle, nq, queries.data_ptr(), f.data_ptr(),
+                                         h.data_ptr(), blocks_per_dim, sums.ctypes.data,
+                                         cnt.ctypes.data), "rbf_block_sq_err")
+    return sums, cnt
+
+
+def rbf_radius_broadcast(plan: Plan, pred_log: torch.Tensor, blocks_per_dim: int, spacing: float,
+                         rho_min: float, rho_max: float, rho_fallback: float) -> torch.Tensor:
+    """Per-centre radii (float64 [M] on the GPU) from per-block log-radius predictions."""
+    nblk = blocks_per_dim ** plan.dim
+    _need32(pred_log, "pred_log", (nblk,))
+    out = torch.empty(plan.m, dtype=torch.float64, device=plan.device)
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_radius_broadcast(plan.handle, pred_log.data_ptr(), blocks_per_dim,
+                                             float(spacing), float(rho_min), float(rho_max),
+                                             float(rho_fallback), out.data_ptr()),
+                "rbf_radius_broadcast")
+    return out
+
+
+class Mlp:
+    """Owner of an rbf_mlp handle (the 16-64-64-1 radius network)."""
+
+    def __init__(self, params, device=None, stream=None):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.shape != (L.MLP_PARAMS,):
+            raise ValueError(f"params must have {L.MLP_PARAMS} entries")
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_create(p.ctypes.data, ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(self.handle)), "rbf_mlp_create")
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(L.MLP_PARAMS, np.float32)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_params(self.handle, out.ctypes.data), "rbf_mlp_params")
+        return out
+
+    def grad(self, x: torch.Tensor, y: torch.Tensor):
+        n = int(x.shape[0])
+        _need32(x, "x", (n, L.MLP_INPUTS))
+        _need32(y, "y", (n,))
+        g = np.zeros(L.MLP_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_grad(self.handle, x.data_ptr(), y.data_ptr(), n, g.ctypes.data,
+                                         ctypes.byref(loss)), "rbf_mlp_grad")
+        return float(loss.value), g
+
+    def train(self, x: torch.Tensor, y: torch.Tensor, order, batch: int, lr: float):
+        n = int(x.shape[0])
+        _need32(x, "x", (n, L.MLP_INPUTS))
+        _need32(y, "y", (n,))
+        o = torch.as_tensor(np.ascontiguousarray(np.asarray(order, dtype=np.int32)),
+                            device=self.device)
+        steps = int(o.numel()) // batch
+        losses = np.zeros(max(steps, 1), np.float32)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_train(self.handle, x.data_ptr(), y.data_ptr(), n, o.data_ptr(),
+                                          steps, batch, float(lr), losses.ctypes.data),
+                    "rbf_mlp_train")
+        return losses[:steps]
+
+    def infer_bf16(self, x: torch.Tensor) -> torch.Tensor:
+        n = int(x.shape[0])
+        _need32(x, "x", (n, L.MLP_INPUTS))
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_infer_bf16(self.handle, x.data_ptr(), n, out.data_ptr()),
+                    "rbf_mlp_infer_bf16")
+        return out
+
+    def close(self):
+        if self.handle and self.handle.value:
+            with torch.cuda.device(self.device):
+                L.lib().rbf_mlp_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def rbf_plan_destroy(plan: Plan) -> None:
     plan.close()

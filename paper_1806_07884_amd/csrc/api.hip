@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "mlp_kernels.h"
 #include "plan_kernels.h"
 #include "rbf.h"
 #include "solver.h"
@@ -54,6 +55,8 @@ struct rbf_plan {
   double lambda_rel = 0.0;
   rbf::Grid grid{};
   double cell_size = 0.0;
+  double cbox[6] = {0, 0, 0, 0, 0, 0};  // centres' bounding box {min_0, max_0, ...}
+  double* cbox_dev = nullptr;
 
   // hash of points and centres
   double* ps = nullptr;
@@ -299,6 +302,10 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
     cs *= 1.25;
   }
   P->cell_size = cs;
+  for (int k = 0; k < dim; ++k) {
+    P->cbox[2 * k] = host[3 * k];
+    P->cbox[2 * k + 1] = host[3 * k + 1];
+  }
   P->grid.inv_cs = 1.0 / cs;
   int64_t ncell = 1;
   for (int k = 0; k < 3; ++k) {
@@ -540,20 +547,16 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
     const int chunk = (int)std::min<int64_t>(left, o.check_every);
     for (int it = 0; it < chunk; ++it) {
       const int par = (int)((h.iter + it) & 1);
-      // every fourth launch is bracketed by events when timing is on
+      // every fourth launch carries start/stop events when timing is on
       const bool timed = P->prof_on && (it & 3) == 0;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         e0 = P->event();
         e1 = P->event();
         if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
-        HIPCHK(hipEventRecord(e0, s));
       }
-      HIPCHK(rbf::cg_spmv<VT, XT>(a, A, par, (fixed_beta && it == 0) ? 1 : 0, s));
-      if (timed) {
-        HIPCHK(hipEventRecord(e1, s));
-        P->pending.push_back({0, *iters + it, e0, e1});
-      }
+      HIPCHK(rbf::cg_spmv<VT, XT>(a, A, par, (fixed_beta && it == 0) ? 1 : 0, e0, e1, s));
+      if (timed) P->pending.push_back({0, *iters + it, e0, e1});
       HIPCHK(rbf::cg_update<XT>(a, par, s));
     }
     fixed_beta = false;
@@ -656,6 +659,9 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->nnz_upper = (P->nnz_full + na) / 2;
   o->n_points_in_box = in_box;
   o->density = (double)P->nnz_full / ((double)P->m * (double)P->m);
+  o->solver_entries = P->nsell;
+  o->solver_col_bytes = P->col16 ? 2 : 4;
+  o->solver_lanes = P->lanes;
   return RBF_OK;
 }
 
@@ -862,5 +868,211 @@ int rbf_profile_read(rbf_plan* P, int32_t kernel, int64_t* launches, double* tot
 }
 
 void rbf_plan_destroy(rbf_plan* P) { delete P; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned radius
+struct rbf_mlp {
+  hipStream_t stream = nullptr;
+  float* params = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  int64_t t = 0;  // Adam steps taken
+  ~rbf_mlp() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (params) (void)hipFree(params);
+    if (m1) (void)hipFree(m1);
+    if (m2) (void)hipFree(m2);
+  }
+};
+
+namespace {
+
+int ensure_cbox(rbf_plan* P) {
+  if (!P->cbox_dev) {
+    GET(P->cbox_dev, 6);
+    HIPCHK(hipMemcpyAsync(P->cbox_dev, P->cbox, sizeof P->cbox, hipMemcpyHostToDevice, P->stream));
+  }
+  return RBF_OK;
+}
+
+int check_blocks(const rbf_plan* P, int32_t bpd, int* nblocks) {
+  if (bpd < 1) return fail(RBF_ERR_INVALID, "blocks_per_dim must be >= 1");
+  int64_t nb = 1;
+  for (int d = 0; d < P->dim; ++d) nb *= bpd;
+  if (nb > 65536) return fail(RBF_ERR_INVALID, "too many blocks");
+  *nblocks = (int)nb;
+  return RBF_OK;
+}
+
+template <typename T>
+struct DevTmp {
+  T* p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(int64_t n) { return hipMalloc(&p, sizeof(T) * (size_t)std::max<int64_t>(n, 1)); }
+};
+
+}  // namespace
+
+extern "C" {
+
+int rbf_density_features(rbf_plan* P, int32_t n_radii, const double* radii_h,
+                         int32_t blocks_per_dim, float* feats) {
+  if (!P || !radii_h || !feats) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (n_radii < 1 || n_radii > rbf::kMaxRadii)
+    return fail(RBF_ERR_INVALID, "n_radii must be in [1, %d]", rbf::kMaxRadii);
+  double rmax = 0.0;
+  for (int s = 0; s < n_radii; ++s) {
+    if (!(radii_h[s] > 0.0) || !isfinite(radii_h[s])) return fail(RBF_ERR_INVALID, "bad radius");
+    rmax = std::max(rmax, radii_h[s]);
+  }
+  int nblocks = 0;
+  int rc = check_blocks(P, blocks_per_dim, &nblocks);
+  if (rc) return rc;
+  rc = ensure_cbox(P);
+  if (rc) return rc;
+  const int reach = (int)ceil(rmax / P->cell_size);
+  if (reach > 4) return fail(RBF_ERR_INVALID, "sweep radius exceeds four hash cells");
+  hipStream_t s = P->stream;
+  DevTmp<double> radii;
+  DevTmp<int32_t> counts, blk;
+  HIPCHK(radii.alloc(n_radii));
+  HIPCHK(counts.alloc(P->m * n_radii));
+  HIPCHK(blk.alloc(P->m));
+  HIPCHK(hipMemcpyAsync(radii.p, radii_h, sizeof(double) * n_radii, hipMemcpyHostToDevice, s));
+  HIPCHK(rbf::launch_density_counts(P->view(), radii.p, n_radii, reach, counts.p, s));
+  HIPCHK(rbf::launch_centre_blocks(P->ctr, P->m, P->dim, P->cbox_dev, blocks_per_dim, blk.p, s));
+  HIPCHK(rbf::launch_block_features(counts.p, blk.p, P->m, n_radii, nblocks, feats, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBF_OK;
+}
+
+int rbf_block_sq_err(rbf_plan* P, int64_t n_query, const double* queries, const double* f,
+                     const double* h, int32_t blocks_per_dim, double* sums_h, int64_t* counts_h) {
+  if (!P || !sums_h || !counts_h) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (n_query < 0 || (n_query > 0 && (!queries || !f || !h)))
+    return fail(RBF_ERR_INVALID, "bad queries");
+  int nblocks = 0;
+  int rc = check_blocks(P, blocks_per_dim, &nblocks);
+  if (rc) return rc;
+  rc = ensure_cbox(P);
+  if (rc) return rc;
+  hipStream_t s = P->stream;
+  DevTmp<double> sums;
+  DevTmp<int64_t> counts;
+  HIPCHK(sums.alloc(nblocks));
+  HIPCHK(counts.alloc(nblocks));
+  HIPCHK(rbf::launch_block_sq_err(queries, n_query, P->dim, f, h, P->cbox_dev, blocks_per_dim,
+                                  nblocks, sums.p, counts.p, s));
+  HIPCHK(hipMemcpyAsync(sums_h, sums.p, sizeof(double) * nblocks, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(counts_h, counts.p, sizeof(int64_t) * nblocks, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBF_OK;
+}
+
+int rbf_radius_broadcast(rbf_plan* P, const float* pred_log, int32_t blocks_per_dim,
+                         double spacing, double rho_min, double rho_max, double rho_fallback,
+                         double* rho_out) {
+  if (!P || !pred_log || !rho_out) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (!(spacing > 0.0) || !(rho_min > 0.0) || !(rho_max >= rho_min) || !(rho_fallback > 0.0))
+    return fail(RBF_ERR_INVALID, "bad radius bounds");
+  int nblocks = 0;
+  int rc = check_blocks(P, blocks_per_dim, &nblocks);
+  if (rc) return rc;
+  rc = ensure_cbox(P);
+  if (rc) return rc;
+  hipStream_t s = P->stream;
+  DevTmp<int32_t> blk;
+  HIPCHK(blk.alloc(P->m));
+  HIPCHK(rbf::launch_centre_blocks(P->ctr, P->m, P->dim, P->cbox_dev, blocks_per_dim, blk.p, s));
+  HIPCHK(rbf::launch_radius_broadcast(pred_log, blk.p, P->m, spacing, rho_min, rho_max,
+                                      rho_fallback, rho_out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return RBF_OK;
+}
+
+int rbf_mlp_create(const float* params_h, void* stream, rbf_mlp** out) {
+  if (!out || !params_h) return fail(RBF_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  rbf_mlp* M = new rbf_mlp();
+  M->stream = (hipStream_t)stream;
+  const size_t bytes = sizeof(float) * rbf::kMlpParams;
+  if (hipMalloc(&M->params, bytes) != hipSuccess || hipMalloc(&M->m1, bytes) != hipSuccess ||
+      hipMalloc(&M->m2, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete M;
+    return fail(RBF_ERR_OOM, "MLP allocation failed");
+  }
+  hipError_t e = hipMemcpyAsync(M->params, params_h, bytes, hipMemcpyHostToDevice, M->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(M->m1, 0, bytes, M->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(M->m2, 0, bytes, M->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+  if (e != hipSuccess) {
+    delete M;
+    return fail(RBF_ERR_HIP, "MLP set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = M;
+  return RBF_OK;
+}
+
+int rbf_mlp_params(const rbf_mlp* M, float* params_h) {
+  if (!M || !params_h) return fail(RBF_ERR_INVALID, "NULL argument");
+  HIPCHK(hipMemcpyAsync(params_h, M->params, sizeof(float) * rbf::kMlpParams,
+                        hipMemcpyDeviceToHost, M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  return RBF_OK;
+}
+
+int rbf_mlp_grad(rbf_mlp* M, const float* x, const float* y, int64_t n, float* grad_h,
+                 float* loss_h) {
+  if (!M || !x || !y || !grad_h || !loss_h) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (n < 1) return fail(RBF_ERR_INVALID, "n must be >= 1");
+  DevTmp<float> g;
+  HIPCHK(g.alloc(rbf::kMlpParams + 1));
+  HIPCHK(rbf::launch_mlp_grad(M->params, x, y, n, g.p, g.p + rbf::kMlpParams, M->stream));
+  HIPCHK(hipMemcpyAsync(grad_h, g.p, sizeof(float) * rbf::kMlpParams, hipMemcpyDeviceToHost,
+                        M->stream));
+  HIPCHK(hipMemcpyAsync(loss_h, g.p + rbf::kMlpParams, sizeof(float), hipMemcpyDeviceToHost,
+                        M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  return RBF_OK;
+}
+
+int rbf_mlp_train(rbf_mlp* M, const float* x, const float* y, int64_t n_rows,
+                  const int32_t* order, int32_t steps, int32_t batch, float lr, float* losses_h) {
+  if (!M || !x || !y || !order) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (n_rows < 1 || steps < 0 || batch < 1 || batch > 4096 || !(lr > 0.0f))
+    return fail(RBF_ERR_INVALID, "bad training arguments");
+  if (steps == 0) return RBF_OK;
+  const int64_t total = (int64_t)steps * batch;
+  // every row index is read by the kernel: check them on the host first
+  std::vector<int32_t> ord(total);
+  HIPCHK(hipMemcpyAsync(ord.data(), order, sizeof(int32_t) * total, hipMemcpyDeviceToHost,
+                        M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  for (int64_t k = 0; k < total; ++k)
+    if (ord[k] < 0 || ord[k] >= n_rows) return fail(RBF_ERR_INVALID, "order index out of range");
+  DevTmp<float> losses;
+  HIPCHK(losses.alloc(steps));
+  HIPCHK(rbf::launch_mlp_train(M->params, M->m1, M->m2, x, y, order, steps, batch, lr,
+                               (int)M->t, losses.p, M->stream));
+  M->t += steps;
+  if (losses_h)
+    HIPCHK(hipMemcpyAsync(losses_h, losses.p, sizeof(float) * steps, hipMemcpyDeviceToHost,
+                          M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  return RBF_OK;
+}
+
+int rbf_mlp_infer_bf16(const rbf_mlp* M, const float* x, int64_t n, float* out) {
+  if (!M || (n > 0 && (!x || !out))) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (n < 0) return fail(RBF_ERR_INVALID, "n < 0");
+  HIPCHK(rbf::launch_mlp_infer_bf16(M->params, x, n, out, M->stream));
+  return RBF_OK;
+}
+
+void rbf_mlp_destroy(rbf_mlp* M) { delete M; }
 
 }  // extern "C"

@@ -22,6 +22,8 @@
 // float32 for the mixed path); every dot product is accumulated in float64.
 // The solution is kept in float64; at a reliable update the float64 residual
 // g - (B + lambda I) x is recomputed and replaces the iterated one.
+#include <hip/hip_ext.h>
+
 #include "plan_kernels.h"
 #include "solver.h"
 
@@ -362,11 +364,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t m, const double* __r
 
 template <typename VT, typename XT, typename CT, int L>
 void launch_spmv_l(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m, A,
-                     (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1], a.q, a.sc,
-                     (const double*)a.part_upd, a.update_blocks, a.part_spmv, parity,
-                     fixed_beta);
+                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+  if (e0) {
+    // the extended launch stamps the events at the kernel's own start and end
+    hipExtLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, e0,
+                          e1, 0, a.m, A, (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1],
+                          a.q, a.sc, (const double*)a.part_upd, a.update_blocks, a.part_spmv,
+                          parity, fixed_beta);
+  } else {
+    hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
+                       A, (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1], a.q, a.sc,
+                       (const double*)a.part_upd, a.update_blocks, a.part_spmv, parity,
+                       fixed_beta);
+  }
 }
 
 template <typename VT, typename XT, typename CT, int L>
@@ -403,11 +413,11 @@ namespace {
 
 template <typename VT, typename XT, typename CT>
 void spmv_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipStream_t s) {
+                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
   switch (A.lanes) {
-    case 2: launch_spmv_l<VT, XT, CT, 2>(a, A, parity, fixed_beta, s); break;
-    case 4: launch_spmv_l<VT, XT, CT, 4>(a, A, parity, fixed_beta, s); break;
-    default: launch_spmv_l<VT, XT, CT, 8>(a, A, parity, fixed_beta, s); break;
+    case 2: launch_spmv_l<VT, XT, CT, 2>(a, A, parity, fixed_beta, e0, e1, s); break;
+    case 4: launch_spmv_l<VT, XT, CT, 4>(a, A, parity, fixed_beta, e0, e1, s); break;
+    default: launch_spmv_l<VT, XT, CT, 8>(a, A, parity, fixed_beta, e0, e1, s); break;
   }
 }
 
@@ -424,12 +434,12 @@ void residual_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, 
 
 template <typename VT, typename XT>
 hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipStream_t s) {
+                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
   if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
   if (A.col16)
-    spmv_dispatch<VT, XT, int16_t>(a, A, parity, fixed_beta, s);
+    spmv_dispatch<VT, XT, int16_t>(a, A, parity, fixed_beta, e0, e1, s);
   else
-    spmv_dispatch<VT, XT, int32_t>(a, A, parity, fixed_beta, s);
+    spmv_dispatch<VT, XT, int32_t>(a, A, parity, fixed_beta, e0, e1, s);
   return hipGetLastError();
 }
 
@@ -474,9 +484,9 @@ hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g,
 }
 
 template hipError_t cg_spmv<double, double>(const CgArgs<double>&, const CgMatrix&, int, int,
-                                            hipStream_t);
+                                            hipEvent_t, hipEvent_t, hipStream_t);
 template hipError_t cg_spmv<float, float>(const CgArgs<float>&, const CgMatrix&, int, int,
-                                          hipStream_t);
+                                          hipEvent_t, hipEvent_t, hipStream_t);
 template hipError_t cg_update<double>(const CgArgs<double>&, int, hipStream_t);
 template hipError_t cg_update<float>(const CgArgs<float>&, int, hipStream_t);
 template hipError_t cg_true_residual<double, double>(const CgArgs<double>&, const CgMatrix&,

@@ -73,10 +73,11 @@ int cg_update_blocks(int64_t m);
 
 // Iteration k = cg_spmv(parity = k & 1) then cg_update(parity).  fixed_beta:
 // the spmv takes beta from the last float64 residual (first iteration after
-// set-up or a reliable update).
+// set-up or a reliable update).  With e0/e1 (may be null) the launch stamps
+// the two events at the kernel's start and end.
 template <typename VT, typename XT>
 hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipStream_t s);
+                   hipEvent_t e0, hipEvent_t e1, hipStream_t s);
 template <typename XT>
 hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s);
 // x_hi += x_lo; float64 residual; r, z from it; scalars for the next spmv.
