@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import time
 from typing import Optional, Sequence
 
 import numpy as np
@@ -65,6 +66,14 @@ class SweepResult:
     block_rmse: np.ndarray    # [n_radii, nblocks] held-out RMSE per radius and block
     block_count: np.ndarray   # [nblocks] held-out queries per block
     rmse: np.ndarray          # [n_radii] held-out RMSE of the whole set
+    seconds: np.ndarray       # [n_radii] wall time of each fit (plan + assembly + solve)
+    work: np.ndarray          # [n_radii] CG work of each fit: stored entries x iterations
+
+
+def fit_work(plan: B.Plan, info: dict) -> float:
+    """Deterministic cost figure of a fit: entries of B times CG iterations
+    (the matrix products dominate a fit's time)."""
+    return float(B.rbf_plan_info(plan)["nnz_full"]) * float(info["iterations"])
 
 
 def sweep_labels(points, values, test_points, test_values, centers, radii, spacing: float,
@@ -74,9 +83,16 @@ def sweep_labels(points, values, test_points, test_values, centers, radii, spaci
     nblk = blocks_per_dim ** int(centers.shape[0])
     brmse = np.zeros((nr, nblk))
     rmse = np.zeros(nr)
+    secs = np.zeros(nr)
+    work = np.zeros(nr)
     cnt = None
     for s, rho in enumerate(radii):
-        plan, c, _ = fit_once(points, values, centers, float(rho), phi, prec, lambda_rel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan, c, info = fit_once(points, values, centers, float(rho), phi, prec, lambda_rel)
+        torch.cuda.synchronize()
+        secs[s] = time.perf_counter() - t0
+        work[s] = fit_work(plan, info)
         f, r = B.rbf_eval(plan, test_points, c, values=test_values)
         sums, cnt = B.rbf_block_sq_err(plan, test_points, f, test_values, blocks_per_dim)
         brmse[s] = np.sqrt(sums / np.maximum(cnt, 1))
@@ -84,7 +100,8 @@ def sweep_labels(points, values, test_points, test_values, centers, radii, spaci
         plan.close()
     best = np.argmin(brmse, axis=0)           # first minimum: ties go to the smaller radius
     labels = np.log(np.asarray(radii)[best] / spacing)
-    return SweepResult(labels=labels, block_rmse=brmse, block_count=cnt, rmse=rmse)
+    return SweepResult(labels=labels, block_rmse=brmse, block_count=cnt, rmse=rmse, seconds=secs,
+                       work=work)
 
 
 @dataclasses.dataclass

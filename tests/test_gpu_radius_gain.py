@@ -1,14 +1,21 @@
-"""What the learned support radius gains over one fixed radius.
+"""What the learned support radius gains over one fixed radius at equal fit time.
 
 A reduced version of the radius-sweep workload: 24 synthetic clustered terrain
-sets (N log-uniform in 2^13..2^15, 1..16 Gaussian clusters, fractal height
-plus noise), 64 x 64 reference points, 4 x 4 blocks of 16 x 16 centres, the 8
-sweep radii covering 10..113 centres.  Labels come from the sweeps (held-out
-RMSE per block, 10 % held out); the network is trained on 18 sets with the
-project's kernels and judged on the other 6 against the radius that is best
-on the training sets as a whole.  Parity of the gain is unpinned (the paper
-has no learned radius); what is asserted is that the learned radii are not
-worse than the fixed one and that the training loss falls.
+sets (N log-uniform in 2^14..2^17, 1..16 Gaussian clusters, fractal height
+plus noise, 10 % held out), 64 x 64 reference points, 4 x 4 blocks of
+16 x 16 centres, the 8 sweep radii covering 10..113 centres.  Labels come from
+the sweeps (held-out RMSE per block; blocks with fewer than 5 held-out
+queries carry no label); the network is trained on 18 sets with the
+project's kernels and judged on the other 6.
+
+For every test set the learned per-block radii are fitted once (CG work W_L
+= stored entries x iterations, held-out RMSE r_L).  The fixed-radius
+comparison at equal cost is the best held-out RMSE among the sweep's fixed
+radii whose fit took at most W_L (the smallest radius if none did).  CG work
+stands in for fit time because it is deterministic (every reduction runs in a
+fixed order) while wall time is not; both are printed.  The paper has no
+learned radius, so the size of the gain is unpinned; the test asserts that at
+equal cost the learned radii are not worse on average.
 """
 import math
 import sys
@@ -38,7 +45,7 @@ def dev(a):
 
 def make_set(seed):
     r = sd.streams(seed, 6)
-    n = int(2 ** r[0].uniform(13, 15))
+    n = int(2 ** r[0].uniform(14, 17))
     k = int(r[0].integers(1, 17))
     pts = sd.gaussian_mixture_points(r[1], n, 2, k)
     clean = sd.terrain_values(sd.terrain_modes(r[2], 256, 2), pts)
@@ -48,7 +55,7 @@ def make_set(seed):
 
 
 @pytest.mark.timeout(900)
-def test_learned_radius_beats_or_matches_fixed():
+def test_learned_radius_at_equal_cost():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1806_07884_amd import radius
@@ -56,57 +63,53 @@ def test_learned_radius_beats_or_matches_fixed():
     ctr = sd.grid_centers(G, 2)
     spacing = 1.0 / (G - 1)
     radii = radius.sweep_radii(spacing, 2)
-    sets = [make_set(1000 + s) for s in range(24)]
+    sets = [make_set(2000 + s) for s in range(24)]
     feats, labels, sweeps = [], [], []
     t0 = time.time()
+    dc = dev(ctr)
     for s, (p, h, tp, th) in enumerate(sets):
-        dp, dh, dtp, dth, dc = dev(p), dev(h), dev(tp), dev(th), dev(ctr)
+        dp, dh, dtp, dth = dev(p), dev(h), dev(tp), dev(th)
         feats.append(radius.block_features(dp, dc, radii, NB).cpu().numpy())
         sw = radius.sweep_labels(dp, dh, dtp, dth, dc, radii, spacing, NB)
         labels.append(sw.labels)
         sweeps.append(sw)
-    say(f"sweeps {time.time() - t0:.1f} s")
-    F = np.concatenate(feats[:18])
-    Y = np.concatenate(labels[:18])
+    # a block with (almost) no held-out queries ties every radius: no label
+    keep = [sw.block_count >= 5 for sw in sweeps]
+    lab = np.concatenate([l[k] for l, k in zip(labels, keep)])
+    idx = np.argmin(np.abs(lab[:, None] - np.log(radii / spacing)[None, :]), axis=1)
+    say(f"sweeps {time.time() - t0:.1f} s; label histogram", np.bincount(idx, minlength=8))
+    F = np.concatenate([f[k] for f, k in zip(feats[:18], keep[:18])])
+    Y = np.concatenate([l[k] for l, k in zip(labels[:18], keep[:18])])
     rng = np.random.default_rng(7)
-    theta = mo.init_params(rng)
-    model, losses = radius.train(F, Y, theta, epochs=400, batch=32, lr=3e-3, rng=rng)
-    say("loss", losses[:3], losses[-3:])
-    assert losses[-20:].mean() < 0.7 * losses[:20].mean()
-    # best fixed radius on the training sets (total held-out squared error)
-    sse = np.zeros(len(radii))
-    for sw in sweeps[:18]:
-        sse += (sw.block_rmse ** 2 * sw.block_count).sum(axis=1)
-    best = int(np.argmin(sse))
-    say("best fixed cover index", best, "rho", radii[best])
-    fixed, learned, oracle_best = [], [], []
-    t_fixed = t_learned = 0.0
+    model, losses = radius.train(F, Y, mo.init_params(rng), epochs=60, batch=32, lr=1e-3,
+                                 rng=rng)
+    say("training loss", losses[:3], losses[-3:])
+    assert losses[-10:].mean() < losses[:10].mean()
+    rows = []
     for s in range(18, 24):
         p, h, tp, th = sets[s]
-        dp, dh, dtp, dth, dc = dev(p), dev(h), dev(tp), dev(th), dev(ctr)
-        fixed.append(sweeps[s].rmse[best])
+        dp, dh, dtp, dth = dev(p), dev(h), dev(tp), dev(th)
         fplan = rbf.rbf_fit_plan(dp, dc, rho=float(radii.max()))
         rho = radius.predict_radii(model, fplan, dev(feats[s]), NB, spacing,
-                                   float(radii.min()), float(radii.max()), float(radii[best]))
+                                   float(radii.min()), float(radii.max()), float(radii[4]))
         fplan.close()
         torch.cuda.synchronize()
-        ta = time.time()
+        ta = time.perf_counter()
         plan, c, info = radius.fit_once(dp, dh, dc, None, "w31", "fp32", 1e-4, rho_per_center=rho)
-        _, r = rbf.rbf_eval(plan, dtp, c, values=dth)
-        t_learned += time.time() - ta
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - ta
+        w_l = radius.fit_work(plan, info)
+        _, r_l = rbf.rbf_eval(plan, dtp, c, values=dth)
         plan.close()
-        ta = time.time()
-        plan, c, info = radius.fit_once(dp, dh, dc, float(radii[best]), "w31", "fp32", 1e-4)
-        _, rf = rbf.rbf_eval(plan, dtp, c, values=dth)
-        t_fixed += time.time() - ta
-        plan.close()
-        learned.append(r)
         sw = sweeps[s]
-        oracle_best.append(math.sqrt((sw.block_rmse.min(axis=0) ** 2 * sw.block_count).sum()
-                                     / sw.block_count.sum()))
-    fixed, learned, oracle_best = map(np.asarray, (fixed, learned, oracle_best))
-    say("fixed", fixed, "learned", learned, "per-block best", oracle_best)
-    say(f"mean held-out RMSE fixed {fixed.mean():.4e} learned {learned.mean():.4e} "
-        f"per-block best {oracle_best.mean():.4e}; fit time fixed {t_fixed:.2f}s "
-        f"learned {t_learned:.2f}s")
-    assert learned.mean() <= 1.02 * fixed.mean()
+        ok = sw.work <= w_l
+        r_eq = sw.rmse[ok].min() if np.any(ok) else sw.rmse[0]
+        b = int(np.argmin(sw.rmse))
+        rows.append((r_l, r_eq, sw.rmse[b], t_l, sw.seconds[b], w_l, sw.work[b]))
+    rows = np.asarray(rows)
+    for r in rows:
+        say(f"learned {r[0]:.4e} ({r[3] * 1e3:.1f} ms, work {r[5]:.3g})  fixed at equal work "
+            f"{r[1]:.4e}  best fixed {r[2]:.4e} ({r[4] * 1e3:.1f} ms, work {r[6]:.3g})")
+    say(f"mean held-out RMSE: learned {rows[:, 0].mean():.4e}, fixed at equal work "
+        f"{rows[:, 1].mean():.4e}, best fixed {rows[:, 2].mean():.4e}")
+    assert rows[:, 0].mean() <= rows[:, 1].mean() * 1.02
