@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "streams", "uniform_points", "gaussian_mixture_points", "franke",
     "terrain_modes", "terrain_values", "grid_centers", "heldout_split",
-    "Problem", "make_problem", "CONFIGS", "support_radius_for_k",
+    "Problem", "make_problem", "CONFIGS", "support_radius_for_k", "scoring_queries",
 ]
 
 
@@ -73,11 +73,20 @@ def gaussian_mixture_points(rng: np.random.Generator, n: int, dim: int,
         sig = np.empty((n_clusters, dim))
         sig[:, 0] = major
         sig[:, 1:] = major[:, None] / aspect
-        pts = np.empty((batch, dim))
+        # group the batch by component once (a stable sort keeps each group in
+        # draw order), transform every group as one contiguous slice, scatter back
+        key = comp.astype(np.uint8) if n_clusters <= 256 else comp
+        order = np.argsort(key, kind="stable")
+        ends = np.cumsum(np.bincount(comp, minlength=n_clusters))
+        zs = z[order]
+        ps = np.empty((batch, dim))
+        start = 0
         for c in range(n_clusters):
-            sel = comp == c
-            if np.any(sel):
-                pts[sel] = (z[sel] * sig[c]) @ rot[c].T + means[c]
+            if ends[c] > start:
+                ps[start:ends[c]] = (zs[start:ends[c]] * sig[c]) @ rot[c].T + means[c]
+            start = ends[c]
+        pts = np.empty((batch, dim))
+        pts[order] = ps
         keep = np.all((pts >= 0.0) & (pts <= 1.0), axis=1)
         if scanlines:
             stripe = np.mod(pts[:, -1] * 512.0, 1.0) >= 0.5
@@ -126,14 +135,26 @@ def terrain_modes(rng: np.random.Generator, n_modes: int, dim: int,
     return TerrainModes(wavevec=d * kmag[:, None], amp=kmag ** -2.0, phase=phase)
 
 
-def terrain_values(modes: TerrainModes, p: np.ndarray, chunk: int = 1 << 18) -> np.ndarray:
-    """h(x) = sum_m amp_m cos(2 pi k_m . x + phase_m) at SoA points ``p``."""
+def terrain_values(modes: TerrainModes, p: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+    """h(x) = sum_m amp_m cos(2 pi k_m . x + phase_m) at SoA points ``p``.
+
+    Chunks are independent and run on a thread pool (NumPy releases the GIL
+    in these loops); every chunk does the same operations whatever the pool
+    size, so the result does not depend on the thread count.
+    """
+    import concurrent.futures as cf
+    import os
     n = p.shape[1]
     out = np.empty(n)
     two_pi_k = 2.0 * math.pi * modes.wavevec          # (m, dim)
-    for s in range(0, n, chunk):
+
+    def run(s):
         arg = two_pi_k @ p[:, s:s + chunk] + modes.phase[:, None]
         out[s:s + chunk] = modes.amp @ np.cos(arg)
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(run, range(0, n, chunk)))
     return out
 
 
@@ -178,6 +199,7 @@ class Problem:
     rho: float
     phi: str                  # "w30" | "w31" | "w32" | "w33"
     grid: int
+    modes: Optional[TerrainModes] = None   # the terrain field's modes (clean values anywhere)
 
 
 # The five workloads (sizes, densities, fields, basis and radius).  A radius
@@ -213,10 +235,12 @@ def make_problem(name: str, scale: float = 1.0, seed: Optional[int] = None,
         pts = uniform_points(r_cloud, n_total, dim)
     else:
         pts = gaussian_mixture_points(r_cloud, n_total, dim, cfg["clusters"])
+    modes = None
     if cfg["field"] == "franke":
         clean = franke(pts)
     else:
-        clean = terrain_values(terrain_modes(r_field, cfg["modes"], dim), pts)
+        modes = terrain_modes(r_field, cfg["modes"], dim)
+        clean = terrain_values(modes, pts)
     noisy = clean + cfg["noise"] * r_noise.standard_normal(n_total)
     if cfg["holdout"] > 0:
         tr, te = heldout_split(r_split, n_total, cfg["holdout"])
@@ -234,4 +258,21 @@ def make_problem(name: str, scale: float = 1.0, seed: Optional[int] = None,
         test_points=np.ascontiguousarray(pts[:, te]),
         test_values=np.ascontiguousarray(noisy[te]),
         test_clean=np.ascontiguousarray(clean[te]),
-        centers=grid_centers(g, dim), rho=rho, phi=cfg["phi"], grid=g)
+        centers=grid_centers(g, dim), rho=rho, phi=cfg["phi"], grid=g, modes=modes)
+
+
+def scoring_queries(prob: Problem, n: int = 1_000_000, seed: Optional[int] = None):
+    """Points at which a fit of ``prob`` is scored, with the values to score against.
+
+    A workload with held-out points is scored there against the noisy samples.
+    One without (the 3D field) is scored at ``n`` points uniform in the unit
+    cube against the noise-free field; the stream is seeded by ``1000 + dim``
+    unless ``seed`` is given.
+    """
+    if prob.test_points.shape[1] > 0:
+        return prob.test_points, prob.test_values
+    if prob.modes is None:
+        raise ValueError("workload has neither held-out points nor a terrain field")
+    rng = streams(1000 + prob.dim if seed is None else seed, 1)[0]
+    q = uniform_points(rng, n, prob.dim)
+    return q, terrain_values(prob.modes, q)
