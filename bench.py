@@ -44,22 +44,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int) -> int:
-    """Algorithmic HBM bytes of one CG SpMV launch: every nonzero of B once
-    (value and column index, padding excluded) and four length-M vectors
-    (z and p_old read, p_new and q written)."""
-    return nnz_full * (val_bytes + col_bytes) + 4 * m * vec_bytes
+def iter_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int) -> int:
+    """Algorithmic HBM bytes of one CG iteration launch: every nonzero of B
+    once (value and column index, padding excluded) and, per row, its state
+    record (r, w, s, d) read and written plus p and x read and written."""
+    return nnz_full * (val_bytes + col_bytes) + 12 * m * vec_bytes
 
 
 def kernel_digest() -> str:
-    """Digest of the SpMV kernel's source (its device code and layout struct)."""
+    """Digest of the CG iteration kernel's source (its device code and layouts)."""
     csrc = os.path.join(ROOT, "paper_1806_07884_amd", "csrc")
     src = open(os.path.join(csrc, "cg_kernels.hip")).read()
-    a = src.index("// For the slice of S = 64 / L rows owned by this wave")
-    b = src.index("template <typename XT>\n__global__ __launch_bounds__(kBlock) void k_cg_update(")
+    a = src.index("// Row sum over one slice of the wave")
+    b = src.index("// x_hi += x_lo; x_lo = 0")
     hdr = open(os.path.join(csrc, "solver.h")).read()
-    c = hdr.index("struct CgMatrix {")
-    d = hdr.index("};", c)
+    c = hdr.index("template <typename XT>\nstruct alignas")
+    d = hdr.index("__host__ __device__ inline int64_t sell_pos")
     return hashlib.sha256((src[a:b] + hdr[c:d]).encode()).hexdigest()[:16]
 
 
@@ -156,7 +156,7 @@ def main() -> int:
         spmv_n, spmv_ms, asm_ms = 0, 0.0, 0.0
         for _ in range(steps):
             plan, info, rmse = fit(prec, profile=True)
-            n, ms = rbf.rbf_profile_read(plan, "spmv")
+            n, ms = rbf.rbf_profile_read(plan, "cg_iter")
             _, ams = rbf.rbf_profile_read(plan, "assemble")
             spmv_n += n
             spmv_ms += ms
@@ -168,7 +168,7 @@ def main() -> int:
         dt = (time.perf_counter() - t0) / steps
         avg = spmv_ms / max(spmv_n, 1) * 1e3
         log(f"{prec}: {dt * 1e3:.1f} ms/fit, iters {per[-1][0]['iterations']}, "
-            f"rmse {per[-1][1]:.6e}, spmv kernel {avg:.2f} us")
+            f"rmse {per[-1][1]:.6e}, cg iteration kernel {avg:.2f} us")
         return dt, per, stats, spmv_n, avg, asm_ms / steps
 
     steps = max(1, args.steps)
@@ -181,10 +181,10 @@ def main() -> int:
     nnz, m, cb = stats["nnz_full"], stats["n_centers"], stats["solver_col_bytes"]
     # kernel time from start/stop events of sampled launches on the plan's stream
     kern32 = max(avg32, 1e-3) * 1e-6
-    bytes32 = spmv_bytes(nnz, m, 4, cb, 4)
+    bytes32 = iter_bytes(nnz, m, 4, cb, 4)
     achieved = bytes32 / kern32
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"spmv_fp32_{wl}_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"cg_iter_fp32_{wl}_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             t = json.load(fh)
@@ -192,11 +192,11 @@ def main() -> int:
             traffic = t.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "kernel": "k_cg_spmv<float,float,int16,L>", "bytes_per_launch": bytes32,
+                "kernel": "k_cg_iter<float,float,int16,L>", "bytes_per_launch": bytes32,
                 "avg_kernel_us": kern32 * 1e6, "timed_launches": n32,
                 "solver_entries": stats["solver_entries"], "solver_lanes": stats["solver_lanes"]}
     kern64 = max(avg64, 1e-3) * 1e-6
-    b64 = spmv_bytes(nnz, m, 8, cb, 8)
+    b64 = iter_bytes(nnz, m, 8, cb, 8)
 
     cpu = None
     if not args.no_cpu_baseline and wl == "terrain2d":
@@ -222,8 +222,8 @@ def main() -> int:
         "fp64": {"value": n_train / dt64, "ms_per_fit": dt64 * 1e3,
                  "iterations": per64[-1][0]["iterations"],
                  "rel_residual": per64[-1][0]["rel_residual"], "scoring_rmse": rmse64,
-                 "assembly_ms": asm64, "spmv_kernel_us": kern64 * 1e6,
-                 "spmv_gbps": b64 / kern64 / 1e9},
+                 "assembly_ms": asm64, "cg_iter_kernel_us": kern64 * 1e6,
+                 "cg_iter_gbps": b64 / kern64 / 1e9},
         "speedup_mixed_vs_fp64": dt64 / dt32,
         "rmse_matched": bool(matched),
         "scoring": (f"{q.shape[1]} held-out points vs noisy samples" if prob.test_points.shape[1]

@@ -184,14 +184,14 @@ int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
 
 /* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
  * starts timing, with HIP events on the plan's stream, the assembly launch
- * (events recorded around it) and every fourth CG matrix-vector launch
+ * (events recorded around it) and every fourth CG iteration launch
  * (events stamped at the kernel's own start and end by the extended launch;
  * launches that returned at entry after convergence are not counted);
  * rbf_profile(plan, 0) stops.
  * rbf_profile_read returns the number of timed launches of `kernel` and their
  * summed duration in milliseconds.  Both block the host (stream sync).
  * Kernel ids: */
-#define RBF_KERNEL_SPMV 0      /* CG: p update, q = (B + lambda I) p, p . q */
+#define RBF_KERNEL_CG_ITER 0   /* one CG iteration: vector updates, w = B D^-1 r, dot products */
 #define RBF_KERNEL_ASSEMBLE 2  /* numeric assembly of B and g */
 int rbf_profile(rbf_plan* plan, int32_t enable);
 int rbf_profile_read(rbf_plan* plan, int32_t kernel, int64_t* launches, double* total_ms);

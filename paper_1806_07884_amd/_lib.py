@@ -21,7 +21,7 @@ RBF_ERR_BREAKDOWN = -4
 RBF_ERR_HIP = -5
 RBF_ERR_OOM = -6
 
-KERNEL = {"spmv": 0, "assemble": 2}
+KERNEL = {"cg_iter": 0, "assemble": 2}
 MLP_PARAMS = 5313
 MLP_INPUTS = 16
 MAX_RADII = 8

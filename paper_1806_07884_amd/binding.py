@@ -187,13 +187,13 @@ def rbf_eval(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
 
 
 def rbf_profile(plan: Plan, enable: bool) -> None:
-    """Start (reset) or stop event timing of the assembly and CG SpMV launches."""
+    """Start (reset) or stop event timing of the assembly and CG iteration launches."""
     with torch.cuda.device(plan.device):
         L.check(L.lib().rbf_profile(plan.handle, int(bool(enable))), "rbf_profile")
 
 
 def rbf_profile_read(plan: Plan, kernel: str):
-    """(timed launches, summed milliseconds) of 'spmv' or 'assemble'."""
+    """(timed launches, summed milliseconds) of 'cg_iter' or 'assemble'."""
     n = ctypes.c_int64()
     ms = ctypes.c_double()
     with torch.cuda.device(plan.device):

@@ -101,10 +101,10 @@ struct rbf_plan {
   double* xhi = nullptr;
   double* r64 = nullptr;
   rbf::CgScalars* sc = nullptr;
-  double* part_spmv = nullptr;
-  double* part_upd = nullptr;
-  void* vec64[6] = {};
-  void* vec32[6] = {};
+  double* part_it = nullptr;   // [2][6 * kCgMaxBlocks] partials of the iterations
+  double* part_ref = nullptr;  // [6 * kCgMaxBlocks] partials of a refresh
+  void* vec64[4] = {};         // state buffers 0 and 1 (4 per row), p, x_lo
+  void* vec32[4] = {};
   double* cs_sorted = nullptr;
   double* eval_part = nullptr;
   rbf::CgScalars* host_sc = nullptr;  // pinned
@@ -396,7 +396,7 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   P->release(marks);
   if (total >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "solver layout exceeds 2^31 entries");
   P->nsell = total;
-  const size_t cbytes = (size_t)std::max<int64_t>(total, 1) * (P->col16 ? 2 : 4);
+  const size_t cbytes = (size_t)(total + rbf::kSellTail) * (P->col16 ? 2 : 4);
   P->scol = P->alloc_bytes(cbytes);
   if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
   HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
@@ -408,20 +408,18 @@ template <typename XT>
 rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   rbf::CgArgs<XT> a;
   a.m = P->m;
-  a.p[0] = (XT*)vec[0];
-  a.p[1] = (XT*)vec[1];
-  a.q = (XT*)vec[2];
-  a.r = (XT*)vec[3];
-  a.z = (XT*)vec[4];
-  a.xlo = (XT*)vec[5];
+  a.st[0] = (rbf::CgState<XT>*)vec[0];
+  a.st[1] = (rbf::CgState<XT>*)vec[1];
+  a.p = (XT*)vec[2];
+  a.xlo = (XT*)vec[3];
   a.dinv = dinv;
   a.xhi = P->xhi;
   a.r64 = P->r64;
   a.sc = P->sc;
-  a.part_spmv = P->part_spmv;
-  a.part_upd = P->part_upd;
-  a.spmv_blocks = rbf::cg_grid_blocks(P->nslices);
-  a.update_blocks = rbf::cg_update_blocks(P->m);
+  a.part[0] = P->part_it;
+  a.part[1] = P->part_it + 6 * rbf::kCgMaxBlocks;
+  a.part_ref = P->part_ref;
+  rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
   return a;
 }
 
@@ -431,14 +429,15 @@ int ensure_solver(rbf_plan* P, bool fp32) {
     GET(P->xhi, m);
     GET(P->r64, m);
     GET(P->sc, 1);
-    GET(P->part_spmv, rbf::kCgMaxBlocks);
-    GET(P->part_upd, 2 * rbf::kCgMaxBlocks);
+    GET(P->part_it, 12 * rbf::kCgMaxBlocks);
+    GET(P->part_ref, 6 * rbf::kCgMaxBlocks);
   }
   void** vec = fp32 ? P->vec32 : P->vec64;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
-  for (int k = 0; k < 6; ++k) {
+  const size_t per_row[4] = {4, 4, 1, 1};
+  for (int k = 0; k < 4; ++k) {
     if (!vec[k]) {
-      vec[k] = P->alloc_bytes(es * (size_t)m);
+      vec[k] = P->alloc_bytes(per_row[k] * es * (size_t)m);
       if (!vec[k]) return fail(RBF_ERR_OOM, "solver vector allocation failed");
     }
   }
@@ -459,16 +458,18 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   hipStream_t s = P->stream;
   rbf::PlanView v = P->view();
   // padding entries of the sliced-ELL layout are never written: zero them once
+  // (and the zeroed tail the CG kernels' batched loads may reach)
+  const int64_t nv = P->nsell + rbf::kSellTail;
   if (fp32) {
     if (!P->val32) {
-      GET(P->val32, P->nsell);
-      HIPCHK(hipMemsetAsync(P->val32, 0, sizeof(float) * std::max<int64_t>(P->nsell, 1), s));
+      GET(P->val32, nv);
+      HIPCHK(hipMemsetAsync(P->val32, 0, sizeof(float) * nv, s));
     }
     if (!P->dinv32) GET(P->dinv32, P->m);
   } else {
     if (!P->val64) {
-      GET(P->val64, P->nsell);
-      HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * std::max<int64_t>(P->nsell, 1), s));
+      GET(P->val64, nv);
+      HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * nv, s));
     }
   }
   void* val = fp32 ? (void*)P->val32 : (void*)P->val64;
@@ -508,9 +509,12 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   A.val = val;
   A.lanes = P->lanes;
   HIPCHK(rbf::cg_setup<XT>(a, P->active, P->g, o.rtol, o.reliable_delta, s));
-  HIPCHK(rbf::cg_true_residual<VT, XT>(a, A, P->g, 1, 0, s));
+  // start: float64 residual of the initial x on state buffer 0, direction reset
+  HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, 0, 1, 1, s));
+  // every refresh moves the state to the other buffer, as every iteration does
+  int64_t refreshes = 1;
   const int64_t base_iter = *iters;
-  bool fixed_beta = true;  // the next spmv takes beta from the float64 residual
+  bool fixed = true;  // the next iteration takes its scalars from the refresh
   double last_true = -1.0;
   int stalls = 0;
   for (;;) {
@@ -518,9 +522,9 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
     if (rc) return rc;
     const rbf::CgScalars h = *P->host_sc;
     *iters = base_iter + h.iter;
-    // the buffer holding the latest direction follows the executed iteration
+    // the buffer holding the latest state follows the executed iteration
     // count (launches after a raised flag return at entry)
-    const int parity = (int)(h.iter & 1);
+    const int q = (int)((h.iter + refreshes) & 1);
     if (P->prof_on) P->resolve(*iters);
     if (h.done == 3) return RBF_OK;
     if (h.done == 2) return fail(RBF_ERR_BREAKDOWN, "CG breakdown after %lld iterations",
@@ -532,13 +536,14 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
         stalls = 0;
       }
       last_true = h.rr_true;
-      HIPCHK(rbf::cg_true_residual<VT, XT>(a, A, P->g, 0, parity, s));
+      HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, q, q ^ 1, 0, s));
+      ++refreshes;
       *updates += 1;
-      fixed_beta = true;
+      fixed = true;
       continue;
     }
     if (*iters >= o.max_iter) {
-      HIPCHK(rbf::cg_true_residual<VT, XT>(a, A, P->g, 1, parity, s));
+      HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, q, q ^ 1, 1, s));
       rc = read_scalars(P);
       if (rc) return rc;
       return P->host_sc->done == 3 ? RBF_OK : RBF_WARN_MAXITER;
@@ -546,7 +551,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
     const int64_t left = o.max_iter - *iters;
     const int chunk = (int)std::min<int64_t>(left, o.check_every);
     for (int it = 0; it < chunk; ++it) {
-      const int par = (int)((h.iter + it) & 1);
+      const int qi = (int)((h.iter + it + refreshes) & 1);
       // every fourth launch carries start/stop events when timing is on
       const bool timed = P->prof_on && (it & 3) == 0;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -555,11 +560,10 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
         e1 = P->event();
         if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
       }
-      HIPCHK(rbf::cg_spmv<VT, XT>(a, A, par, (fixed_beta && it == 0) ? 1 : 0, e0, e1, s));
+      HIPCHK(rbf::cg_iterate<VT, XT>(a, A, qi, (fixed && it == 0) ? 1 : 0, e0, e1, s));
       if (timed) P->pending.push_back({0, *iters + it, e0, e1});
-      HIPCHK(rbf::cg_update<XT>(a, par, s));
     }
-    fixed_beta = false;
+    fixed = false;
   }
 }
 

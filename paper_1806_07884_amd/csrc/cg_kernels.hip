@@ -1,27 +1,41 @@
-// Jacobi-preconditioned conjugate gradients on the assembled normal equations.
+// Jacobi-preconditioned conjugate gradients on the assembled normal equations,
+// in the single-reduction form of Chronopoulos and Gear (1989), one kernel per
+// iteration.
 //
-// One CG iteration k is two kernels, with every cross-block scalar carried
-// from one kernel to the next through plain per-block partial sums:
+// With u = D^-1 r, w = B u, s = B p and gamma = r . u, delta = w . u, the
+// iteration i (alpha_i, beta_i known) is
 //
-//   spmv(k):   every block reduces the previous update's partials of r.z and
-//              r.r (same fixed order in every block, so all blocks agree),
-//              checks the trigger, forms beta = rz_k / rz_{k-1}, then
-//              p_new = z + beta p_old (on the fly for every column it reads),
-//              q = (B + lambda I) p_new and a partial of p_new . q.
-//   update(k): every block reduces the partials of p . q, forms
-//              alpha = rz_k / (p . q); x += alpha p; r -= alpha q;
-//              z = D^-1 r; partials of r . z and r . r.
+//     p_i     = u_i + beta_i p_{i-1}          s_i = w_i + beta_i s_{i-1}
+//     x_{i+1} = x_i + alpha_i p_i             r_{i+1} = r_i - alpha_i s_i
+//     u_{i+1} = D^-1 r_{i+1}                  w_{i+1} = B u_{i+1}
+//     gamma_{i+1} = r_{i+1} . u_{i+1}         delta_{i+1} = w_{i+1} . u_{i+1}
+//     beta_{i+1}  = gamma_{i+1} / gamma_i
+//     alpha_{i+1} = gamma_{i+1} / (p_{i+1} . s_{i+1}),
+//     p_{i+1} . s_{i+1} = delta_{i+1} + beta_{i+1} (u_{i+1} . s_i + p_i . w_{i+1})
+//                         + beta_{i+1}^2 p_i . s_i
 //
-// Kernel boundaries make the partials of one kernel visible to every block of
-// the next on all XCDs, so no device-scope fence (an L2 write-back per block
-// on this chip) is ever executed.  Scalars the host reads are written by block
-// 0 of each kernel.  Once a flag is raised the remaining launched kernels
-// return at entry.
+// so both scalars come from dot products of one pass.  (The shorter
+// recurrence alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1}
+// gamma_{i+1} / alpha_i) leans on orthogonality that float32 iterates lose:
+// it broke down on the mixed path, the expanded product does not.)  Kernel i
+// reduces the partial sums of gamma_i, delta_i, r_i . r_i and the three
+// products left by kernel i - 1 (every block, same fixed order, so all
+// blocks agree bit for bit), then streams its
+// slices of B once: the u_{i+1} of every column it reads is formed on the fly
+// from that neighbour's (r_i, w_i, s_{i-1}, d) record, one vector gather per
+// stored entry, and the row's own p_i, x_{i+1}, r_{i+1}, s_i are updated in
+// the same pass.  The records are double-buffered (read st[q], write
+// st[q ^ 1]); p and x are touched by their own row only.  No device-scope
+// fence is ever executed: kernel boundaries make one kernel's partials
+// visible to the next on every XCD.
 //
-// Precision: the matrix and the iterated vectors are VT / XT (float64, or
-// float32 for the mixed path); every dot product is accumulated in float64.
-// The solution is kept in float64; at a reliable update the float64 residual
-// g - (B + lambda I) x is recomputed and replaces the iterated one.
+// A reliable update (and the start) replaces r by the float64 residual of the
+// stored system, recomputes w = B D^-1 r and sets alpha, beta of the next
+// iteration from the same expanded product, the direction kept (or reset).
+//
+// Precision: matrix and iterated vectors are VT / XT (float64, or float32
+// for the mixed path); every dot product is a float64 sum of float64
+// products; the solution is accumulated in float64 at every reliable update.
 #include <hip/hip_ext.h>
 
 #include "plan_kernels.h"
@@ -30,46 +44,59 @@
 namespace rbf {
 namespace {
 
-constexpr int kBlock = 256;
+// s_i = w_i + beta s_{i-1} and r_{i+1} = r_i - alpha s_i, rounded step by step
+// so that a row's own update and every neighbour's on-the-fly copy of it are
+// the same numbers.
+template <typename XT>
+__device__ __forceinline__ XT s_next(XT w, XT s, XT beta) {
+#pragma clang fp contract(off)
+  return w + beta * s;
+}
+template <typename XT>
+__device__ __forceinline__ XT r_next(XT r, XT sn, XT alpha) {
+#pragma clang fp contract(off)
+  return r - alpha * sn;
+}
 
-template <typename T, int G>
-__device__ __forceinline__ T group_sum(T v) {
+// Block-wide sums of N doubles per thread in a fixed order.  ALL: every
+// thread gets them (and the call ends with a barrier, so it can be made again
+// right away); otherwise only thread 0 does.
+template <int N, int W, bool ALL = true>
+__device__ __forceinline__ void block_sums(double (&v)[N], double (*ws)[W]) {
+  const int wave = threadIdx.x / kWave;
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-// Block-wide sum of one double per thread in a fixed order; every thread gets it.
-__device__ __forceinline__ double block_sum(double v, double* ws) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
-  __syncthreads();
-  double t = 0.0;
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-  for (int w = 0; w < kBlock / kWave; ++w) t += ws[w];
-  return t;
+    for (int k = 0; k < N; ++k) ws[k][wave] = v[k];
+  }
+  __syncthreads();
+  if (ALL || threadIdx.x == 0) {
+    for (int k = 0; k < N; ++k) {
+      double t = 0.0;
+#pragma unroll 4
+      for (int w = 0; w < W; ++w) t += ws[k][w];
+      v[k] = t;
+    }
+  }
+  if (ALL) __syncthreads();
 }
 
-// Sum of n partials part[stride * k + off], identical in every block.
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int n,
-                                                  int stride, int off, double* ws) {
-  double s = 0.0;
-  for (int k = threadIdx.x; k < n; k += kBlock) s += part[stride * k + off];
-  return block_sum(s, ws);
+// The flag is read once per block and broadcast, so that all waves of a block
+// take the same branch even if block 0 raises it meanwhile.
+__device__ __forceinline__ bool block_done(const CgScalars* sc, int* s_flag) {
+  if (threadIdx.x == 0) *s_flag = sc->done;
+  __syncthreads();
+  return *s_flag != 0;
 }
 
-constexpr int kWavesPerBlock = kBlock / kWave;
-
-// For the slice of S = 64 / L rows owned by this wave, the row sums
-// az = sum_e b_e z[col_e] and ap = sum_e b_e p[col_e], complete in the lane
-// with (lane % L) == 0 of every row.  Four independent loads per lane are in
+// Row sum over one slice of the wave: acc = sum_e b_e f(col_e), with f the
+// gathered quantity of the neighbour, complete in the lane with
+// (lane % L) == 0 of every row.  Four independent loads per lane are in
 // flight per step; rows past m gather from row m - 1 with value 0.
-template <typename VT, typename XT, typename CT, int L>
-__device__ __forceinline__ void slice_products(int64_t m, int64_t slice, const CgMatrix& A,
-                                               const XT* __restrict__ z,
-                                               const XT* __restrict__ p, XT* az, XT* ap,
-                                               int64_t* row_out) {
+template <typename VT, typename XT, typename CT, int L, typename F>
+__device__ __forceinline__ XT slice_sum(int64_t m, int64_t slice, const CgMatrix& A, F f,
+                                        int64_t* row_out) {
   constexpr int S = kWave / L;
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
@@ -79,7 +106,6 @@ __device__ __forceinline__ void slice_products(int64_t m, int64_t slice, const C
   const int64_t base = A.sptr[slice] + lane;
   const int steps = A.slen[slice] / L;
   XT a0 = (XT)0, a1 = (XT)0, a2 = (XT)0, a3 = (XT)0;
-  XT b0 = (XT)0, b1 = (XT)0, b2 = (XT)0, b3 = (XT)0;
   int st = 0;
   for (; st + 3 < steps; st += 4) {
     const int64_t o = base + (int64_t)st * kWave;
@@ -89,150 +115,233 @@ __device__ __forceinline__ void slice_products(int64_t m, int64_t slice, const C
     const int32_t l3 = rowc + (int32_t)col[o + 3 * kWave];
     const XT v0 = (XT)val[o], v1 = (XT)val[o + kWave];
     const XT v2 = (XT)val[o + 2 * kWave], v3 = (XT)val[o + 3 * kWave];
-    a0 += v0 * z[l0];
-    b0 += v0 * p[l0];
-    a1 += v1 * z[l1];
-    b1 += v1 * p[l1];
-    a2 += v2 * z[l2];
-    b2 += v2 * p[l2];
-    a3 += v3 * z[l3];
-    b3 += v3 * p[l3];
+    a0 += v0 * f(l0);
+    a1 += v1 * f(l1);
+    a2 += v2 * f(l2);
+    a3 += v3 * f(l3);
   }
   for (; st < steps; ++st) {
     const int64_t o = base + (int64_t)st * kWave;
     const int32_t l0 = rowc + (int32_t)col[o];
-    const XT v0 = (XT)val[o];
-    a0 += v0 * z[l0];
-    b0 += v0 * p[l0];
+    a0 += (XT)val[o] * f(l0);
   }
-  XT a = (a0 + a1) + (a2 + a3), b = (b0 + b1) + (b2 + b3);
+  XT a = (a0 + a1) + (a2 + a3);
 #pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) {
-    a += __shfl_xor(a, off, kWave);
-    b += __shfl_xor(b, off, kWave);
-  }
-  *az = a;
-  *ap = b;
+  for (int off = L / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
   *row_out = row;
+  return a;
 }
 
-// q = (B + lambda I) p_new with p_new = z + beta p_old, factored as
-// q = B z + beta B p_old so that the matrix is streamed before beta is known.
-// One wave per slice (grid-stride over slices).
-template <typename VT, typename XT, typename CT, int L>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(
-    int64_t m, CgMatrix A, const XT* __restrict__ z, const XT* __restrict__ pold,
-    XT* __restrict__ pnew, XT* __restrict__ q, CgScalars* __restrict__ sc,
-    const double* __restrict__ part_in, int n_in, double* __restrict__ part_out, int parity,
-    int fixed_beta) {
-  __shared__ double ws[kBlock / kWave];
-  if (sc->done) return;
-  // partials of the previous update: loaded first, reduced after the first
-  // slice's matrix loads are in flight
-  double prz = 0.0, prr = 0.0;
-  for (int k = threadIdx.x; k < n_in; k += kBlock) {
-    prz += part_in[2 * k];
-    prr += part_in[2 * k + 1];
+// Steps (of 64 entries per wave) whose column indices and values are loaded
+// together; the next batch is in flight while the current one's gathers are.
+// Float64 records are twice as wide, so their batches are half as long.
+template <typename XT>
+constexpr int kBatch = sizeof(XT) == 4 ? 8 : 4;
+
+// One batch of a slice: the gathered column index and value of each of its
+// steps (index = the row itself and value 0 past the slice's end).
+template <typename XT>
+struct Batch {
+  int32_t l[kBatch<XT>];
+  XT v[kBatch<XT>];
+};
+
+template <typename VT, typename XT, typename CT>
+__device__ __forceinline__ void load_batch(const CgMatrix& A, int64_t base, int32_t rowc, int st,
+                                           int steps, Batch<XT>& b) {
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  // Loads are unconditional: past the slice's end they read the next slice or
+  // the zeroed tail of the arrays (kSellTail), and the select drops them.
+#pragma unroll
+  for (int t = 0; t < kBatch<XT>; ++t) {
+    const int64_t o = base + (int64_t)(st + t) * kWave;
+    const int32_t c = (int32_t)col[o];
+    const XT v = (XT)val[o];
+    const bool in = st + t < steps;
+    b.l[t] = rowc + (in ? c : 0);
+    b.v[t] = in ? v : (XT)0;
   }
+}
+
+// One slice of a wave: its geometry and its first batch, loaded before the
+// kernel's reduction so that their latency overlaps it.
+template <typename XT>
+struct SliceHead {
+  int64_t row, base;
+  int32_t rowc;
+  int steps;
+  Batch<XT> b;
+};
+
+template <typename VT, typename XT, typename CT, int L>
+__device__ __forceinline__ void open_slice(int64_t m, int64_t slice, const CgMatrix& A,
+                                           SliceHead<XT>& h) {
+  constexpr int S = kWave / L;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
-  int64_t slice = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  XT az = (XT)0, ap = (XT)0;
-  int64_t row = m;
-  if (slice < A.nslices) slice_products<VT, XT, CT, L>(m, slice, A, z, pold, &az, &ap, &row);
-  const double rz = block_sum(prz, ws);
-  const double rr = block_sum(prr, ws);
-  if (!__builtin_isfinite(rz) || !__builtin_isfinite(rr)) {
+  h.row = slice * S + lane / L;
+  h.rowc = (int32_t)(h.row < m ? h.row : m - 1);
+  h.base = A.sptr[slice] + lane;
+  h.steps = A.slen[slice] / L;
+  load_batch<VT, XT, CT>(A, h.base, h.rowc, 0, h.steps, h.b);
+}
+
+// Row sum of an opened slice, complete in the lane with (lane % L) == 0:
+// software-pipelined, the next batch's indices and values load while the
+// current batch is gathered.
+template <typename VT, typename XT, typename CT, int L, typename F>
+__device__ __forceinline__ XT finish_slice(const SliceHead<XT>& h, const CgMatrix& A, F f) {
+  constexpr int U = kBatch<XT>;
+  XT acc[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) acc[t] = (XT)0;
+  Batch<XT> cur = h.b;
+  for (int st = U;; st += U) {
+    const bool more = st < h.steps;
+    Batch<XT> nxt;
+    if (more) load_batch<VT, XT, CT>(A, h.base, h.rowc, st, h.steps, nxt);
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc[t] += cur.v[t] * f(cur.l[t]);
+    if (!more) break;
+    cur = nxt;
+  }
+#pragma unroll
+  for (int w = U / 2; w > 0; w >>= 1) {
+#pragma unroll
+    for (int t = 0; t < w; ++t) acc[t] += acc[t + w];
+  }
+  XT a = acc[0];
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+  return a;
+}
+
+template <typename VT, typename XT, typename CT, int L, int BS>
+__global__ __launch_bounds__(BS) void k_cg_iter(
+    int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
+    XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc,
+    const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int q,
+    int fixed) {
+  constexpr int W = BS / kWave;
+  __shared__ double ws[6][W];
+  __shared__ double ws_out[6][W];
+  __shared__ int s_flag;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int64_t wstride = (int64_t)gridDim.x * W;
+  int64_t slice = (int64_t)blockIdx.x * W + wave;
+
+  // Loads that do not depend on this iteration's scalars go out first: the
+  // first slice's geometry and first batch, the row's own state, the
+  // previous kernel's partials and the scalars.
+  SliceHead<XT> h;
+  CgState<XT> own;
+  XT p_old = (XT)0, x_old = (XT)0;
+  const bool have = slice < A.nslices;
+  if (have) {
+    open_slice<VT, XT, CT, L>(m, slice, A, h);
+    if ((lane & (L - 1)) == 0 && h.row < m) {
+      own = sin[h.row];
+      p_old = p[h.row];
+      x_old = xlo[h.row];
+    }
+  }
+  double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!fixed) {
+    for (int k = threadIdx.x; k < n_in; k += BS) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) red[t] += part_in[6 * k + t];
+    }
+  }
+  const double gam_prev = sc->gam[q ^ 1];
+  const double trigger2 = sc->trigger2;
+  const double fgamma = sc->fix_gamma, frr = sc->fix_rr;
+  const double falpha = sc->fix_alpha, fbeta = sc->fix_beta;
+  // one barrier publishes both the block's partial sums and the flag
+#pragma unroll
+  for (int t = 0; t < 6; ++t) red[t] = wave_sum(red[t]);
+  if (lane == 0) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) ws[t][wave] = red[t];
+  }
+  if (threadIdx.x == 0) s_flag = sc->done;
+  __syncthreads();
+  if (s_flag) return;
+  for (int t = 0; t < 6; ++t) {
+    double v = 0.0;
+#pragma unroll 4
+    for (int w = 0; w < W; ++w) v += ws[t][w];
+    red[t] = v;
+  }
+  const double gamma = fixed ? fgamma : red[0];
+  const double rr = fixed ? frr : red[2];
+  double alpha_d, beta_d;
+  if (fixed) {
+    alpha_d = falpha;
+    beta_d = fbeta;
+  } else {
+    beta_d = gamma / gam_prev;
+    alpha_d = gamma / (red[1] + beta_d * (red[3] + red[4]) + beta_d * beta_d * red[5]);
+  }
+  if (!__builtin_isfinite(rr) || !__builtin_isfinite(gamma)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
     return;
   }
-  if (rr <= sc->trigger2) {
+  if (rr <= trigger2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->rr = rr;
       sc->done = 1;
     }
     return;
   }
-  const double beta_d = fixed_beta ? sc->beta_fixed : rz / sc->rzh[parity ^ 1];
-  const XT beta = (XT)beta_d;
-  double contrib = 0.0;
-  while (slice < A.nslices) {
-    if ((lane & (L - 1)) == 0 && row < m) {
-      const XT pj = z[row] + beta * pold[row];
-      const XT qj = az + beta * ap;
-      pnew[row] = pj;
-      q[row] = qj;
-      contrib += (double)pj * (double)qj;
-    }
-    slice += wstride;
-    if (slice < A.nslices) slice_products<VT, XT, CT, L>(m, slice, A, z, pold, &az, &ap, &row);
-  }
-  const double bs = block_sum(contrib, ws);
-  if (threadIdx.x == 0) {
-    part_out[blockIdx.x] = bs;
-    if (blockIdx.x == 0) {
-      sc->rzh[parity] = rz;
-      sc->rr = rr;
-      sc->beta = beta_d;
-    }
-  }
-}
-
-template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_cg_update(
-    int64_t m, const XT* __restrict__ p, const XT* __restrict__ q, XT* __restrict__ x,
-    XT* __restrict__ r, XT* __restrict__ z, const XT* __restrict__ dinv,
-    CgScalars* __restrict__ sc, const double* __restrict__ part_in, int n_in,
-    double* __restrict__ part_out, int parity) {
-  __shared__ double ws[kBlock / kWave];
-  if (sc->done) return;
-  double ppq = 0.0;
-  for (int k = threadIdx.x; k < n_in; k += kBlock) ppq += part_in[k];
-  // the first element's operands are loaded before alpha is known
-  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  XT pj = (XT)0, qj = (XT)0, xj = (XT)0, rj = (XT)0, dj = (XT)0;
-  if (j < m) {
-    pj = p[j];
-    qj = q[j];
-    xj = x[j];
-    rj = r[j];
-    dj = dinv[j];
-  }
-  const double pq = block_sum(ppq, ws);
-  if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+  if (!(alpha_d > 0.0) || !__builtin_isfinite(alpha_d) || !__builtin_isfinite(beta_d)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
     return;
   }
-  const double alpha_d = sc->rzh[parity] / pq;
-  const XT alpha = (XT)alpha_d;
-  double rz = 0.0, rr = 0.0;
-  while (j < m) {
-    xj += alpha * pj;
-    rj -= alpha * qj;
-    const XT zj = dj * rj;
-    x[j] = xj;
-    r[j] = rj;
-    z[j] = zj;
-    rz += (double)rj * (double)zj;
-    rr += (double)rj * (double)rj;
-    j += stride;
-    if (j < m) {
-      pj = p[j];
-      qj = q[j];
-      xj = x[j];
-      rj = r[j];
-      dj = dinv[j];
+  const XT alpha = (XT)alpha_d, beta = (XT)beta_d;
+  auto u_next = [&](int32_t l) -> XT {
+    const CgState<XT> t = sin[l];
+    return t.d * r_next(t.r, s_next(t.w, t.s, beta), alpha);
+  };
+  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  auto own_row = [&](int64_t row, XT wn, const CgState<XT>& t, XT po, XT xo) {
+    const XT pn = t.d * t.r + beta * po;
+    const XT sn = s_next(t.w, t.s, beta);
+    const XT rn = r_next(t.r, sn, alpha);
+    const XT un = t.d * rn;
+    p[row] = pn;
+    xlo[row] = xo + alpha * pn;
+    CgState<XT> o;
+    o.r = rn;
+    o.w = wn;
+    o.s = sn;
+    o.d = t.d;
+    sout[row] = o;
+    part[0] += (double)rn * (double)un;
+    part[1] += (double)wn * (double)un;
+    part[2] += (double)rn * (double)rn;
+    part[3] += (double)un * (double)sn;
+    part[4] += (double)pn * (double)wn;
+    part[5] += (double)pn * (double)sn;
+  };
+  if (have) {
+    const XT wn = finish_slice<VT, XT, CT, L>(h, A, u_next);
+    if ((lane & (L - 1)) == 0 && h.row < m) own_row(h.row, wn, own, p_old, x_old);
+    for (slice += wstride; slice < A.nslices; slice += wstride) {
+      open_slice<VT, XT, CT, L>(m, slice, A, h);
+      const XT wn2 = finish_slice<VT, XT, CT, L>(h, A, u_next);
+      if ((lane & (L - 1)) == 0 && h.row < m)
+        own_row(h.row, wn2, sin[h.row], p[h.row], xlo[h.row]);
     }
   }
-  const double brz = block_sum(rz, ws);
-  const double brr = block_sum(rr, ws);
+  block_sums<6, W, false>(part, ws_out);
   if (threadIdx.x == 0) {
-    part_out[2 * blockIdx.x] = brz;
-    part_out[2 * blockIdx.x + 1] = brr;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) part_out[6 * blockIdx.x + t] = part[t];
     if (blockIdx.x == 0) {
-      sc->alpha = alpha_d;
-      sc->pq = pq;
+      sc->gam[q] = gamma;
+      sc->alp[q] = alpha_d;
+      sc->rr = rr;
       sc->iter += 1;
     }
   }
@@ -247,148 +356,239 @@ __global__ void k_fold_solution(int64_t m, double* __restrict__ xhi, XT* __restr
   xlo[j] = (XT)0;
 }
 
-// Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, then
-// r = (XT) r64 and z = D^-1 r (one wave per slice).
-template <typename VT, typename XT, typename CT, int L>
-__global__ __launch_bounds__(kBlock) void k_true_residual(int64_t m, CgMatrix A,
-                                                          const double* __restrict__ xhi,
-                                                          const double* __restrict__ g,
-                                                          const XT* __restrict__ dinv,
-                                                          double* __restrict__ r64,
-                                                          XT* __restrict__ r, XT* __restrict__ z) {
+// Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, and
+// r = (XT) r64 into the state record (one wave per slice).
+template <typename VT, typename XT, typename CT, int L, int BS>
+__global__ __launch_bounds__(BS) void k_true_residual(int64_t m, CgMatrix A,
+                                                            const double* __restrict__ xhi,
+                                                            const double* __restrict__ g,
+                                                            double* __restrict__ r64,
+                                                            CgState<XT>* __restrict__ st) {
   constexpr int S = kWave / L;
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
   const int lane = threadIdx.x & (kWave - 1);
-  for (int64_t slice = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-       slice < A.nslices; slice += (int64_t)gridDim.x * kWavesPerBlock) {
+  constexpr int W = BS / kWave;
+  for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
+       slice += (int64_t)gridDim.x * W) {
     const int64_t row = slice * S + lane / L;
     const int32_t rowc = (int32_t)(row < m ? row : m - 1);
     const int64_t base = A.sptr[slice] + lane;
     const int steps = A.slen[slice] / L;
     double acc = 0.0;
-    for (int st = 0; st < steps; ++st) {
-      const int64_t o = base + (int64_t)st * kWave;
+    for (int s = 0; s < steps; ++s) {
+      const int64_t o = base + (int64_t)s * kWave;
       acc += (double)val[o] * xhi[rowc + (int32_t)col[o]];
     }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((lane & (L - 1)) == 0 && row < m) {
       const double rv = g[row] - acc;
-      const XT ri = (XT)rv;
       r64[row] = rv;
-      r[row] = ri;
-      z[row] = dinv[row] * ri;
+      st[row].r = (XT)rv;
     }
   }
 }
 
-// Partials of r.z and r64.r64 in the update kernel's layout.
-template <typename XT>
-__global__ __launch_bounds__(kBlock) void k_residual_dots(int64_t m, const double* __restrict__ r64,
-                                                          const XT* __restrict__ r,
-                                                          const XT* __restrict__ z,
-                                                          double* __restrict__ part_out) {
-  __shared__ double ws[kBlock / kWave];
-  double rz = 0.0, rr = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m;
-       j += (int64_t)gridDim.x * kBlock) {
-    rz += (double)r[j] * (double)z[j];
-    rr += r64[j] * r64[j];
+// w = B D^-1 r from the records of st[q] (r just replaced), written with the
+// carried s and d into the other buffer; partials of r.u, w.u, r64.r64,
+// p.w, u.s and p.s.
+template <typename VT, typename XT, typename CT, int L, int BS>
+__global__ __launch_bounds__(BS) void k_cg_refresh(int64_t m, CgMatrix A,
+                                                         const CgState<XT>* __restrict__ sin,
+                                                         CgState<XT>* __restrict__ sout,
+                                                         const XT* __restrict__ p,
+                                                         const double* __restrict__ r64,
+                                                         double* __restrict__ part_out) {
+  constexpr int W = BS / kWave;
+  __shared__ double ws[6][W];
+  auto u_of = [&](int32_t l) -> XT {
+    const CgState<XT> t = sin[l];
+    return t.d * t.r;
+  };
+  const int lane = threadIdx.x & (kWave - 1);
+  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
+       slice += (int64_t)gridDim.x * W) {
+    int64_t row;
+    const XT wn = slice_sum<VT, XT, CT, L>(m, slice, A, u_of, &row);
+    if ((lane & (L - 1)) == 0 && row < m) {
+      const CgState<XT> t = sin[row];
+      const XT u = t.d * t.r;
+      const XT pj = p[row];
+      CgState<XT> o;
+      o.r = t.r;
+      o.w = wn;
+      o.s = t.s;
+      o.d = t.d;
+      sout[row] = o;
+      const double r64j = r64[row];
+      part[0] += (double)t.r * (double)u;
+      part[1] += (double)wn * (double)u;
+      part[2] += r64j * r64j;
+      part[3] += (double)pj * (double)wn;
+      part[4] += (double)u * (double)t.s;
+      part[5] += (double)pj * (double)t.s;
+    }
   }
-  const double brz = block_sum(rz, ws);
-  const double brr = block_sum(rr, ws);
+  block_sums<6, W, false>(part, ws);
   if (threadIdx.x == 0) {
-    part_out[2 * blockIdx.x] = brz;
-    part_out[2 * blockIdx.x + 1] = brr;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part_out[6 * blockIdx.x + k] = part[k];
   }
 }
 
-// After a float64 residual: sets the true residual norm, the convergence flag,
-// the next trigger, and the beta the next spmv takes (0 on a restart,
-// rz_true / rz_{k-1} on a reliable update).
-__global__ __launch_bounds__(kBlock) void k_residual_scalars(CgScalars* __restrict__ sc,
-                                                             const double* __restrict__ part,
-                                                             int n, int restart, int parity) {
-  __shared__ double ws[kBlock / kWave];
-  const double rz = reduce_partials(part, n, 2, 0, ws);
-  const double rr = reduce_partials(part, n, 2, 1, ws);
+// After a refresh: the true residual norm, the convergence flag, the next
+// trigger and the scalars of the next iteration (restart: beta = 0, so
+// p = u and s = w; otherwise beta = gamma / gamma_prev with the direction
+// kept, and alpha = gamma / (p . s) from the expanded product).
+__global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(CgScalars* __restrict__ sc,
+                                                              const double* __restrict__ part,
+                                                              int n, int q_prev, int restart) {
+  constexpr int W = kCgLargeBlock / kWave;
+  __shared__ double ws[6][W];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += kCgLargeBlock) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) v[t] += part[6 * k + t];
+  }
+  block_sums<6, W, false>(v, ws);
   if (threadIdx.x == 0) {
+    const double gamma = v[0], delta = v[1], rr = v[2];
+    const double beta = restart ? 0.0 : gamma / sc->gam[q_prev];
+    const double ps = delta + beta * (v[3] + v[4]) + beta * beta * v[5];
+    const double alpha = gamma / ps;
     sc->rr_true = rr;
     sc->rr = rr;
-    sc->beta_fixed = restart ? 0.0 : rz / sc->rzh[parity ^ 1];
+    sc->fix_rr = rr;
+    sc->fix_gamma = gamma;
+    sc->fix_beta = beta;
+    sc->fix_alpha = alpha;
     const double trig = sc->delta2 * rr;
     sc->trigger2 = trig > sc->tol2 ? trig : sc->tol2;
-    if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
+    if (!__builtin_isfinite(rr) || !__builtin_isfinite(gamma)) {
       sc->done = 2;
     } else if (rr <= sc->tol2) {
       sc->done = 3;
+    } else if (!(ps > 0.0) || !__builtin_isfinite(alpha) || !__builtin_isfinite(beta)) {
+      sc->done = 2;
     } else {
       sc->done = 0;
     }
   }
 }
 
+// Start of a solve: inactive coefficients zeroed, x_lo, p and both state
+// buffers cleared (s = 0), d = D^-1 in both.
 template <typename XT>
-__global__ void k_zero_inactive(int64_t m, const uint8_t* __restrict__ active,
-                                double* __restrict__ xhi, XT* __restrict__ xlo,
-                                XT* __restrict__ p0, XT* __restrict__ p1) {
+__global__ void k_cg_clear(int64_t m, const uint8_t* __restrict__ active, const XT* __restrict__ dinv,
+                           double* __restrict__ xhi, XT* __restrict__ xlo, XT* __restrict__ p,
+                           CgState<XT>* __restrict__ s0, CgState<XT>* __restrict__ s1) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   if (!active[j]) xhi[j] = 0.0;
   xlo[j] = (XT)0;
-  p0[j] = (XT)0;
-  p1[j] = (XT)0;
+  p[j] = (XT)0;
+  CgState<XT> t;
+  t.r = (XT)0;
+  t.w = (XT)0;
+  t.s = (XT)0;
+  t.d = dinv[j];
+  s0[j] = t;
+  s1[j] = t;
 }
 
 // ||g||^2 and the initial state of the scalars (single block, fixed order).
-__global__ __launch_bounds__(kBlock) void k_cg_init(int64_t m, const double* __restrict__ g,
-                                                    CgScalars* __restrict__ sc, double rtol,
-                                                    double delta) {
-  __shared__ double ws[kBlock / kWave];
-  double s = 0.0;
-  for (int64_t j = threadIdx.x; j < m; j += kBlock) s += g[j] * g[j];
-  s = block_sum(s, ws);
+__global__ __launch_bounds__(kCgLargeBlock) void k_cg_init(int64_t m, const double* __restrict__ g,
+                                                      CgScalars* __restrict__ sc, double rtol,
+                                                      double delta) {
+  constexpr int W = kCgLargeBlock / kWave;
+  __shared__ double ws[1][W];
+  double v[1] = {0.0};
+  for (int64_t j = threadIdx.x; j < m; j += kCgLargeBlock) v[0] += g[j] * g[j];
+  block_sums<1, W, false>(v, ws);
   if (threadIdx.x == 0) {
-    sc->gg = s;
-    sc->tol2 = rtol * rtol * s;
+    sc->gg = v[0];
+    sc->tol2 = rtol * rtol * v[0];
     sc->delta2 = delta * delta;
     sc->trigger2 = sc->tol2;
     sc->done = 0;
     sc->iter = 0;
-    sc->rzh[0] = sc->rzh[1] = 1.0;
-    sc->beta = sc->beta_fixed = 0.0;
-    sc->alpha = sc->pq = 0.0;
+    sc->gam[0] = sc->gam[1] = 1.0;
+    sc->alp[0] = sc->alp[1] = 1.0;
+    sc->fix_gamma = sc->fix_alpha = sc->fix_beta = sc->fix_rr = 0.0;
+    sc->rr = sc->rr_true = v[0];
   }
 }
 
-template <typename VT, typename XT, typename CT, int L>
-void launch_spmv_l(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+template <typename VT, typename XT, typename CT, int L, int BS>
+void launch_iter_b(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                   hipEvent_t e1, hipStream_t s) {
   if (e0) {
     // the extended launch stamps the events at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, e0,
-                          e1, 0, a.m, A, (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1],
-                          a.q, a.sc, (const double*)a.part_upd, a.update_blocks, a.part_spmv,
-                          parity, fixed_beta);
+    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, e0, e1,
+                          0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                          (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
   } else {
-    hipLaunchKernelGGL((k_cg_spmv<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s, a.m,
-                       A, (const XT*)a.z, (const XT*)a.p[parity], a.p[parity ^ 1], a.q, a.sc,
-                       (const double*)a.part_upd, a.update_blocks, a.part_spmv, parity,
-                       fixed_beta);
+    hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m, A,
+                       (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
   }
 }
 
 template <typename VT, typename XT, typename CT, int L>
-void launch_true_residual_l(const CgArgs<XT>& a, const CgMatrix& A, const double* g,
-                            hipStream_t s) {
-  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, L>), dim3(a.spmv_blocks), dim3(kBlock), 0, s,
-                     a.m, A, (const double*)a.xhi, g, (const XT*)a.dinv, a.r64, a.r, a.z);
+void launch_iter_l(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                   hipEvent_t e1, hipStream_t s) {
+  if (a.threads == kCgSmallBlock)
+    launch_iter_b<VT, XT, CT, L, kCgSmallBlock>(a, A, q, fixed, e0, e1, s);
+  else
+    launch_iter_b<VT, XT, CT, L, kCgLargeBlock>(a, A, q, fixed, e0, e1, s);
 }
 
-bool grids_ok(int spmv_blocks, int update_blocks) {
-  return spmv_blocks >= 1 && spmv_blocks <= kCgMaxBlocks && update_blocks >= 1 &&
-         update_blocks <= kCgMaxBlocks;
+template <typename VT, typename XT, typename CT, int L, int BS>
+void launch_refresh_b(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+                     A, (const double*)a.xhi, g, a.r64, a.st[q]);
+  hipLaunchKernelGGL((k_cg_refresh<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m, A,
+                     (const CgState<XT>*)a.st[q], a.st[q ^ 1], (const XT*)a.p,
+                     (const double*)a.r64, a.part_ref);
+}
+
+template <typename VT, typename XT, typename CT, int L>
+void launch_refresh_l(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q,
+                      hipStream_t s) {
+  if (a.threads == kCgSmallBlock)
+    launch_refresh_b<VT, XT, CT, L, kCgSmallBlock>(a, A, g, q, s);
+  else
+    launch_refresh_b<VT, XT, CT, L, kCgLargeBlock>(a, A, g, q, s);
+}
+
+template <typename VT, typename XT, typename CT>
+void iter_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                   hipEvent_t e1, hipStream_t s) {
+  switch (A.lanes) {
+    case 2: launch_iter_l<VT, XT, CT, 2>(a, A, q, fixed, e0, e1, s); break;
+    case 4: launch_iter_l<VT, XT, CT, 4>(a, A, q, fixed, e0, e1, s); break;
+    default: launch_iter_l<VT, XT, CT, 8>(a, A, q, fixed, e0, e1, s); break;
+  }
+}
+
+template <typename VT, typename XT, typename CT>
+void refresh_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q,
+                      hipStream_t s) {
+  switch (A.lanes) {
+    case 2: launch_refresh_l<VT, XT, CT, 2>(a, A, g, q, s); break;
+    case 4: launch_refresh_l<VT, XT, CT, 4>(a, A, g, q, s); break;
+    default: launch_refresh_l<VT, XT, CT, 8>(a, A, g, q, s); break;
+  }
+}
+
+template <typename XT>
+bool args_ok(const CgArgs<XT>& a, const CgMatrix& A) {
+  return a.blocks >= 1 && a.blocks <= kCgMaxBlocks && A.nslices >= 1 &&
+         (a.threads == kCgSmallBlock || a.threads == kCgLargeBlock) &&
+         (A.lanes == 2 || A.lanes == 4 || A.lanes == 8);
 }
 
 }  // namespace
@@ -399,76 +599,44 @@ int sell_lanes(double mean_row) {
   return 2;
 }
 
-int cg_grid_blocks(int64_t nslices) {
-  const int64_t b = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
-  return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
-}
-
-int cg_update_blocks(int64_t m) {
-  const int64_t b = (m + kBlock - 1) / kBlock;
-  return (int)(b < 1 ? 1 : (b > kCgMaxBlocks ? kCgMaxBlocks : b));
-}
-
-namespace {
-
-template <typename VT, typename XT, typename CT>
-void spmv_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
-  switch (A.lanes) {
-    case 2: launch_spmv_l<VT, XT, CT, 2>(a, A, parity, fixed_beta, e0, e1, s); break;
-    case 4: launch_spmv_l<VT, XT, CT, 4>(a, A, parity, fixed_beta, e0, e1, s); break;
-    default: launch_spmv_l<VT, XT, CT, 8>(a, A, parity, fixed_beta, e0, e1, s); break;
+void cg_grid(int64_t nslices, int* blocks, int* threads) {
+  const int64_t ws = kCgSmallBlock / kWave, wl = kCgLargeBlock / kWave;
+  const int64_t bs = (nslices + ws - 1) / ws;
+  if (bs <= kCgMaxBlocks) {
+    *blocks = (int)(bs < 1 ? 1 : bs);
+    *threads = kCgSmallBlock;
+    return;
   }
+  const int64_t bl = (nslices + wl - 1) / wl;
+  *blocks = (int)(bl > kCgMaxBlocks ? kCgMaxBlocks : bl);
+  *threads = kCgLargeBlock;
 }
-
-template <typename VT, typename XT, typename CT>
-void residual_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, hipStream_t s) {
-  switch (A.lanes) {
-    case 2: launch_true_residual_l<VT, XT, CT, 2>(a, A, g, s); break;
-    case 4: launch_true_residual_l<VT, XT, CT, 4>(a, A, g, s); break;
-    default: launch_true_residual_l<VT, XT, CT, 8>(a, A, g, s); break;
-  }
-}
-
-}  // namespace
 
 template <typename VT, typename XT>
-hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
-  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+hipError_t cg_iterate(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                      hipEvent_t e1, hipStream_t s) {
+  if (!args_ok(a, A) || (q != 0 && q != 1)) return hipErrorInvalidValue;
   if (A.col16)
-    spmv_dispatch<VT, XT, int16_t>(a, A, parity, fixed_beta, e0, e1, s);
+    iter_dispatch<VT, XT, int16_t>(a, A, q, fixed, e0, e1, s);
   else
-    spmv_dispatch<VT, XT, int32_t>(a, A, parity, fixed_beta, e0, e1, s);
-  return hipGetLastError();
-}
-
-template <typename XT>
-hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s) {
-  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
-  // the direction written by the preceding spmv sits in p[parity ^ 1]
-  hipLaunchKernelGGL(k_cg_update<XT>, dim3(a.update_blocks), dim3(kBlock), 0, s, a.m,
-                     (const XT*)a.p[parity ^ 1], (const XT*)a.q, a.xlo, a.r, a.z,
-                     (const XT*)a.dinv, a.sc, (const double*)a.part_spmv, a.spmv_blocks,
-                     a.part_upd, parity);
+    iter_dispatch<VT, XT, int32_t>(a, A, q, fixed, e0, e1, s);
   return hipGetLastError();
 }
 
 template <typename VT, typename XT>
-hipError_t cg_true_residual(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int restart,
-                            int parity, hipStream_t s) {
-  if (!grids_ok(a.spmv_blocks, a.update_blocks)) return hipErrorInvalidValue;
+hipError_t cg_refresh(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q, int q_prev,
+                      int restart, hipStream_t s) {
+  if (!args_ok(a, A) || (q != 0 && q != 1) || (q_prev != 0 && q_prev != 1))
+    return hipErrorInvalidValue;
   const int bs = 256;
   const dim3 eg((unsigned)((a.m + bs - 1) / bs));
   hipLaunchKernelGGL(k_fold_solution<XT>, eg, dim3(bs), 0, s, a.m, a.xhi, a.xlo);
   if (A.col16)
-    residual_dispatch<VT, XT, int16_t>(a, A, g, s);
+    refresh_dispatch<VT, XT, int16_t>(a, A, g, q, s);
   else
-    residual_dispatch<VT, XT, int32_t>(a, A, g, s);
-  hipLaunchKernelGGL(k_residual_dots<XT>, dim3(a.update_blocks), dim3(kBlock), 0, s, a.m,
-                     (const double*)a.r64, (const XT*)a.r, (const XT*)a.z, a.part_upd);
-  hipLaunchKernelGGL(k_residual_scalars, dim3(1), dim3(kBlock), 0, s, a.sc,
-                     (const double*)a.part_upd, a.update_blocks, restart, parity);
+    refresh_dispatch<VT, XT, int32_t>(a, A, g, q, s);
+  hipLaunchKernelGGL(k_refresh_scalars, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                     (const double*)a.part_ref, a.blocks, q_prev, restart);
   return hipGetLastError();
 }
 
@@ -477,22 +645,20 @@ hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g,
                     double delta, hipStream_t s) {
   const int bs = 256;
   const dim3 eg((unsigned)((a.m + bs - 1) / bs));
-  hipLaunchKernelGGL(k_zero_inactive<XT>, eg, dim3(bs), 0, s, a.m, active, a.xhi, a.xlo, a.p[0],
-                     a.p[1]);
-  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kBlock), 0, s, a.m, g, a.sc, rtol, delta);
+  hipLaunchKernelGGL(k_cg_clear<XT>, eg, dim3(bs), 0, s, a.m, active, a.dinv, a.xhi, a.xlo, a.p,
+                     a.st[0], a.st[1]);
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kCgLargeBlock), 0, s, a.m, g, a.sc, rtol, delta);
   return hipGetLastError();
 }
 
-template hipError_t cg_spmv<double, double>(const CgArgs<double>&, const CgMatrix&, int, int,
-                                            hipEvent_t, hipEvent_t, hipStream_t);
-template hipError_t cg_spmv<float, float>(const CgArgs<float>&, const CgMatrix&, int, int,
-                                          hipEvent_t, hipEvent_t, hipStream_t);
-template hipError_t cg_update<double>(const CgArgs<double>&, int, hipStream_t);
-template hipError_t cg_update<float>(const CgArgs<float>&, int, hipStream_t);
-template hipError_t cg_true_residual<double, double>(const CgArgs<double>&, const CgMatrix&,
-                                                     const double*, int, int, hipStream_t);
-template hipError_t cg_true_residual<float, float>(const CgArgs<float>&, const CgMatrix&,
-                                                   const double*, int, int, hipStream_t);
+template hipError_t cg_iterate<double, double>(const CgArgs<double>&, const CgMatrix&, int, int,
+                                               hipEvent_t, hipEvent_t, hipStream_t);
+template hipError_t cg_iterate<float, float>(const CgArgs<float>&, const CgMatrix&, int, int,
+                                             hipEvent_t, hipEvent_t, hipStream_t);
+template hipError_t cg_refresh<double, double>(const CgArgs<double>&, const CgMatrix&,
+                                               const double*, int, int, int, hipStream_t);
+template hipError_t cg_refresh<float, float>(const CgArgs<float>&, const CgMatrix&, const double*,
+                                             int, int, int, hipStream_t);
 template hipError_t cg_setup<double>(const CgArgs<double>&, const uint8_t*, const double*, double,
                                      double, hipStream_t);
 template hipError_t cg_setup<float>(const CgArgs<float>&, const uint8_t*, const double*, double,

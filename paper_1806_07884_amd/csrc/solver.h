@@ -1,46 +1,66 @@
-// Device scalars and argument bundles of the conjugate-gradient kernels.
+// Device scalars, per-row state and argument bundles of the conjugate-gradient kernels.
 #pragma once
 
 #include "internal.h"
 
 namespace rbf {
 
-// Most blocks of any CG kernel; bounds the partial-sum arrays.
-constexpr int kCgMaxBlocks = 2048;
+// CG blocks hold 256 threads (4 waves) while a grid of one slice per wave has
+// at most kCgMaxBlocks blocks, else 1024 threads (16 waves).  Every block of a
+// kernel reduces all partial sums of the previous kernel, a cost quadratic in
+// the block count that kCgMaxBlocks bounds; small blocks keep the waves of a
+// block from waiting on one another at its barriers.
+constexpr int kCgSmallBlock = 256;
+constexpr int kCgLargeBlock = 1024;
+constexpr int kCgMaxBlocks = 1024;
+// Entries past the last slice that every stored-matrix array (columns and
+// values) carries, zeroed: a CG kernel loads whole batches of 8 steps of 64
+// entries, so a batch may run up to 7 steps past the end of its slice.
+constexpr int64_t kSellTail = 8 * 64;
 
 // Scalars of one CG solve, kept in device memory.  Each is written by block 0
-// of one kernel and read by later kernels (or the host) only.
+// of one kernel and read by later kernels (or the host) only; the per-parity
+// pairs let an iteration read its predecessor's value while writing its own.
 struct CgScalars {
-  double rzh[2];     // r . z of iterate k at [k & 1]
-  double beta_fixed; // beta of the next spmv after a float64 residual
-  double alpha, beta, pq;
+  double gam[2];     // gamma = r . u of the iteration run on state buffer q, at [q]
+  double alp[2];     // alpha of that iteration, at [q] (reported only)
+  double fix_gamma;  // gamma, alpha, beta, ||r||^2 of the first iteration after a
+  double fix_alpha;  // float64 residual (set by the refresh)
+  double fix_beta;
+  double fix_rr;
   double rr;         // ||r||^2 of the iterated residual (last seen)
   double rr_true;    // ||g - (B + lambda I) x||^2 at the last float64 recomputation
   double gg;         // ||g||^2
   double tol2;       // rtol^2 * gg
   double delta2;     // reliable-update factor squared
-  double trigger2;   // iterated ||r||^2 at which the spmv raises the flag
+  double trigger2;   // iterated ||r||^2 at which an iteration raises the flag
   int64_t iter;      // executed iterations
   int32_t done;      // 0 running, 1 trigger reached, 2 breakdown, 3 converged
   int32_t pad_;
 };
 
+// Per-row state read by neighbouring rows: residual r, w = B D^-1 r, the
+// recurrence s = B p, and the Jacobi scale d = 1 / (b_jj + lambda).  One
+// aligned record per row, so a neighbour's whole state is one vector load.
+template <typename XT>
+struct alignas(4 * sizeof(XT)) CgState {
+  XT r, w, s, d;
+};
+
 template <typename XT>
 struct CgArgs {
   int64_t m;
-  XT* p[2];
-  XT* q;
-  XT* r;
-  XT* z;
-  XT* xlo;            // iterated correction
+  CgState<XT>* st[2];  // state, double-buffered: an iteration reads one, writes the other
+  XT* p;               // search direction (read and written by its own row only)
+  XT* xlo;             // iterated correction of the solution
   const XT* dinv;
-  double* xhi;        // float64 solution
-  double* r64;        // float64 true residual
+  double* xhi;         // float64 solution
+  double* r64;         // float64 true residual
   CgScalars* sc;
-  double* part_spmv;  // [spmv_blocks] partials of p . q
-  double* part_upd;   // [2 * update_blocks] partials of r . z and r . r
-  int spmv_blocks;
-  int update_blocks;
+  double* part[2];     // [6 * blocks] partials of an iteration, by state buffer
+  double* part_ref;    // [6 * blocks] partials of a refresh
+  int blocks;          // grid of every slice kernel
+  int threads;         // its block size: kCgSmallBlock or kCgLargeBlock
 };
 
 // The stored matrix in the solver's sliced-ELL layout.  Rows are taken in
@@ -68,22 +88,24 @@ __host__ __device__ inline int64_t sell_pos(const int64_t* sptr, int lanes, int6
 }
 
 int sell_lanes(double mean_row);
-int cg_grid_blocks(int64_t nslices);
-int cg_update_blocks(int64_t m);
+// Grid (blocks, threads per block) of the slice kernels for nslices slices.
+void cg_grid(int64_t nslices, int* blocks, int* threads);
 
-// Iteration k = cg_spmv(parity = k & 1) then cg_update(parity).  fixed_beta:
-// the spmv takes beta from the last float64 residual (first iteration after
-// set-up or a reliable update).  With e0/e1 (may be null) the launch stamps
-// the two events at the kernel's start and end.
+// One CG iteration on state buffer q (reads st[q], writes st[q ^ 1]).  fixed:
+// the first iteration after a refresh, which takes its scalars from the
+// refresh instead of from partial sums.  With e0/e1 (may be null) the launch
+// stamps the two events at the kernel's start and end.
 template <typename VT, typename XT>
-hipError_t cg_spmv(const CgArgs<XT>& a, const CgMatrix& A, int parity, int fixed_beta,
-                   hipEvent_t e0, hipEvent_t e1, hipStream_t s);
-template <typename XT>
-hipError_t cg_update(const CgArgs<XT>& a, int parity, hipStream_t s);
-// x_hi += x_lo; float64 residual; r, z from it; scalars for the next spmv.
+hipError_t cg_iterate(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                      hipEvent_t e1, hipStream_t s);
+// Reliable update on state buffer q: x_hi += x_lo, float64 residual
+// r64 = g - (B + lambda I) x_hi, r = (XT) r64, w = B D^-1 r written to
+// st[q ^ 1] (with s, d carried over), then the scalars of the next iteration
+// (restart: beta = 0; otherwise the direction is kept).  q_prev is the state
+// buffer of the last executed iteration (its gamma is the previous one).
 template <typename VT, typename XT>
-hipError_t cg_true_residual(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int restart,
-                            int parity, hipStream_t s);
+hipError_t cg_refresh(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q, int q_prev,
+                      int restart, hipStream_t s);
 template <typename XT>
 hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
                     double delta, hipStream_t s);
