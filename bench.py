@@ -46,8 +46,9 @@ def log(*a):
 
 def iter_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int) -> int:
     """Algorithmic HBM bytes of one CG iteration launch: every nonzero of B
-    once (value and column index, padding excluded) and, per row, its state
-    record (r, w, s, d) read and written plus p and x read and written."""
+    once (value and column index, padding excluded) and, per solver row (an
+    active centre), its state record (r, w, s, d) read and written plus p and
+    x read and written."""
     return nnz_full * (val_bytes + col_bytes) + 12 * m * vec_bytes
 
 
@@ -178,7 +179,8 @@ def main() -> int:
     rmse32, rmse64 = per32[-1][1], per64[-1][1]
     matched = abs(rmse32 - rmse64) <= 1e-3 * rmse64
 
-    nnz, m, cb = stats["nnz_full"], stats["n_centers"], stats["solver_col_bytes"]
+    # the solver's rows are the active centres
+    nnz, m, cb = stats["nnz_full"], stats["n_active"], stats["solver_col_bytes"]
     # kernel time from start/stop events of sampled launches on the plan's stream
     kern32 = max(avg32, 1e-3) * 1e-6
     bytes32 = iter_bytes(nnz, m, 4, cb, 4)
@@ -210,7 +212,8 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": wl, "dim": prob.dim,
                    "n_points": int(prob.points.shape[1] + prob.test_points.shape[1]),
-                   "n_train": int(n_train), "n_centers": int(m), "grid": prob.grid,
+                   "n_train": int(n_train), "n_centers": int(stats["n_centers"]),
+                   "n_active": int(m), "grid": prob.grid,
                    "phi": prob.phi, "rho": prob.rho, "lambda_rel": LAMBDA_REL, "rtol": RTOL,
                    "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates"},
         "roofline": roofline,

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "mlp_kernels.h"
@@ -38,6 +39,34 @@ int fail(int code, const char* fmt, ...) {
 constexpr int64_t kMaxCells = int64_t(1) << 26;
 
 }  // namespace
+
+// Pinned host slots for the solver's scalar snapshots, kept for the life of
+// the process and handed from plan to plan (page-locking memory is slow, and
+// a plan is often made per fit).
+std::mutex g_pinned_mu;
+std::vector<rbf::CgScalars*> g_pinned_free;
+
+rbf::CgScalars* pinned_acquire() {
+  {
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      rbf::CgScalars* p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, 2 * sizeof(rbf::CgScalars), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return static_cast<rbf::CgScalars*>(p);
+}
+
+void pinned_release(rbf::CgScalars* p) {
+  std::lock_guard<std::mutex> lock(g_pinned_mu);
+  g_pinned_free.push_back(p);
+}
 
 struct rbf_plan {
   rbf_allocator alloc{};
@@ -74,6 +103,9 @@ struct rbf_plan {
   // pattern
   int32_t* support = nullptr;
   uint8_t* active = nullptr;
+  int32_t* amap = nullptr;  // centre -> solver row (active centres in order) or -1
+  int32_t* srow = nullptr;  // solver row -> centre
+  int64_t ms = 0;           // solver rows
   int64_t* row_ptr = nullptr;
   int32_t* lower_cnt = nullptr;
   int32_t* col = nullptr;
@@ -89,6 +121,7 @@ struct rbf_plan {
   // system
   double* hs = nullptr;
   double* g = nullptr;
+  double* g_s = nullptr;  // g over the solver rows
   double* diag = nullptr;
   double* lam = nullptr;
   double* val64 = nullptr;
@@ -107,8 +140,8 @@ struct rbf_plan {
   void* vec32[4] = {};
   double* cs_sorted = nullptr;
   double* eval_part = nullptr;
-  rbf::CgScalars* host_sc = nullptr;  // pinned
-  double* host_small = nullptr;       // pinned
+  rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots (from the pinned pool)
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
 
   // optional kernel timing: HIP events bracketing sampled launches
   struct Pending {
@@ -132,12 +165,20 @@ struct rbf_plan {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
-  // folds every finished pair into the totals; CG launches at or beyond
-  // `cg_done` iterations returned at entry and are dropped
-  void resolve(int64_t cg_done) {
+  // Folds the pairs of executed launches (CG launches below `cg_done`
+  // iterations, every other launch) into the totals.  CG launches at or
+  // beyond it either returned at entry, when `settled` (dropped), or are
+  // still queued (kept for a later call).
+  void resolve(int64_t cg_done, bool settled) {
+    std::vector<Pending> keep;
     for (const Pending& q : pending) {
+      const bool ran = q.iter < 0 || q.iter < cg_done;
+      if (!ran && !settled) {
+        keep.push_back(q);
+        continue;
+      }
       float ms = 0.f;
-      if ((q.iter < 0 || q.iter < cg_done) && hipEventSynchronize(q.b) == hipSuccess &&
+      if (ran && hipEventSynchronize(q.b) == hipSuccess &&
           hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
         prof_launches[q.kernel] += 1;
         prof_ms[q.kernel] += ms;
@@ -145,7 +186,7 @@ struct rbf_plan {
       ev_free.push_back(q.a);
       ev_free.push_back(q.b);
     }
-    pending.clear();
+    pending.swap(keep);
   }
 
   void* alloc_bytes(size_t bytes) {
@@ -196,13 +237,15 @@ struct rbf_plan {
     v.rho2 = rho2;
     v.irho = irho;
     v.active = active;
+    v.amap = amap;
     return v;
   }
   ~rbf_plan() {
     if (stream) (void)hipStreamSynchronize(stream);
     while (!bufs.empty()) release(bufs.back().p);
-    if (host_sc) (void)hipHostFree(host_sc);
-    if (host_small) (void)hipHostFree(host_small);
+    if (host_sc) pinned_release(host_sc);
+    for (hipEvent_t e : snap_ev)
+      if (e) (void)hipEventDestroy(e);
     for (const Pending& q : pending) {
       (void)hipEventDestroy(q.a);
       (void)hipEventDestroy(q.b);
@@ -342,6 +385,15 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   rbf::PlanView v = P->view();
   HIPCHK(rbf::launch_support_count(v, P->min_support, P->support, P->active, s));
 
+  // rows of the solver's system: the active centres in order
+  int64_t* apos;
+  GET(P->amap, m);
+  GET(P->srow, m);
+  GET(apos, m + 1);
+  void* atmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
+  if (!atmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::launch_solver_rows(P->active, m, apos, atmp, P->amap, P->srow, s));
+
   int64_t* cnt;
   int32_t *err, *maxd;
   GET(cnt, m + 1);
@@ -357,12 +409,16 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
   if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
   HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
-  int64_t nnz = 0;
+  int64_t nnz = 0, ms = 0;
   int32_t flags[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&ms, apos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(flags, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(cnt);
+  P->release(apos);
+  P->release(atmp);
+  P->ms = ms;
   if (flags[0])
     return fail(RBF_ERR_INVALID,
                 "a centre has more than %d neighbouring centres within two support radii",
@@ -374,17 +430,18 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, maxd, marks,
                               s));
 
-  // solver layout: sliced ELL with L lanes per row
-  P->lanes = rbf::sell_lanes((double)nnz / (double)std::max<int64_t>(m, 1));
+  // solver layout: sliced ELL with L lanes per row, over the solver rows
+  P->lanes = rbf::sell_lanes((double)nnz / (double)std::max<int64_t>(ms, 1));
   const int64_t rows_per_slice = 64 / P->lanes;
-  P->nslices = (m + rows_per_slice - 1) / rows_per_slice;
+  P->nslices = (ms + rows_per_slice - 1) / rows_per_slice;
   int64_t* ssize;
   GET(P->slen, P->nslices);
   GET(P->sptr, P->nslices + 1);
   GET(ssize, P->nslices + 1);
   void* stmp2 = P->alloc_bytes(rbf::scan_temp_bytes(P->nslices + 1));
   if (!stmp2) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
-  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, m, P->lanes, P->nslices, P->slen, ssize, s));
+  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, P->srow, ms, P->lanes, P->nslices, P->slen, ssize,
+                                   s));
   HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -400,14 +457,15 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   P->scol = P->alloc_bytes(cbytes);
   if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
   HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
-  HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, m, P->sptr, P->lanes, P->col16, P->scol, s));
+  HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, P->srow, P->amap, ms, P->sptr, P->lanes,
+                               P->col16, P->scol, s));
   return RBF_OK;
 }
 
 template <typename XT>
 rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   rbf::CgArgs<XT> a;
-  a.m = P->m;
+  a.m = P->ms;
   a.st[0] = (rbf::CgState<XT>*)vec[0];
   a.st[1] = (rbf::CgState<XT>*)vec[1];
   a.p = (XT*)vec[2];
@@ -428,6 +486,7 @@ int ensure_solver(rbf_plan* P, bool fp32) {
   if (!P->xhi) {
     GET(P->xhi, m);
     GET(P->r64, m);
+    GET(P->g_s, m);
     GET(P->sc, 1);
     GET(P->part_it, 12 * rbf::kCgMaxBlocks);
     GET(P->part_ref, 6 * rbf::kCgMaxBlocks);
@@ -442,8 +501,11 @@ int ensure_solver(rbf_plan* P, bool fp32) {
     }
   }
   if (!P->host_sc) {
-    HIPCHK(hipHostMalloc((void**)&P->host_sc, sizeof(rbf::CgScalars), hipHostMallocDefault));
+    P->host_sc = pinned_acquire();
+    if (!P->host_sc) return fail(RBF_ERR_OOM, "pinned host allocation failed");
   }
+  for (hipEvent_t& e : P->snap_ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return RBF_OK;
 }
 
@@ -487,14 +549,19 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     P->pending.push_back({2, -1, e0, e1});
   }
   void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
-  HIPCHK(rbf::launch_finalize(P->m, P->active, P->sptr, P->lanes, P->lower_cnt, P->diag,
-                              P->lambda_rel,
-                              P->lam, fp32, val, dinv, P->dinv64, s));
+  HIPCHK(rbf::launch_finalize(P->m, P->active, P->ms, P->srow, P->sptr, P->lanes, P->lower_cnt,
+                              P->diag, P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64, s));
   return RBF_OK;
 }
 
 // Reliable-update Jacobi-PCG (see cg_kernels.hip).  Returns a status; the
 // float64 solution is left in P->xhi.
+//
+// Iterations are launched in chunks of check_every, each followed by a copy
+// of the scalars into one of two pinned slots and an event.  The next chunk
+// is always queued before the host waits on the previous one, so the GPU
+// never idles on a convergence check; launches after a raised flag return at
+// entry.  Launches never exceed the iteration budget.
 template <typename VT, typename XT>
 int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_solve_opts& o,
            int64_t* iters, int64_t* updates, bool allow_stall_exit) {
@@ -508,24 +575,84 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   A.col16 = P->col16;
   A.val = val;
   A.lanes = P->lanes;
-  HIPCHK(rbf::cg_setup<XT>(a, P->active, P->g, o.rtol, o.reliable_delta, s));
+  HIPCHK(rbf::cg_setup<XT>(a, P->g_s, o.rtol, o.reliable_delta, s));
   // start: float64 residual of the initial x on state buffer 0, direction reset
-  HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, 0, 1, 1, s));
+  HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g_s, 0, 1, 1, s));
   // every refresh moves the state to the other buffer, as every iteration does
   int64_t refreshes = 1;
   const int64_t base_iter = *iters;
-  bool fixed = true;  // the next iteration takes its scalars from the refresh
+  const int64_t budget = std::max<int64_t>(o.max_iter - base_iter, 0);
+  int64_t launched = 0;  // iterations launched since the start (>= executed)
+  bool fixed = true;     // the next launch takes its scalars from the refresh
   double last_true = -1.0;
   int stalls = 0;
+
+  // queue one chunk and its snapshot into slot `slot`; false if none is left
+  auto enqueue = [&](int slot, bool* queued) -> int {
+    *queued = false;
+    const int64_t chunk = std::min<int64_t>(budget - launched, o.check_every);
+    if (chunk <= 0) return RBF_OK;
+    for (int64_t it = 0; it < chunk; ++it) {
+      const int q = (int)((launched + refreshes) & 1);
+      // every fourth launch carries start/stop events when timing is on
+      const bool timed = P->prof_on && (it & 3) == 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = P->event();
+        e1 = P->event();
+        if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
+      }
+      HIPCHK(rbf::cg_iterate<VT, XT>(a, A, q, fixed ? 1 : 0, e0, e1, s));
+      if (timed) P->pending.push_back({0, base_iter + launched, e0, e1});
+      fixed = false;
+      ++launched;
+    }
+    HIPCHK(hipMemcpyAsync(P->host_sc + slot, P->sc, sizeof(rbf::CgScalars),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(P->snap_ev[slot], s));
+    *queued = true;
+    return RBF_OK;
+  };
+  auto wait_slot = [&](int slot, rbf::CgScalars* h) -> int {
+    HIPCHK(hipEventSynchronize(P->snap_ev[slot]));
+    *h = P->host_sc[slot];
+    return RBF_OK;
+  };
+
+  int cur = 0;
+  bool cur_q = false;
+  int rc = enqueue(cur, &cur_q);
+  if (rc) return rc;
   for (;;) {
-    int rc = read_scalars(P);
-    if (rc) return rc;
-    const rbf::CgScalars h = *P->host_sc;
+    rbf::CgScalars h;
+    if (cur_q) {
+      bool next_q = false;
+      rc = enqueue(cur ^ 1, &next_q);
+      if (rc) return rc;
+      rc = wait_slot(cur, &h);
+      if (rc) return rc;
+      if (h.done == 0 && next_q) {
+        *iters = base_iter + h.iter;
+        if (P->prof_on) P->resolve(*iters, false);
+        cur ^= 1;
+        continue;
+      }
+      // a flag is up (or the budget is spent): the other chunk has run its
+      // course too, take the latest state
+      if (next_q) {
+        rc = wait_slot(cur ^ 1, &h);
+        if (rc) return rc;
+      }
+    } else {
+      // nothing was queued: the budget was spent before any launch
+      rc = read_scalars(P);
+      if (rc) return rc;
+      h = *P->host_sc;
+    }
     *iters = base_iter + h.iter;
-    // the buffer holding the latest state follows the executed iteration
-    // count (launches after a raised flag return at entry)
+    // every queued launch has run by now
+    if (P->prof_on) P->resolve(*iters, true);
     const int q = (int)((h.iter + refreshes) & 1);
-    if (P->prof_on) P->resolve(*iters);
     if (h.done == 3) return RBF_OK;
     if (h.done == 2) return fail(RBF_ERR_BREAKDOWN, "CG breakdown after %lld iterations",
                                  (long long)h.iter);
@@ -536,34 +663,21 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
         stalls = 0;
       }
       last_true = h.rr_true;
-      HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, q, q ^ 1, 0, s));
+      HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g_s, q, q ^ 1, 0, s));
       ++refreshes;
       *updates += 1;
       fixed = true;
-      continue;
-    }
-    if (*iters >= o.max_iter) {
-      HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g, q, q ^ 1, 1, s));
-      rc = read_scalars(P);
+      launched = h.iter;  // every queued launch has run; later ones returned at entry
+      cur = 0;
+      rc = enqueue(cur, &cur_q);
       if (rc) return rc;
-      return P->host_sc->done == 3 ? RBF_OK : RBF_WARN_MAXITER;
+      if (cur_q) continue;
     }
-    const int64_t left = o.max_iter - *iters;
-    const int chunk = (int)std::min<int64_t>(left, o.check_every);
-    for (int it = 0; it < chunk; ++it) {
-      const int qi = (int)((h.iter + it + refreshes) & 1);
-      // every fourth launch carries start/stop events when timing is on
-      const bool timed = P->prof_on && (it & 3) == 0;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (timed) {
-        e0 = P->event();
-        e1 = P->event();
-        if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
-      }
-      HIPCHK(rbf::cg_iterate<VT, XT>(a, A, qi, (fixed && it == 0) ? 1 : 0, e0, e1, s));
-      if (timed) P->pending.push_back({0, *iters + it, e0, e1});
-    }
-    fixed = false;
+    // iteration budget spent: the float64 residual decides
+    HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g_s, q, q ^ 1, 1, s));
+    rc = read_scalars(P);
+    if (rc) return rc;
+    return P->host_sc->done == 3 ? RBF_OK : RBF_WARN_MAXITER;
   }
 }
 
@@ -724,7 +838,9 @@ int rbf_system_export(const rbf_plan* P, double* val_upper_h, double* g_h, doubl
   const int64_t m = P->m;
   if (val_upper_h) {
     std::vector<int64_t> rp(m + 1), sp(P->nslices + 1);
-    std::vector<int32_t> low(m);
+    std::vector<int32_t> low(m), amap(m);
+    HIPCHK(hipMemcpyAsync(amap.data(), P->amap, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                          P->stream));
     std::vector<double> v64;
     std::vector<float> v32;
     HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (m + 1),
@@ -746,7 +862,7 @@ int rbf_system_export(const rbf_plan* P, double* val_upper_h, double* g_h, doubl
     int64_t pos = 0;
     for (int64_t j = 0; j < m; ++j)
       for (int64_t e = rp[j] + low[j]; e < rp[j + 1]; ++e) {
-        const int64_t e4 = rbf::sell_pos(sp.data(), P->lanes, j, e - rp[j]);
+        const int64_t e4 = rbf::sell_pos(sp.data(), P->lanes, amap[j], e - rp[j]);
         val_upper_h[pos++] = P->prec == RBF_PREC_FP64 ? v64[e4] : (double)v32[e4];
       }
   }
@@ -774,10 +890,28 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   int rc = ensure_solver(P, fp32);
   if (rc) return rc;
   hipStream_t s = P->stream;
+  if (P->ms == 0) {
+    // no centre has a support: every coefficient is 0, nothing to solve
+    HIPCHK(hipMemsetAsync(coeffs, 0, sizeof(double) * P->m, s));
+    double lam = 0.0;
+    HIPCHK(hipMemcpyAsync(&lam, P->lam, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+      info->iterations = 0;
+      info->reliable_updates = 0;
+      info->rel_residual = 0.0;
+      info->lambda = lam;
+      info->precision = P->prec;
+      info->status = RBF_OK;
+    }
+    return RBF_OK;
+  }
+  // the solver works on the active centres (rows in order)
+  HIPCHK(rbf::launch_gather(P->g, P->srow, P->ms, P->g_s, s));
   if (o.warm_start)
-    HIPCHK(hipMemcpyAsync(P->xhi, coeffs, sizeof(double) * P->m, hipMemcpyDeviceToDevice, s));
+    HIPCHK(rbf::launch_gather(coeffs, P->srow, P->ms, P->xhi, s));
   else
-    HIPCHK(hipMemsetAsync(P->xhi, 0, sizeof(double) * P->m, s));
+    HIPCHK(hipMemsetAsync(P->xhi, 0, sizeof(double) * P->ms, s));
   int64_t iters = 0, updates = 0;
   int used = P->prec;
   if (fp32) {
@@ -802,7 +936,7 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
     rc = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters, &updates, false);
   }
   if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;
-  HIPCHK(hipMemcpyAsync(coeffs, P->xhi, sizeof(double) * P->m, hipMemcpyDeviceToDevice, s));
+  HIPCHK(rbf::launch_scatter_rows(P->xhi, P->amap, P->m, coeffs, s));
   const int rcr = read_scalars(P);
   if (rcr) return rcr;
   double lam = 0.0;
@@ -853,7 +987,7 @@ int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double
 int rbf_profile(rbf_plan* P, int32_t enable) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   HIPCHK(hipStreamSynchronize(P->stream));
-  P->resolve(INT64_MAX);
+  P->resolve(INT64_MAX, true);
   for (int k = 0; k < 3; ++k) {
     P->prof_launches[k] = 0;
     P->prof_ms[k] = 0.0;
@@ -865,7 +999,7 @@ int rbf_profile(rbf_plan* P, int32_t enable) {
 int rbf_profile_read(rbf_plan* P, int32_t kernel, int64_t* launches, double* total_ms) {
   if (!P || kernel < 0 || kernel > 2) return fail(RBF_ERR_INVALID, "bad plan or kernel id");
   HIPCHK(hipStreamSynchronize(P->stream));
-  P->resolve(INT64_MAX);
+  P->resolve(INT64_MAX, true);
   if (launches) *launches = P->prof_launches[kernel];
   if (total_ms) *total_ms = P->prof_ms[kernel];
   return RBF_OK;

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
         for (int u = 0; u < kAsmWaves; ++u) sum += red[u][lane + kWave * t];
         const T v = (T)sum;
         const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
-        val[sell_pos(sptr, lanes, j, e - row_ptr[j])] = v;
+        val[sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j])] = v;
         const int32_t l = lcol[t];
         if (l == (int32_t)j) {
           diag[j] = (double)v;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
             const int64_t mid = (lo + hi) >> 1;
             if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
           }
-          val[sell_pos(sptr, lanes, l, lo - row_ptr[l])] = v;
+          val[sell_pos(sptr, lanes, P.amap[l], lo - row_ptr[l])] = v;
         }
       }
     }
@@ -221,23 +221,18 @@ __global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__
 // Adds lambda to the stored diagonal and forms the Jacobi inverse diagonal
 // from the value actually stored.
 template <typename T>
-__global__ void k_add_ridge(int64_t m, const uint8_t* __restrict__ active,
+__global__ void k_add_ridge(int64_t ms, const int32_t* __restrict__ srow,
                             const int64_t* __restrict__ sptr, int lanes,
                             const int32_t* __restrict__ lower_cnt, const double* __restrict__ lam,
                             T* __restrict__ val, T* __restrict__ dinv,
                             double* __restrict__ dinv64) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  if (!active[j]) {
-    dinv[j] = (T)0;
-    dinv64[j] = 0.0;
-    return;
-  }
-  const int64_t e = sell_pos(sptr, lanes, j, lower_cnt[j]);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ms) return;
+  const int64_t e = sell_pos(sptr, lanes, k, lower_cnt[srow[k]]);
   const T v = (T)((double)val[e] + lam[0]);
   val[e] = v;
-  dinv[j] = (T)1 / v;
-  dinv64[j] = 1.0 / (double)v;
+  dinv[k] = (T)1 / v;
+  dinv64[k] = 1.0 / (double)v;
 }
 
 template <int DIM, typename T>
@@ -285,20 +280,21 @@ hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* 
                                         g, diag, s);
 }
 
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* sptr, int lanes,
-                           const int32_t* lower_cnt, const double* diag, double lambda_rel,
-                           double* lam, bool fp32, void* val, void* dinv, double* dinv64,
-                           hipStream_t s) {
+hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,
+                           const int64_t* sptr, int lanes, const int32_t* lower_cnt,
+                           const double* diag, double lambda_rel, double* lam, bool fp32,
+                           void* val, void* dinv, double* dinv64, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ridge_value, dim3(1), dim3(kRed), 0, s, diag, active, m, lambda_rel, lam);
+  if (ms <= 0) return hipGetLastError();
   const int bs = 256;
-  const dim3 grid((unsigned)((m + bs - 1) / bs));
+  const dim3 grid((unsigned)((ms + bs - 1) / bs));
   if (fp32)
-    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, m, active, sptr, lanes, lower_cnt,
+    hipLaunchKernelGGL(k_add_ridge<float>, grid, dim3(bs), 0, s, ms, srow, sptr, lanes, lower_cnt,
                        (const double*)lam, (float*)val, (float*)dinv, dinv64);
   else
-    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, m, active, sptr, lanes, lower_cnt,
-                       (const double*)lam, (double*)val, (double*)dinv, dinv64);
+    hipLaunchKernelGGL(k_add_ridge<double>, grid, dim3(bs), 0, s, ms, srow, sptr, lanes,
+                       lower_cnt, (const double*)lam, (double*)val, (double*)dinv, dinv64);
   return hipGetLastError();
 }
 

@@ -478,15 +478,14 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(CgScalars* __
   }
 }
 
-// Start of a solve: inactive coefficients zeroed, x_lo, p and both state
-// buffers cleared (s = 0), d = D^-1 in both.
+// Start of a solve: x_lo, p and both state buffers cleared (s = 0), d = D^-1
+// in both.
 template <typename XT>
-__global__ void k_cg_clear(int64_t m, const uint8_t* __restrict__ active, const XT* __restrict__ dinv,
-                           double* __restrict__ xhi, XT* __restrict__ xlo, XT* __restrict__ p,
-                           CgState<XT>* __restrict__ s0, CgState<XT>* __restrict__ s1) {
+__global__ void k_cg_clear(int64_t m, const XT* __restrict__ dinv, XT* __restrict__ xlo,
+                           XT* __restrict__ p, CgState<XT>* __restrict__ s0,
+                           CgState<XT>* __restrict__ s1) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
-  if (!active[j]) xhi[j] = 0.0;
   xlo[j] = (XT)0;
   p[j] = (XT)0;
   CgState<XT> t;
@@ -641,12 +640,12 @@ hipError_t cg_refresh(const CgArgs<XT>& a, const CgMatrix& A, const double* g, i
 }
 
 template <typename XT>
-hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
-                    double delta, hipStream_t s) {
+hipError_t cg_setup(const CgArgs<XT>& a, const double* g, double rtol, double delta,
+                    hipStream_t s) {
   const int bs = 256;
   const dim3 eg((unsigned)((a.m + bs - 1) / bs));
-  hipLaunchKernelGGL(k_cg_clear<XT>, eg, dim3(bs), 0, s, a.m, active, a.dinv, a.xhi, a.xlo, a.p,
-                     a.st[0], a.st[1]);
+  hipLaunchKernelGGL(k_cg_clear<XT>, eg, dim3(bs), 0, s, a.m, a.dinv, a.xlo, a.p, a.st[0],
+                     a.st[1]);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kCgLargeBlock), 0, s, a.m, g, a.sc, rtol, delta);
   return hipGetLastError();
 }
@@ -659,9 +658,9 @@ template hipError_t cg_refresh<double, double>(const CgArgs<double>&, const CgMa
                                                const double*, int, int, int, hipStream_t);
 template hipError_t cg_refresh<float, float>(const CgArgs<float>&, const CgMatrix&, const double*,
                                              int, int, int, hipStream_t);
-template hipError_t cg_setup<double>(const CgArgs<double>&, const uint8_t*, const double*, double,
-                                     double, hipStream_t);
-template hipError_t cg_setup<float>(const CgArgs<float>&, const uint8_t*, const double*, double,
-                                    double, hipStream_t);
+template hipError_t cg_setup<double>(const CgArgs<double>&, const double*, double, double,
+                                     hipStream_t);
+template hipError_t cg_setup<float>(const CgArgs<float>&, const double*, double, double,
+                                    hipStream_t);
 
 }  // namespace rbf

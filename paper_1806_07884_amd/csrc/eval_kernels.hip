@@ -44,6 +44,12 @@ __global__ void k_gather(const double* __restrict__ src, const int32_t* __restri
   if (i < n) dst[i] = src[perm[i]];
 }
 
+__global__ void k_scatter_rows(const double* __restrict__ src, const int32_t* __restrict__ amap,
+                               int64_t m, double* __restrict__ dst) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) dst[j] = amap[j] >= 0 ? src[amap[j]] : 0.0;
+}
+
 constexpr int kRed = 256;
 
 __global__ __launch_bounds__(kRed) void k_sq_err(const double* __restrict__ f,
@@ -101,6 +107,15 @@ hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, doub
   const int bs = 256;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, src, perm, n,
                      dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double* src, const int32_t* amap, int64_t m, double* dst,
+                               hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, src,
+                     amap, m, dst);
   return hipGetLastError();
 }
 

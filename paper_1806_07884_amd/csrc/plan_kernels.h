@@ -24,6 +24,7 @@ struct PlanView {
   const double* rho2;     // rho * rho
   const double* irho;     // 1 / rho
   const uint8_t* active;  // centre has >= min_support points
+  const int32_t* amap;    // centre -> row of the solver's system (active centres in order), -1 if inactive
 };
 
 // Orders LDS traffic among the lanes of one wave (no workgroup barrier).
@@ -117,31 +118,43 @@ size_t symbolic_marks_words(int64_t m);
 hipError_t launch_symbolic(const PlanView& P, bool fill, int64_t* full_cnt, int32_t* lower_cnt,
                            const int64_t* row_ptr, int32_t* col, int32_t* err, int32_t* maxdelta,
                            uint32_t* marks, hipStream_t s);
-// Sliced-ELL layout of the solver (see CgMatrix): slice lengths and sizes,
-// then the column deltas at their positions.
-hipError_t launch_slice_lengths(const int64_t* row_ptr, int64_t m, int lanes, int64_t nslices,
-                                int32_t* slen, int64_t* ssize, hipStream_t s);
-hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, int64_t m,
-                            const int64_t* sptr, int lanes, bool col16, void* cols,
-                            hipStream_t s);
+// Rows of the solver's system: the active centres in order.  pos (m + 1
+// int64, scratch of a scan with `temp` of scan_temp_bytes(m + 1) bytes) ends
+// with pos[m] = number of solver rows; amap[j] = row of centre j or -1;
+// srow[k] = centre of row k (room for m entries).
+hipError_t launch_solver_rows(const uint8_t* active, int64_t m, int64_t* pos, void* temp,
+                              int32_t* amap, int32_t* srow, hipStream_t s);
+// Sliced-ELL layout of the solver (see CgMatrix) over its ms rows: slice
+// lengths and sizes, then the column deltas (in solver rows) at their
+// positions.
+hipError_t launch_slice_lengths(const int64_t* row_ptr, const int32_t* srow, int64_t ms, int lanes,
+                                int64_t nslices, int32_t* slen, int64_t* ssize, hipStream_t s);
+hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, const int32_t* srow,
+                            const int32_t* amap, int64_t ms, const int64_t* sptr, int lanes,
+                            bool col16, void* cols, hipStream_t s);
 
 }  // namespace rbf
 
 namespace rbf {
 // assemble_kernels.hip
 // Values go to the solver's sliced-ELL layout (sptr, lanes): entry e of row j
-// of the CSR pattern sits at sell_pos(sptr, lanes, j, e - row_ptr[j]).
+// of the CSR pattern sits at sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j]).
 hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
                            const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s);
-hipError_t launch_finalize(int64_t m, const uint8_t* active, const int64_t* sptr, int lanes,
-                           const int32_t* lower_cnt, const double* diag, double lambda_rel,
-                           double* lam, bool fp32, void* val, void* dinv, double* dinv64,
-                           hipStream_t s);
+// lambda from the diagonals of the m centres, then, over the ms solver rows,
+// the diagonal entries + lambda and the Jacobi scales dinv[k] (in solver rows).
+hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,
+                           const int64_t* sptr, int lanes, const int32_t* lower_cnt,
+                           const double* diag, double lambda_rel, double* lam, bool fp32,
+                           void* val, void* dinv, double* dinv64, hipStream_t s);
 // eval_kernels.hip
 hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, double* dst,
                          hipStream_t s);
+// dst[j] = amap[j] >= 0 ? src[amap[j]] : 0 for j < m.
+hipError_t launch_scatter_rows(const double* src, const int32_t* amap, int64_t m, double* dst,
+                               hipStream_t s);
 hipError_t launch_eval(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
                        const double* rho2_s, const double* irho_s, double* out, hipStream_t s);
 int sq_err_blocks(int64_t n);

@@ -300,9 +300,31 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   }
 }
 
-// Sliced-ELL geometry: entries per row of every slice (longest row of the
-// slice rounded up to a multiple of L) and the slice's size S * slen.
-__global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr, int64_t m, int lanes,
+// pos[j] = 1 for an active centre, 0 otherwise (pos[m] = 0), scanned next.
+__global__ void k_active_flags(const uint8_t* __restrict__ active, int64_t m,
+                               int64_t* __restrict__ pos) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  pos[j] = (j < m && active[j]) ? 1 : 0;
+}
+
+__global__ void k_solver_rows(const uint8_t* __restrict__ active, const int64_t* __restrict__ pos,
+                              int64_t m, int32_t* __restrict__ amap, int32_t* __restrict__ srow) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  if (active[j]) {
+    amap[j] = (int32_t)pos[j];
+    srow[pos[j]] = (int32_t)j;
+  } else {
+    amap[j] = -1;
+  }
+}
+
+// Sliced-ELL geometry over the solver rows: entries per row of every slice
+// (longest row of the slice rounded up to a multiple of L) and the slice's
+// size S * slen.
+__global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr,
+                                const int32_t* __restrict__ srow, int64_t ms, int lanes,
                                 int64_t nslices, int32_t* __restrict__ slen,
                                 int64_t* __restrict__ ssize) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -314,8 +336,9 @@ __global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr, int64_t m, 
   const int64_t rows = kWave / lanes;
   int64_t mx = 0;
   for (int64_t i = 0; i < rows; ++i) {
-    const int64_t j = s * rows + i;
-    if (j < m) {
+    const int64_t k = s * rows + i;
+    if (k < ms) {
+      const int64_t j = srow[k];
       const int64_t len = row_ptr[j + 1] - row_ptr[j];
       mx = len > mx ? len : mx;
     }
@@ -325,41 +348,59 @@ __global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr, int64_t m, 
   ssize[s] = mx * rows;
 }
 
-// Column deltas l - j of every stored entry at its sliced-ELL position, one
-// wave per row (padding stays 0 from the allocation).
+// Column deltas amap[l] - k of every stored entry of solver row k at its
+// sliced-ELL position, one wave per row (padding stays 0 from the
+// allocation).  Every column of the pattern is an active centre.
 template <typename CT>
 __global__ __launch_bounds__(256) void k_sell_cols(const int64_t* __restrict__ row_ptr,
-                                                   const int32_t* __restrict__ col, int64_t m,
+                                                   const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ srow,
+                                                   const int32_t* __restrict__ amap, int64_t ms,
                                                    const int64_t* __restrict__ sptr, int lanes,
                                                    CT* __restrict__ cols) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (j >= m) return;
+  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (k >= ms) return;
+  const int64_t j = srow[k];
   const int64_t a = row_ptr[j], n = row_ptr[j + 1] - a;
-  for (int64_t k = lane; k < n; k += kWave) cols[sell_pos(sptr, lanes, j, k)] = (CT)(col[a + k] - (int32_t)j);
+  for (int64_t e = lane; e < n; e += kWave)
+    cols[sell_pos(sptr, lanes, k, e)] = (CT)(amap[col[a + e]] - (int32_t)k);
 }
 
 }  // namespace
 
-hipError_t launch_slice_lengths(const int64_t* row_ptr, int64_t m, int lanes, int64_t nslices,
-                                int32_t* slen, int64_t* ssize, hipStream_t s) {
+hipError_t launch_solver_rows(const uint8_t* active, int64_t m, int64_t* pos, void* temp,
+                              int32_t* amap, int32_t* srow, hipStream_t s) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_slice_lengths, dim3((unsigned)((nslices + 1 + bs - 1) / bs)), dim3(bs), 0,
-                     s, row_ptr, m, lanes, nslices, slen, ssize);
+  hipLaunchKernelGGL(k_active_flags, dim3((unsigned)((m + 1 + bs - 1) / bs)), dim3(bs), 0, s,
+                     active, m, pos);
+  hipError_t e = exclusive_scan(pos, pos, m + 1, temp, s);
+  if (e != hipSuccess) return e;
+  if (m > 0)
+    hipLaunchKernelGGL(k_solver_rows, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, active,
+                       (const int64_t*)pos, m, amap, srow);
   return hipGetLastError();
 }
 
-hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, int64_t m,
-                            const int64_t* sptr, int lanes, bool col16, void* cols,
-                            hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((m + 3) / 4));
+hipError_t launch_slice_lengths(const int64_t* row_ptr, const int32_t* srow, int64_t ms, int lanes,
+                                int64_t nslices, int32_t* slen, int64_t* ssize, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_slice_lengths, dim3((unsigned)((nslices + 1 + bs - 1) / bs)), dim3(bs), 0,
+                     s, row_ptr, srow, ms, lanes, nslices, slen, ssize);
+  return hipGetLastError();
+}
+
+hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, const int32_t* srow,
+                            const int32_t* amap, int64_t ms, const int64_t* sptr, int lanes,
+                            bool col16, void* cols, hipStream_t s) {
+  if (ms <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((ms + 3) / 4));
   if (col16)
-    hipLaunchKernelGGL(k_sell_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, m, sptr, lanes,
-                       (int16_t*)cols);
+    hipLaunchKernelGGL(k_sell_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, srow, amap, ms,
+                       sptr, lanes, (int16_t*)cols);
   else
-    hipLaunchKernelGGL(k_sell_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, m, sptr, lanes,
-                       (int32_t*)cols);
+    hipLaunchKernelGGL(k_sell_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, srow, amap, ms,
+                       sptr, lanes, (int32_t*)cols);
   return hipGetLastError();
 }
 

@@ -106,8 +106,9 @@ hipError_t cg_iterate(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, 
 template <typename VT, typename XT>
 hipError_t cg_refresh(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q, int q_prev,
                       int restart, hipStream_t s);
+// x_lo, p and both state buffers cleared (s = 0, d = D^-1); scalars from g.
 template <typename XT>
-hipError_t cg_setup(const CgArgs<XT>& a, const uint8_t* active, const double* g, double rtol,
-                    double delta, hipStream_t s);
+hipError_t cg_setup(const CgArgs<XT>& a, const double* g, double rtol, double delta,
+                    hipStream_t s);
 
 }  // namespace rbf
