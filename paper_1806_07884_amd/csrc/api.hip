@@ -263,8 +263,10 @@ struct rbf_plan {
 
 namespace {
 
+// Grid hash of `count` points: sorted by cell (with sub_order, by sub-cell
+// within a cell as well), sorted copy, permutation and cell starts.
 int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, int32_t* perm,
-              int32_t* cell_start) {
+              int32_t* cell_start, bool sub_order) {
   uint32_t *ka, *kb;
   int32_t *va, *vb;
   void* tmp;
@@ -272,14 +274,17 @@ int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, 
   if (!P->get(&ka, count) || !P->get(&kb, count) || !P->get(&va, count) || !P->get(&vb, count) ||
       !(tmp = P->alloc_bytes(tb)))
     return fail(RBF_ERR_OOM, "hash workspace allocation failed");
-  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, ka, va, P->stream));
+  // sub-cell bits below the cell id while the shifted ids still fit 32 bits
+  int sub = sub_order ? 2 * P->dim : 0;
+  if ((((int64_t)P->grid.ncell + 1) << sub) > (int64_t)UINT32_MAX) sub = 0;
+  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, sub, ka, va, P->stream));
   int bits = 1;
-  while ((int64_t(1) << bits) <= (int64_t)P->grid.ncell) ++bits;
+  while ((int64_t(1) << bits) <= ((int64_t)P->grid.ncell << sub) + ((int64_t(1) << sub) - 1)) ++bits;
   bool in_alt = false;
   HIPCHK(rbf::radix_sort_pairs(ka, va, kb, vb, count, bits, tmp, P->stream, &in_alt));
   const uint32_t* keys = in_alt ? kb : ka;
   const int32_t* vals = in_alt ? vb : va;
-  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, cell_start, P->stream));
+  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, sub, cell_start, P->stream));
   HIPCHK(hipMemcpyAsync(perm, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice,
                         P->stream));
   HIPCHK(rbf::launch_gather_soa(coords, perm, count, P->dim, sorted, P->stream));
@@ -368,12 +373,12 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   GET(P->ps, dim * n);
   GET(P->pperm, n);
   GET(P->pcs, ncell + 2);
-  int rc = hash_into(P, d->points, n, P->ps, P->pperm, P->pcs);
+  int rc = hash_into(P, d->points, n, P->ps, P->pperm, P->pcs, true);
   if (rc) return rc;
   GET(P->ctr_s, dim * m);
   GET(P->cperm, m);
   GET(P->ccs, ncell + 2);
-  rc = hash_into(P, P->ctr, m, P->ctr_s, P->cperm, P->ccs);
+  rc = hash_into(P, P->ctr, m, P->ctr_s, P->cperm, P->ccs, false);
   if (rc) return rc;
   GET(P->rho2_s, m);
   GET(P->irho_s, m);
@@ -542,8 +547,11 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
     HIPCHK(hipEventRecord(e0, s));
   }
-  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->hs, P->row_ptr, P->lower_cnt, P->col, P->sptr,
-                              P->lanes, val, P->g, P->diag, s));
+  // rows wider than one wave on average: the grouped path (see assemble_kernels.hip)
+  const double upper_mean =
+      (double)(P->nnz_full + P->ms) / (2.0 * (double)std::max<int64_t>(P->ms, 1));
+  HIPCHK(rbf::launch_assemble(v, phi, fp32, upper_mean > 64.0, P->hs, P->row_ptr, P->lower_cnt,
+                              P->col, P->sptr, P->lanes, val, P->g, P->diag, s));
   if (P->prof_on) {
     HIPCHK(hipEventRecord(e1, s));
     P->pending.push_back({2, -1, e0, e1});
@@ -587,10 +595,16 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   double last_true = -1.0;
   int stalls = 0;
 
+  // Latest snapshot's ||r||^2 and trigger: once the residual is within a
+  // small factor of the trigger, chunks shrink, so that fewer launches are
+  // queued past the iteration that raises the flag (each costs a few us).
+  double seen_rr = -1.0, seen_trig = 0.0;
   // queue one chunk and its snapshot into slot `slot`; false if none is left
   auto enqueue = [&](int slot, bool* queued) -> int {
     *queued = false;
-    const int64_t chunk = std::min<int64_t>(budget - launched, o.check_every);
+    const bool near = seen_rr >= 0.0 && seen_rr <= 3.0 * seen_trig;
+    const int64_t step = near ? std::min<int64_t>(o.check_every, 8) : o.check_every;
+    const int64_t chunk = std::min<int64_t>(budget - launched, step);
     if (chunk <= 0) return RBF_OK;
     for (int64_t it = 0; it < chunk; ++it) {
       const int q = (int)((launched + refreshes) & 1);
@@ -631,6 +645,8 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       if (rc) return rc;
       rc = wait_slot(cur, &h);
       if (rc) return rc;
+      seen_rr = h.rr;
+      seen_trig = h.trigger2;
       if (h.done == 0 && next_q) {
         *iters = base_iter + h.iter;
         if (P->prof_on) P->resolve(*iters, false);
@@ -667,6 +683,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       ++refreshes;
       *updates += 1;
       fixed = true;
+      seen_rr = -1.0;     // the refresh sets a new trigger
       launched = h.iter;  // every queued launch has run; later ones returned at entry
       cur = 0;
       rc = enqueue(cur, &cur_q);

@@ -14,6 +14,16 @@
 // the solver reads, so the stored matrix is exactly symmetric.  A is never
 // materialised: phi is evaluated on the fly.
 //
+// Plans whose rows are wider than one wave (more than 64 upper columns on
+// average) take a grouped path:
+// the staged points are taken 64 at a time (consecutive, so spatially close:
+// points are sorted by sub-cell within a hash cell); a group's bounding ball
+// selects the columns whose support can reach it; those columns are handed
+// to the lanes, and each lane runs through the group's points for its column,
+// accumulating into the wave's LDS accumulator of that column.  Groups a
+// column cannot reach contribute no term, so the sums are the same as when
+// every lane visits every point.
+//
 // FP64 variant: float64 phi and float64 accumulation.
 // FP32 variant: squared distance and support test in float64 (the pattern is
 // fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
@@ -25,6 +35,7 @@ namespace {
 
 constexpr int kAsmChunk = 256;
 constexpr int kSlots = 4;  // columns per lane in one pass: 256 per pass
+constexpr int kCols = kWave * kSlots;
 
 template <typename T>
 struct Acc;
@@ -54,6 +65,25 @@ __device__ __forceinline__ float scaled_r<float>(double s, double irho) {
 
 constexpr int kAsmWaves = 4;
 
+// Plain-data copy of an accumulator (LDS variables take no initialisers).
+template <typename T>
+struct AccPod {
+  T s, c;
+};
+__device__ __forceinline__ Acc<double> from_pod(const AccPod<double>& p) {
+  Acc<double> a;
+  a.s = p.s;
+  return a;
+}
+__device__ __forceinline__ Acc<float> from_pod(const AccPod<float>& p) {
+  Acc<float> a;
+  a.k.s = p.s;
+  a.k.c = p.c;
+  return a;
+}
+__device__ __forceinline__ AccPod<double> to_pod(const Acc<double>& a) { return {a.s, 0.0}; }
+__device__ __forceinline__ AccPod<float> to_pod(const Acc<float>& a) { return {a.k.s, a.k.c}; }
+
 template <typename T>
 __device__ __forceinline__ double partial_value(const Acc<T>& a);
 template <>
@@ -65,20 +95,29 @@ __device__ __forceinline__ double partial_value<float>(const Acc<float>& a) {
   return (double)a.k.s - (double)a.k.c;
 }
 
-template <int DIM, int PHI, typename T>
+template <int DIM, int PHI, typename T, bool GROUPED>
 __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
     PlanView P, const double* __restrict__ hs, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ lower_cnt, const int32_t* __restrict__ col,
     const int64_t* __restrict__ sptr, int lanes, T* __restrict__ val, double* __restrict__ g,
     double* __restrict__ diag) {
-  __shared__ double sp[kAsmWaves][DIM][kAsmChunk];
-  __shared__ int32_t sidx[kAsmWaves][kAsmChunk];
-  __shared__ T sphi[kAsmWaves][kAsmChunk];
-  __shared__ double red[kAsmWaves][kWave * kSlots];
+  // the grouped path stages half as many points per chunk (its LDS holds the
+  // pass's columns and accumulators too)
+  constexpr int kChunk = GROUPED ? kAsmChunk / 2 : kAsmChunk;
+  __shared__ double sp[kAsmWaves][DIM][kChunk];
+  __shared__ int32_t sidx[kAsmWaves][kChunk];
+  __shared__ T sphi[kAsmWaves][kChunk];
+  __shared__ double red[GROUPED ? 1 : kAsmWaves][GROUPED ? 1 : kCols];
   __shared__ double gred[kAsmWaves];
+  // grouped path: the pass's columns, per-wave accumulators and column lists
+  __shared__ double cxs[GROUPED ? DIM : 1][GROUPED ? kCols : 1];
+  __shared__ double crs[GROUPED ? kCols : 1], cr2s[GROUPED ? kCols : 1], cirs[GROUPED ? kCols : 1];
+  __shared__ AccPod<T> cacc[GROUPED ? kAsmWaves : 1][GROUPED ? kCols : 1];
+  __shared__ int16_t nlist[GROUPED ? kAsmWaves : 1][GROUPED ? kCols : 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
+  const uint64_t lt = lanemask_lt();
   if (!P.active[j]) {
     if (threadIdx.x == 0) {
       g[j] = 0.0;
@@ -108,16 +147,31 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
       const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
       ok[t] = t < nslot && e < e1;
       lcol[t] = ok[t] ? col[e] : 0;
+      if (!GROUPED) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) xl[t][d] = ok[t] ? P.ctr[d * P.m + lcol[t]] : 0.0;
-      r2l[t] = ok[t] ? P.rho2[lcol[t]] : 0.0;
-      irl[t] = ok[t] ? P.irho[lcol[t]] : 0.0;
+        for (int d = 0; d < DIM; ++d) xl[t][d] = ok[t] ? P.ctr[d * P.m + lcol[t]] : 0.0;
+        r2l[t] = ok[t] ? P.rho2[lcol[t]] : 0.0;
+        irl[t] = ok[t] ? P.irho[lcol[t]] : 0.0;
+      }
     }
     const bool first = cb == 0;
+    const int ncol = (int)(R - cb < kCols ? R - cb : kCols);
+    if (GROUPED) {
+      for (int t = threadIdx.x; t < ncol; t += kWave * kAsmWaves) {
+        const int32_t l = col[e0 + cb + t];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) cxs[d][t] = P.ctr[d * P.m + l];
+        crs[t] = P.rho[l];
+        cr2s[t] = P.rho2[l];
+        cirs[t] = P.irho[l];
+      }
+      for (int t = lane; t < ncol; t += kWave) cacc[w][t] = AccPod<T>{(T)0, (T)0};
+      __syncthreads();
+    }
     T* wphi = sphi[w];
     const int32_t* widx = sidx[w];
-    double(*wsp)[kAsmChunk] = sp[w];
-    stream_support_part<DIM, kAsmChunk>(P, xj, r2j, w, kAsmWaves, wsp, sidx[w], [&](int np) {
+    double(*wsp)[kChunk] = sp[w];
+    stream_support_part<DIM, kChunk>(P, xj, r2j, w, kAsmWaves, wsp, sidx[w], [&](int np) {
       // phi_kj of the chunk's points, and their share of g_j
       for (int q = lane; q < np; q += kWave) {
         double p[DIM];
@@ -128,23 +182,84 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
         if (first) gacc.add(phij * (T)hs[widx[q]]);
       }
       wave_sync();
-      for (int q = 0; q < np; ++q) {
-        double p[DIM];
+      if constexpr (!GROUPED) {
+        for (int q = 0; q < np; ++q) {
+          double p[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
-        const T phij = wphi[q];
+          for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+          const T phij = wphi[q];
 #pragma unroll
-        for (int t = 0; t < kSlots; ++t) {
-          if (t < nslot && ok[t]) {
-            const double s = sqdist<DIM>(p, xl[t]);
-            if (s < r2l[t]) acc[t].add(phij * wendland<PHI, T>(scaled_r<T>(s, irl[t])));
+          for (int t = 0; t < kSlots; ++t) {
+            if (t < nslot && ok[t]) {
+              const double s = sqdist<DIM>(p, xl[t]);
+              if (s < r2l[t]) acc[t].add(phij * wendland<PHI, T>(scaled_r<T>(s, irl[t])));
+            }
           }
         }
+        return;
+      } else {
+      for (int g0 = 0; g0 < np; g0 += kWave) {
+        const int n = np - g0 < kWave ? np - g0 : kWave;
+        // bounding ball of the group: centre its first point, radius the
+        // farthest of its points (rounded up)
+        double c0[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) c0[d] = wsp[d][g0];
+        float rg = 0.f;
+        if (lane < n) {
+          double p[DIM];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) p[d] = wsp[d][g0 + lane];
+          rg = (float)__builtin_sqrt(sqdist<DIM>(p, c0)) * 1.0001f + 1e-30f;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) rg = fmaxf(rg, __shfl_xor(rg, off, kWave));
+        // the columns whose support can reach the group
+        int nn = 0;
+        for (int t0 = 0; t0 < ncol; t0 += kWave) {
+          const int t = t0 + lane;
+          bool need = false;
+          if (t < ncol) {
+            double xl0[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xl0[d] = cxs[d][t];
+            const double reach = (crs[t] + (double)rg) * (1.0 + 1e-9);
+            need = sqdist<DIM>(xl0, c0) < reach * reach;
+          }
+          const uint64_t msk = __ballot(need);
+          if (need) nlist[w][nn + __popcll(msk & lt)] = (int16_t)t;
+          nn += __popcll(msk);
+        }
+        wave_sync();
+        for (int k0 = 0; k0 < nn; k0 += kWave) {
+          const int k = k0 + lane;
+          if (k < nn) {
+            const int t = nlist[w][k];
+            double xt[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xt[d] = cxs[d][t];
+            const double r2t = cr2s[t], irt = cirs[t];
+            Acc<T> a = from_pod(cacc[w][t]);
+            for (int q = g0; q < g0 + n; ++q) {
+              double p[DIM];
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+              const double s = sqdist<DIM>(p, xt);
+              if (s < r2t) a.add(wphi[q] * wendland<PHI, T>(scaled_r<T>(s, irt)));
+            }
+            cacc[w][t] = to_pod(a);
+          }
+        }
+        wave_sync();
+      }
       }
     });
-    // add the waves' partial sums in wave order
+    // add the waves' partial sums in wave order (the grouped path's sums are
+    // already in LDS)
+    if constexpr (!GROUPED) {
 #pragma unroll
-    for (int t = 0; t < kSlots; ++t) red[w][lane + kWave * t] = partial_value<T>(acc[t]);
+      for (int t = 0; t < kSlots; ++t) red[w][lane + kWave * t] = partial_value<T>(acc[t]);
+    }
     __syncthreads();
     if (w == 0) {
 #pragma unroll
@@ -152,7 +267,12 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
         if (!ok[t]) continue;
         double sum = 0.0;
 #pragma unroll
-        for (int u = 0; u < kAsmWaves; ++u) sum += red[u][lane + kWave * t];
+        for (int u = 0; u < kAsmWaves; ++u) {
+          if constexpr (GROUPED)
+            sum += partial_value<T>(from_pod(cacc[u][lane + kWave * t]));
+          else
+            sum += red[u][lane + kWave * t];
+        }
         const T v = (T)sum;
         const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
         val[sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j])] = v;
@@ -235,49 +355,60 @@ __global__ void k_add_ridge(int64_t ms, const int32_t* __restrict__ srow,
   dinv64[k] = 1.0 / (double)v;
 }
 
-template <int DIM, typename T>
-hipError_t assemble_dim(const PlanView& P, int phi, const double* hs, const int64_t* row_ptr,
-                        const int32_t* lower_cnt, const int32_t* col, const int64_t* sptr,
-                        int lanes, T* val, double* g, double* diag, hipStream_t s) {
+template <int DIM, typename T, bool GROUPED>
+void assemble_phi(const PlanView& P, int phi, const double* hs, const int64_t* row_ptr,
+                  const int32_t* lower_cnt, const int32_t* col, const int64_t* sptr, int lanes,
+                  T* val, double* g, double* diag, hipStream_t s) {
   const dim3 grid((unsigned)P.m), block(kWave * kAsmWaves);
   switch (phi) {
     case 0:
-      hipLaunchKernelGGL((k_assemble<DIM, 0, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, sptr, lanes, val, g, diag);
+      hipLaunchKernelGGL((k_assemble<DIM, 0, T, GROUPED>), grid, block, 0, s, P, hs, row_ptr,
+                         lower_cnt, col, sptr, lanes, val, g, diag);
       break;
     case 1:
-      hipLaunchKernelGGL((k_assemble<DIM, 1, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, sptr, lanes, val, g, diag);
+      hipLaunchKernelGGL((k_assemble<DIM, 1, T, GROUPED>), grid, block, 0, s, P, hs, row_ptr,
+                         lower_cnt, col, sptr, lanes, val, g, diag);
       break;
     case 2:
-      hipLaunchKernelGGL((k_assemble<DIM, 2, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, sptr, lanes, val, g, diag);
+      hipLaunchKernelGGL((k_assemble<DIM, 2, T, GROUPED>), grid, block, 0, s, P, hs, row_ptr,
+                         lower_cnt, col, sptr, lanes, val, g, diag);
       break;
     default:
-      hipLaunchKernelGGL((k_assemble<DIM, 3, T>), grid, block, 0, s, P, hs, row_ptr, lower_cnt,
-                         col, sptr, lanes, val, g, diag);
+      hipLaunchKernelGGL((k_assemble<DIM, 3, T, GROUPED>), grid, block, 0, s, P, hs, row_ptr,
+                         lower_cnt, col, sptr, lanes, val, g, diag);
       break;
   }
+}
+
+template <int DIM, typename T>
+hipError_t assemble_dim(const PlanView& P, int phi, bool grouped, const double* hs,
+                        const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
+                        const int64_t* sptr, int lanes, T* val, double* g, double* diag,
+                        hipStream_t s) {
+  if (grouped)
+    assemble_phi<DIM, T, true>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, val, g, diag, s);
+  else
+    assemble_phi<DIM, T, false>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, val, g, diag, s);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
+hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
                            const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s) {
   if (P.m <= 0) return hipSuccess;
   if (P.dim == 2) {
-    return fp32 ? assemble_dim<2, float>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (float*)val,
-                                         g, diag, s)
-                : assemble_dim<2, double>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes,
-                                          (double*)val, g, diag, s);
+    return fp32 ? assemble_dim<2, float>(P, phi, grouped, hs, row_ptr, lower_cnt, col, sptr,
+                                         lanes, (float*)val, g, diag, s)
+                : assemble_dim<2, double>(P, phi, grouped, hs, row_ptr, lower_cnt, col, sptr,
+                                          lanes, (double*)val, g, diag, s);
   }
-  return fp32 ? assemble_dim<3, float>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (float*)val, g,
-                                       diag, s)
-              : assemble_dim<3, double>(P, phi, hs, row_ptr, lower_cnt, col, sptr, lanes, (double*)val,
-                                        g, diag, s);
+  return fp32 ? assemble_dim<3, float>(P, phi, grouped, hs, row_ptr, lower_cnt, col, sptr, lanes,
+                                       (float*)val, g, diag, s)
+              : assemble_dim<3, double>(P, phi, grouped, hs, row_ptr, lower_cnt, col, sptr, lanes,
+                                        (double*)val, g, diag, s);
 }
 
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,

@@ -22,9 +22,10 @@ size_t radix_temp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
                             int64_t n, int key_bits, void* temp, hipStream_t s, bool* in_alt);
 
-// cell_start[c] = first sorted index whose key >= c, for c in [0, ncell + 1];
-// cell_start[ncell + 1] = n.  Keys must be sorted and <= ncell.
-hipError_t cell_starts(const uint32_t* sorted_keys, int64_t n, int32_t ncell, int32_t* cell_start,
-                       hipStream_t s);
+// cell_start[c] = first sorted index whose key >> shift >= c, for c in
+// [0, ncell + 1]; cell_start[ncell + 1] = n.  Keys must be sorted and
+// key >> shift <= ncell.
+hipError_t cell_starts(const uint32_t* sorted_keys, int64_t n, int32_t ncell, int shift,
+                       int32_t* cell_start, hipStream_t s);
 
 }  // namespace rbf

@@ -1,6 +1,8 @@
 // Plan data shared by the plan, assembly, solve and evaluation kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace rbf {
@@ -40,8 +42,10 @@ __device__ __forceinline__ void wave_sync() {
 // pieces; the points of this piece that lie in the support are compacted in
 // sorted order (coordinates in sp, sorted positions in sidx unless it is
 // null) and handed to
-// `consume(np)`.  Only wave-level synchronisation is used, so the waves of a
-// block may take different numbers of chunks.
+// `consume(np)`.  A consumer that returns bool stops the stream by returning
+// true (the value must be uniform over the wave).  Only wave-level
+// synchronisation is used, so the waves of a block may take different
+// numbers of chunks.
 template <int DIM, int kChunk, typename Consume>
 __device__ __forceinline__ void stream_support_part(const PlanView& P, const double* xj, double r2,
                                                     int part, int nparts,
@@ -73,7 +77,11 @@ __device__ __forceinline__ void stream_support_part(const PlanView& P, const dou
     for (int i0 = s0; i0 < s1; i0 += kWave) {
       if (np > kChunk - kWave) {
         wave_sync();
-        consume(np);
+        if constexpr (std::is_same<decltype(consume(np)), bool>::value) {
+          if (consume(np)) return;
+        } else {
+          consume(np);
+        }
         wave_sync();
         np = 0;
       }
@@ -104,8 +112,10 @@ __device__ __forceinline__ void stream_support_part(const PlanView& P, const dou
 
 hipError_t launch_minmax(const double* a, int64_t n, double* partial_min, double* partial_max,
                          int* partial_bad, int nblocks, double* out3, hipStream_t s);
-hipError_t launch_cell_keys(int dim, const Grid& G, const double* x, int64_t n, uint32_t* keys,
-                            int32_t* idx, hipStream_t s);
+// Cell keys (shifted left by `sub` bits with the sub-cell Morton code below,
+// see k_cell_keys) and identity indices.
+hipError_t launch_cell_keys(int dim, const Grid& G, const double* x, int64_t n, int sub,
+                            uint32_t* keys, int32_t* idx, hipStream_t s);
 hipError_t launch_gather_soa(const double* src, const int32_t* perm, int64_t n, int dim,
                              double* dst, hipStream_t s);
 hipError_t launch_radius_tables(const double* rho_in, double rho, int64_t m, double* rho_c,
@@ -139,7 +149,8 @@ namespace rbf {
 // assemble_kernels.hip
 // Values go to the solver's sliced-ELL layout (sptr, lanes): entry e of row j
 // of the CSR pattern sits at sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j]).
-hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, const double* hs,
+// grouped: the grouped path (rows wider than one wave on average).
+hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
                            const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s);

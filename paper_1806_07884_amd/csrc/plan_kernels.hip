@@ -76,8 +76,12 @@ __global__ void k_minmax_final(const double* __restrict__ pmin, const double* __
   out[2] = (double)bad;
 }
 
+// Sort key of a point: its cell id, and with sub = 2 DIM, below it the
+// Morton code of its sub-cell on a 4^DIM subdivision of the cell, so that
+// points of a cell come in a spatially coherent order.  Points outside the box
+// get ncell << sub.
 template <int DIM>
-__global__ void k_cell_keys(Grid G, const double* __restrict__ x, int64_t n,
+__global__ void k_cell_keys(Grid G, const double* __restrict__ x, int64_t n, int sub,
                             uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -86,7 +90,22 @@ __global__ void k_cell_keys(Grid G, const double* __restrict__ x, int64_t n,
   for (int d = 0; d < DIM; ++d) p[d] = x[d * n + i];
   int c[3];
   const bool in = cell_of<DIM>(G, p, c);
-  keys[i] = in ? (uint32_t)cell_id<DIM>(G, c) : (uint32_t)G.ncell;
+  uint32_t key = in ? (uint32_t)cell_id<DIM>(G, c) : (uint32_t)G.ncell;
+  if (sub) {
+    uint32_t code = 0;
+    if (in) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double f = (p[d] - G.lo[d]) * G.inv_cs - (double)c[d];
+        int q = (int)(f * 4.0);
+        q = q < 0 ? 0 : (q > 3 ? 3 : q);
+        code |= (uint32_t)(q & 1) << d;
+        code |= (uint32_t)(q >> 1) << (DIM + d);
+      }
+    }
+    key = (key << sub) | code;
+  }
+  keys[i] = key;
   idx[i] = (int32_t)i;
 }
 
@@ -154,8 +173,11 @@ constexpr int kCandWords = kMaxCand / 32;
 // from the centre hash in a fixed order.  Count mode: the row's candidate
 // points are split among the waves (as in the assembly); each wave streams
 // the supported points of its piece and marks every candidate with one of
-// them in its support (LDS bit set, order-independent).  A wave stops once
-// every candidate is marked.  The marks are saved as a bitmask per row, and
+// them in its support (LDS bit set, order-independent).  The points are
+// taken 64 at a time; a group is scanned only for the unmarked candidates
+// whose ball can reach the group's bounding ball, one candidate per lane,
+// each stopping at its first hit.  A wave stops once every candidate is
+// marked.  The marks are saved as a bitmask per row, and
 // the full-row and lower-part sizes and the largest |l - j| are written.
 // Fill mode rebuilds the same candidate list, reads the saved marks and
 // writes the marked columns in ascending order.
@@ -168,6 +190,7 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   __shared__ int32_t surv[kMaxCand];
   __shared__ uint32_t word[kCandWords];
   __shared__ double sp[kSymWaves][DIM][kSymChunk];
+  __shared__ int16_t glist[kSymWaves][kMaxCand];
   __shared__ int nc_s;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -233,26 +256,64 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   if (!FILL) {
     stream_support_part<DIM, kSymChunk>(P, xj, P.rho2[j], w, kSymWaves, sp[w], nullptr,
                                         [&](int np) {
-      int open = 0;
-      for (int t = lane; t < nc; t += kWave) {
-        if ((word[t >> 5] >> (t & 31)) & 1u) continue;
-        const int l = cand[t];
-        double xl[DIM];
+      // groups of 64 consecutive staged points (spatially close: points are
+      // sorted by sub-cell within a hash cell); only the unmarked candidates
+      // whose ball can reach a group's bounding ball scan that group
+      for (int g0 = 0; g0 < np; g0 += kWave) {
+        const int n = np - g0 < kWave ? np - g0 : kWave;
+        double c0[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
-        const double r2l = P.rho2[l];
-        bool hit = false;
-        for (int q = 0; q < np; ++q) {
+        for (int d = 0; d < DIM; ++d) c0[d] = sp[w][d][g0];
+        float rg = 0.f;
+        if (lane < n) {
           double p[DIM];
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q];
-          if (sqdist<DIM>(p, xl) < r2l) {
-            hit = true;
-            break;
+          for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][g0 + lane];
+          rg = (float)__builtin_sqrt(sqdist<DIM>(p, c0)) * 1.0001f + 1e-30f;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) rg = fmaxf(rg, __shfl_xor(rg, off, kWave));
+        int nn = 0;
+        for (int t0 = 0; t0 < nc; t0 += kWave) {
+          const int t = t0 + lane;
+          bool need = false;
+          if (t < nc && !((word[t >> 5] >> (t & 31)) & 1u)) {
+            const int l = cand[t];
+            double xl[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
+            const double reach = (P.rho[l] + (double)rg) * (1.0 + 1e-9);
+            need = sqdist<DIM>(xl, c0) < reach * reach;
+          }
+          const uint64_t msk = __ballot(need);
+          if (need) glist[w][nn + __popcll(msk & lt)] = (int16_t)t;
+          nn += __popcll(msk);
+        }
+        wave_sync();
+        for (int k0 = 0; k0 < nn; k0 += kWave) {
+          const int k = k0 + lane;
+          if (k < nn) {
+            const int t = glist[w][k];
+            const int l = cand[t];
+            double xl[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
+            const double r2l = P.rho2[l];
+            for (int q = g0; q < g0 + n; ++q) {
+              double p[DIM];
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q];
+              if (sqdist<DIM>(p, xl) < r2l) {
+                atomicOr(&word[t >> 5], 1u << (t & 31));
+                break;
+              }
+            }
           }
         }
-        if (hit) atomicOr(&word[t >> 5], 1u << (t & 31)); else ++open;
+        wave_sync();
       }
+      int open = 0;
+      for (int t = lane; t < nc; t += kWave) open += ((word[t >> 5] >> (t & 31)) & 1u) ? 0 : 1;
       return wave_sum_int(open) == 0;
     });
     __syncthreads();
@@ -413,15 +474,15 @@ hipError_t launch_minmax(const double* a, int64_t n, double* partial_min, double
   return hipGetLastError();
 }
 
-hipError_t launch_cell_keys(int dim, const Grid& G, const double* x, int64_t n, uint32_t* keys,
-                            int32_t* idx, hipStream_t s) {
+hipError_t launch_cell_keys(int dim, const Grid& G, const double* x, int64_t n, int sub,
+                            uint32_t* keys, int32_t* idx, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int bs = 256;
   const dim3 grid((unsigned)((n + bs - 1) / bs));
   if (dim == 2)
-    hipLaunchKernelGGL(k_cell_keys<2>, grid, dim3(bs), 0, s, G, x, n, keys, idx);
+    hipLaunchKernelGGL(k_cell_keys<2>, grid, dim3(bs), 0, s, G, x, n, sub, keys, idx);
   else
-    hipLaunchKernelGGL(k_cell_keys<3>, grid, dim3(bs), 0, s, G, x, n, keys, idx);
+    hipLaunchKernelGGL(k_cell_keys<3>, grid, dim3(bs), 0, s, G, x, n, sub, keys, idx);
   return hipGetLastError();
 }
 

@@ -197,12 +197,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 }
 
 __global__ void k_cell_starts(const uint32_t* __restrict__ keys, int64_t n, int32_t ncell,
-                              int32_t* __restrict__ cell_start) {
+                              int shift, int32_t* __restrict__ cell_start) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
   // boundary between sorted position i-1 and i: cells (prev, cur] start at i
-  const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
-  const int64_t cur = i == n ? (int64_t)ncell + 1 : (int64_t)keys[i];
+  const int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> shift);
+  const int64_t cur = i == n ? (int64_t)ncell + 1 : (int64_t)(keys[i] >> shift);
   for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = (int32_t)i;
 }
 
@@ -254,12 +254,12 @@ hipError_t radix_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, i
   return hipGetLastError();
 }
 
-hipError_t cell_starts(const uint32_t* sorted_keys, int64_t n, int32_t ncell, int32_t* cell_start,
-                       hipStream_t s) {
+hipError_t cell_starts(const uint32_t* sorted_keys, int64_t n, int32_t ncell, int shift,
+                       int32_t* cell_start, hipStream_t s) {
   const int64_t threads = n + 1;
   const int bs = 256;
   hipLaunchKernelGGL(k_cell_starts, dim3((unsigned)((threads + bs - 1) / bs)), dim3(bs), 0, s,
-                     sorted_keys, n, ncell, cell_start);
+                     sorted_keys, n, ncell, shift, cell_start);
   return hipGetLastError();
 }
 
