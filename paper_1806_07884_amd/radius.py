@@ -25,6 +25,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
+from . import _lib as L
 from . import binding as B
 
 # sweep radii: balls covering c_s grid centres on average
@@ -35,6 +36,22 @@ def sweep_radii(spacing: float, dim: int, cover: Sequence[float] = SWEEP_COVER) 
     if dim == 2:
         return np.array([spacing * math.sqrt(c / math.pi) for c in cover])
     return np.array([spacing * (3.0 * c / (4.0 * math.pi)) ** (1.0 / 3.0) for c in cover])
+
+
+def initial_params(rng: np.random.Generator) -> np.ndarray:
+    """Glorot-uniform weights and zero biases for the 16-64-64-1 network, in
+    the parameter layout of the library (W1 input-major, b1, W2, b2, W3, b3);
+    the draw is host-side and handed to the kernels as their input."""
+    n_in, n_h = L.MLP_INPUTS, 64
+
+    def glorot(fan_in, fan_out, count):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-a, a, size=count)
+    parts = [glorot(n_in, n_h, n_in * n_h), np.zeros(n_h), glorot(n_h, n_h, n_h * n_h),
+             np.zeros(n_h), glorot(n_h, 1, n_h), np.zeros(1)]
+    theta = np.concatenate(parts)
+    assert theta.size == L.MLP_PARAMS
+    return theta
 
 
 def _dev(a) -> torch.Tensor:
