@@ -162,6 +162,36 @@ def test_values_fp64_and_fp32(rbf, phi, dim):
     say(f"max scaled error fp64 {e64:.2e} fp32 {e32:.2e}")
 
 
+# Rows wider than one wave take the assembly's grouped path (columns listed
+# per group of 64 spatially ordered points); two cases pass the row in more
+# than one block of 256 columns.
+@pytest.mark.parametrize("dim,g,rho_cells,n,seed", [
+    (2, 24, 5.5, 20000, 0),   # upper rows 121 columns on average, up to 187
+    (2, 24, 8.0, 12000, 1),   # 202 on average, up to 342: two column blocks
+    (3, 10, 3.0, 20000, 2),   # 199 on average, up to 404
+])
+def test_values_grouped_path(rbf, dim, g, rho_cells, n, seed):
+    rng = np.random.default_rng(60 + seed)
+    ctr = sd.grid_centers(g, dim)
+    rho = rho_cells / (g - 1)
+    pts = np.concatenate([rng.random((dim, n // 2)),
+                          sd.gaussian_mixture_points(rng, n - n // 2, dim, 4)], axis=1)
+    h = np.cos(5 * pts[0]) * pts[1] + 0.1 * rng.standard_normal(n)
+    say("grouped values", dim, g, rho_cells, n)
+    ne = orc.normal_equations(pts, h, ctr, rho, "w31", lambda_rel=1e-5)
+    plan = rbf.rbf_fit_plan(dev(pts), dev(ctr), rho=rho, lambda_rel=1e-5)
+    check_pattern(rbf, plan, ne)
+    info = rbf.rbf_plan_info(plan)
+    upper_mean = (info["nnz_full"] + info["n_active"]) / (2 * info["n_active"])
+    say("upper row mean", upper_mean)
+    assert upper_mean > 64
+    rbf.rbf_assemble(plan, "w31", "fp64", dev(h))
+    e64 = check_values(rbf, plan, ne, h, 1e-12)
+    rbf.rbf_assemble(plan, "w31", "fp32", dev(h))
+    e32 = check_values(rbf, plan, ne, h, 2e-6)
+    say(f"max scaled error fp64 {e64:.2e} fp32 {e32:.2e}")
+
+
 def test_deterministic(rbf):
     p = sd.make_problem("terrain2d", scale=1 / 64)
     outs = []
