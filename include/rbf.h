@@ -166,8 +166,11 @@ int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, do
 /* Solve (B + lambda I) c = g by Jacobi-preconditioned CG in the precision of
  * the last rbf_assemble.  coeffs: device [M] float64 output (input too when
  * opts->warm_start); inactive centres get 0.  opts NULL: rtol 1e-10,
- * max_iter 100000, check_every 32, reliable_delta 0.1.  Blocks the host every
- * check_every iterations to read the residual.  Returns OK, WARN_MAXITER
+ * max_iter 100000, check_every 32, reliable_delta 0.1.  Iterations are queued
+ * in chunks of check_every (at most 8 once the residual nears the next
+ * trigger), each followed by a copy of the residual to host memory; the host
+ * waits on a chunk's copy only after the next chunk is queued, so launches
+ * queued past convergence return at entry.  Returns OK, WARN_MAXITER
  * (best iterate kept), WARN_FALLBACK (mixed precision stalled and FP64 took
  * over), ERR_BREAKDOWN, ERR_INVALID (not assembled), ERR_HIP.  info may be
  * NULL. */

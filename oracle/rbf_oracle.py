@@ -12,6 +12,9 @@ using Radial Basis Functions: A Comparative Study":
 * the Wendland basis functions with truncated power (1 - r)_+          (Table 2, eq. 18)
 * support found by a strict range query ||x_q - xi_j|| < 1/alpha       (Algorithm 1)
 * the COO sparse product y[row] += data * x[col]                        (Section 4)
+* linear polynomial reproduction: f(x) = sum_j c_j phi_j(x) + a^T x + a_0 and
+  the bordered normal equations [[A^T A, A^T P], [P^T A, P^T P]] (c, k) =
+  (A^T h, P^T h) with P_i = (x_i^T, 1)                                   (Section 3, eq. 6-10)
 
 Every routine is the plain definition: the design matrix is built explicitly,
 B and g are library sparse products of it, and the solve is a Cholesky
@@ -33,12 +36,17 @@ design notes of the repository):
 * ridge: the solved system is (B + lambda I) c = g with
   lambda = lambda_rel * mean(diag B over active centres);
 * phi_{3,2} = (1-r)^6 (35 r^2 + 18 r + 3) completes the Wendland family of
-  Table 2 (same family, smoothness C^4).
+  Table 2 (same family, smoothness C^4);
+* polynomial with ridge: the ridge is added to the A^T A block only (the
+  polynomial coefficients are not penalised); inactive centres have no row in
+  Q = A^T P, every point is a row of P.
 
 Parity: pinned.  Basis closed forms, brute-force supports, dense least
 squares (QR), symmetry / positive definiteness, the normal-equation invariant,
 the interpolation special case and the worked COO example of Section 4 pin
-every function here (see tests/test_oracle_*.py).
+every function here; the polynomial part is pinned by exact reproduction of
+linear data, the QR solution of eq. 9 and the Table 4 density with a
+polynomial (see tests/test_oracle_*.py).
 """
 from __future__ import annotations
 
@@ -229,30 +237,119 @@ def normal_equations(points, values, centers, rho, phi: str, min_support: int = 
 # ---------------------------------------------------------------------------
 # Direct solve (the paper leaves the solver open; the oracle takes Cholesky)
 # ---------------------------------------------------------------------------
-def solve(ne: NormalEquations, dense_limit: int = 4096) -> np.ndarray:
-    """c solving (B + lambda I) c = g on the active set by Cholesky; 0 elsewhere.
+def _active_solver(ne: NormalEquations, dense_limit: int):
+    """Cholesky of (B + lambda I) on the active set; returns a solve(rhs) function.
 
-    Dense Cholesky up to ``dense_limit`` active centres, banded Cholesky above
-    (band taken from the pattern in the original centre order).
+    Dense up to ``dense_limit`` active centres, banded above (band taken from
+    the pattern in the original centre order).
     """
     act = np.nonzero(ne.active)[0]
     full = ne.full_matrix(with_ridge=True)[act][:, act].tocsr()
-    rhs = ne.g[act]
-    c = np.zeros(ne.m)
-    if act.size == 0:
-        return c
     if act.size <= dense_limit:
         cf = sla.cho_factor(full.toarray(), lower=False)
-        c[act] = sla.cho_solve(cf, rhs)
-        return c
+        return lambda rhs: sla.cho_solve(cf, rhs)
     coo = full.tocoo()
     up = coo.col >= coo.row
     bw = int(np.max(coo.col[up] - coo.row[up]))
     ab = np.zeros((bw + 1, act.size))
     ab[bw + coo.row[up] - coo.col[up], coo.col[up]] = coo.data[up]
     cb = sla.cholesky_banded(ab, lower=False, check_finite=False)
-    c[act] = sla.cho_solve_banded((cb, False), rhs, check_finite=False)
+    return lambda rhs: sla.cho_solve_banded((cb, False), rhs, check_finite=False)
+
+
+def solve(ne: NormalEquations, dense_limit: int = 4096) -> np.ndarray:
+    """c solving (B + lambda I) c = g on the active set by Cholesky; 0 elsewhere."""
+    act = np.nonzero(ne.active)[0]
+    c = np.zeros(ne.m)
+    if act.size == 0:
+        return c
+    c[act] = _active_solver(ne, dense_limit)(ne.g[act])
     return c
+
+
+# ---------------------------------------------------------------------------
+# Linear polynomial reproduction (Section 3, eq. 6-10)
+# ---------------------------------------------------------------------------
+def poly_basis(points) -> np.ndarray:
+    """P (N x (d+1)): row i is (x_i^T, 1), the linear polynomial basis of eq. 9."""
+    pts = np.asarray(points, dtype=np.float64)
+    return np.vstack([pts, np.ones(pts.shape[1])]).T
+
+
+@dataclasses.dataclass
+class PolySystem:
+    """The blocks that eq. 10 adds to the normal equations.
+
+    Q = A^T P restricted to active centres (inactive rows are zero), C = P^T P,
+    e = P^T h.  The bordered matrix is [[B + lambda I, Q], [Q^T, C]] and the
+    unknown vector (c, k) with k = (a, a_0) of eq. 7.
+    """
+    Q: np.ndarray   # float64 [M][d+1]
+    C: np.ndarray   # float64 [d+1][d+1]
+    e: np.ndarray   # float64 [d+1]
+
+    def bordered_matrix(self, ne: NormalEquations) -> sp.csr_matrix:
+        """The full matrix of eq. 10 over the active centres, ridge included."""
+        act = np.nonzero(ne.active)[0]
+        B = ne.full_matrix(with_ridge=True)[act][:, act]
+        Qa = sp.csr_matrix(self.Q[act])
+        return sp.bmat([[B, Qa], [Qa.T, sp.csr_matrix(self.C)]]).tocsr()
+
+
+def poly_system(ne: NormalEquations, points, values) -> PolySystem:
+    """Q = A^T P, C = P^T P and e = P^T h (eq. 10) as plain products."""
+    P = poly_basis(points)
+    h = np.asarray(values, dtype=np.float64)
+    Q = np.zeros((ne.m, P.shape[1]))
+    act = np.nonzero(ne.active)[0]
+    if act.size:
+        Q[act] = ne.A[:, act].T @ P
+    return PolySystem(Q=Q, C=P.T @ P, e=P.T @ h)
+
+
+def solve_poly(ne: NormalEquations, ps: PolySystem, dense_limit: int = 4096):
+    """(c, k) solving eq. 10 with the ridge on the A^T A block; c is 0 off the active set.
+
+    Small systems: Cholesky of the whole bordered matrix.  Large ones: the same
+    system by block elimination, (B + lambda I) Y = [g, Q] by Cholesky, then the
+    (d+1) x (d+1) Schur complement C - Q^T Y_Q for k, and c = Y_g - Y_Q k.
+    """
+    act = np.nonzero(ne.active)[0]
+    nk = ps.C.shape[0]
+    c = np.zeros(ne.m)
+    if act.size == 0:
+        return c, np.linalg.solve(ps.C, ps.e)
+    if act.size + nk <= dense_limit:
+        K = ps.bordered_matrix(ne).toarray()
+        z = sla.cho_solve(sla.cho_factor(K, lower=False), np.concatenate([ne.g[act], ps.e]))
+        c[act] = z[:act.size]
+        return c, z[act.size:]
+    Qa = ps.Q[act]
+    Y = _active_solver(ne, dense_limit)(np.column_stack([ne.g[act], Qa]))
+    S = ps.C - Qa.T @ Y[:, 1:]
+    k = np.linalg.solve(S, ps.e - Qa.T @ Y[:, 0])
+    c[act] = Y[:, 0] - Y[:, 1:] @ k
+    return c, k
+
+
+def lstsq_dense_poly(points, values, centers, rho, phi: str, lam: float = 0.0):
+    """min ||A c + P k - h||^2 + lam ||c||^2 by dense QR of [A P] (eq. 9, no normal equations)."""
+    A = design_matrix(points, centers, rho, phi).toarray()
+    P = poly_basis(points)
+    m = A.shape[1]
+    AP = np.hstack([A, P])
+    h = np.asarray(values, dtype=np.float64)
+    if lam != 0.0:
+        AP = np.vstack([AP, np.hstack([np.sqrt(lam) * np.eye(m), np.zeros((m, P.shape[1]))])])
+        h = np.concatenate([h, np.zeros(m)])
+    q, r = np.linalg.qr(AP)
+    z = sla.solve_triangular(r, q.T @ h)
+    return z[:m], z[m:]
+
+
+def evaluate_poly(queries, centers, rho, phi: str, coeffs, k) -> np.ndarray:
+    """f(y) of eq. 6 with the linear polynomial of eq. 7: the RBF sum plus a^T y + a_0."""
+    return evaluate(queries, centers, rho, phi, coeffs) + poly_basis(queries) @ np.asarray(k)
 
 
 def lstsq_dense(points, values, centers, rho, phi: str, lam: float = 0.0) -> np.ndarray:
