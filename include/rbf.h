@@ -11,6 +11,11 @@
  *
  * with A_ij = phi(||x_i - xi_j|| / rho_j) a Wendland CS-RBF (Table 2), and
  * solving (B + lambda I) c = g by Jacobi-preconditioned conjugate gradients.
+ * Optionally the approximant carries a linear polynomial a^T x + a_0
+ * (Section 3, eq. 6-7) and the solved system is the bordered one of eq. 10,
+ *
+ *     [ B + lambda I   A^T P ] [ c ]   [ A^T h ]
+ *     [ P^T A          P^T P ] [ k ] = [ P^T h ],   P_i = (x_i^T, 1), k = (a, a_0).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -88,7 +93,10 @@ typedef struct {
   int32_t min_support;          /* centres with fewer supported points are
                                    inactive: no row/column, c_j = 0 (>= 1) */
   double lambda_rel;            /* ridge: lambda = lambda_rel * mean diag(B) over
-                                   active centres, added to the diagonal (>= 0) */
+                                   active centres, added to the diagonal of B only
+                                   (>= 0) */
+  int32_t polynomial;           /* 0: none; 1: linear polynomial reproduction
+                                   (Section 3): dim + 1 more unknowns k */
 } rbf_plan_desc;
 
 typedef struct {
@@ -107,6 +115,7 @@ typedef struct {
   int64_t solver_entries;       /* stored entries of the solver layout (with padding) */
   int32_t solver_col_bytes;     /* bytes per stored column index (2 or 4) */
   int32_t solver_lanes;         /* lanes per row of the solver layout */
+  int32_t n_poly;               /* dim + 1 with a linear polynomial, else 0 */
 } rbf_plan_stats;
 
 typedef struct {
@@ -153,9 +162,20 @@ int rbf_plan_pattern(const rbf_plan* plan, int64_t* row_ptr_h, int32_t* col_h,
 /* Assemble the values of B and g = A^T h for samples `values` (device [N],
  * caller's point order) with basis `phi` in precision `prec` (Section 5,
  * eq. 11-12: b_jl = sum_k phi_kj phi_kl over the points in both supports),
- * then add the ridge and form the Jacobi preconditioner.  Stream-ordered, does
- * not block.  Errors: INVALID (bad phi/prec, NULL values), HIP. */
+ * then add the ridge and form the Jacobi preconditioner.  With a polynomial
+ * also A^T P, P^T P and P^T h of eq. 10 (float64; internally in the basis
+ * ((x - o) / s, 1), o and s the centre and half-extent of the points'
+ * bounding box, which spans the same functions).  Stream-ordered, does not
+ * block.  Errors: INVALID (bad phi/prec, NULL values), HIP. */
 int rbf_assemble(rbf_plan* plan, rbf_phi phi, rbf_precision prec, const double* values);
+
+/* Copy the polynomial blocks of eq. 10 to host memory, in the paper's basis
+ * P_i = (x_i^T, 1): q_h [M][n_poly] row-major = A^T P (rows of inactive
+ * centres 0), c_h [n_poly][n_poly] = P^T P, e_h [n_poly] = P^T h; float64 as
+ * assembled (a float32 solve uses A^T P rounded to float32).  Any pointer may
+ * be NULL.  Blocks the host.  Errors: INVALID (no polynomial, nothing
+ * assembled). */
+int rbf_poly_export(const rbf_plan* plan, double* q_h, double* c_h, double* e_h);
 
 /* Copy the assembled system to host memory: the upper-CSR values of
  * B + lambda I in the pattern's order (nnz_upper; float32 values widened when
@@ -164,8 +184,12 @@ int rbf_assemble(rbf_plan* plan, rbf_phi phi, rbf_precision prec, const double* 
 int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, double* lambda_h);
 
 /* Solve (B + lambda I) c = g by Jacobi-preconditioned CG in the precision of
- * the last rbf_assemble.  coeffs: device [M] float64 output (input too when
- * opts->warm_start); inactive centres get 0.  opts NULL: rtol 1e-10,
+ * the last rbf_assemble; with a polynomial, the bordered system of eq. 10 by
+ * the same CG, the polynomial unknowns preconditioned by (P^T P)^-1 and
+ * iterated in float64.  coeffs: device [M + n_poly] float64 output (input too
+ * when opts->warm_start): c in the caller's centre order, then k = (a, a_0)
+ * in the paper's basis (x^T, 1); inactive centres get 0.  The residual
+ * ||.|| and ||g|| of the stopping test cover the whole bordered system.  opts NULL: rtol 1e-10,
  * max_iter 100000, check_every 32, reliable_delta 0.1.  Iterations are queued
  * in chunks of check_every (at most 8 once the residual nears the next
  * trigger), each followed by a copy of the residual to host memory; the host
@@ -178,8 +202,9 @@ int rbf_solve(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs, rbf_so
 
 /* Evaluate the approximant (eq. 3) at n_query points: out[q] =
  * sum_j coeffs[j] phi(||y_q - xi_j|| / rho_j) over centres with y_q in their
- * support, basis of the last rbf_assemble (or W31 if none).  queries: device
- * SoA [dim][n_query]; coeffs: device [M]; out: device [n_query].  When
+ * support (plus a^T y_q + a_0 with a polynomial, eq. 6), basis of the last
+ * rbf_assemble (or W31 if none).  queries: device SoA [dim][n_query]; coeffs:
+ * device [M + n_poly] as rbf_solve writes them; out: device [n_query].  When
  * values is not NULL (device [n_query]) the root-mean-square of out - values
  * is written to *rmse_h (blocks the host); otherwise stream-ordered. */
 int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,

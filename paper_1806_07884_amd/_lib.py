@@ -36,7 +36,7 @@ class PlanDesc(ctypes.Structure):
                 ("n_centers", ctypes.c_int64), ("points", ctypes.c_void_p),
                 ("centers", ctypes.c_void_p), ("rho", ctypes.c_double),
                 ("rho_per_center", ctypes.c_void_p), ("min_support", ctypes.c_int32),
-                ("lambda_rel", ctypes.c_double)]
+                ("lambda_rel", ctypes.c_double), ("polynomial", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -47,7 +47,8 @@ class PlanStats(ctypes.Structure):
                 ("density", ctypes.c_double), ("support_total", ctypes.c_int64),
                 ("support_max", ctypes.c_int32), ("row_max", ctypes.c_int32),
                 ("cell_size", ctypes.c_double), ("solver_entries", ctypes.c_int64),
-                ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32)]
+                ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32),
+                ("n_poly", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -81,6 +82,8 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "rbf_system_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "rbf_poly_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "rbf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
                                  ctypes.POINTER(SolveInfo)]),
     "rbf_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,

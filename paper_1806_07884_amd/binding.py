@@ -33,6 +33,7 @@ class Plan:
     def __init__(self):
         self.handle = ctypes.c_void_p()
         self.dim = self.n = self.m = 0
+        self.n_poly = 0       # dim + 1 with a linear polynomial
         self.device = None
         self.stream = None
         self._alloc = None
@@ -71,8 +72,12 @@ def _make_allocator(device: torch.device, stream: torch.cuda.Stream):
 
 def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[float] = None,
                  rho_per_center: Optional[torch.Tensor] = None, min_support: int = 1,
-                 lambda_rel: float = 0.0, stream: Optional[torch.cuda.Stream] = None) -> Plan:
-    """Hash, support counts and the sparsity pattern of B (rbf_fit_plan)."""
+                 lambda_rel: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
+                 polynomial: bool = False) -> Plan:
+    """Hash, support counts and the sparsity pattern of B (rbf_fit_plan).
+
+    polynomial: linear polynomial reproduction (coefficients c, then k = (a, a_0)).
+    """
     _need(points, "points")
     if points.dim() != 2:
         raise ValueError("points must be (dim, N)")
@@ -87,13 +92,14 @@ def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[floa
         raise ValueError("give rho or rho_per_center")
     plan = Plan()
     plan.dim, plan.n, plan.m = int(dim), int(n), int(m)
+    plan.n_poly = int(dim) + 1 if polynomial else 0
     plan.device = points.device
     plan.stream = stream if stream is not None else torch.cuda.current_stream(points.device)
     plan._alloc = _make_allocator(plan.device, plan.stream)
     desc = L.PlanDesc(int(dim), int(n), int(m), points.data_ptr(), centers.data_ptr(),
                       float(rho) if rho is not None else 0.0,
                       rho_per_center.data_ptr() if rho_per_center is not None else None,
-                      int(min_support), float(lambda_rel))
+                      int(min_support), float(lambda_rel), int(bool(polynomial)))
     with torch.cuda.device(plan.device):
         st = L.lib().rbf_fit_plan(ctypes.byref(desc), ctypes.byref(plan._alloc),
                                   plan._stream_handle(), ctypes.byref(plan.handle))
@@ -143,13 +149,26 @@ def rbf_system_export(plan: Plan):
     return val[:info["nnz_upper"]], g, lam.value
 
 
+def rbf_poly_export(plan: Plan):
+    """(A^T P [M][d+1], P^T P, P^T h) of eq. 10 on the host, basis P_i = (x_i^T, 1)."""
+    k = plan.n_poly
+    q = np.zeros((plan.m, k))
+    c = np.zeros((k, k))
+    e = np.zeros(k)
+    with torch.cuda.device(plan.device):
+        L.check(L.lib().rbf_poly_export(plan.handle, q.ctypes.data, c.ctypes.data,
+                                        e.ctypes.data), "rbf_poly_export")
+    return q, c, e
+
+
 def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1e-10,
               max_iter: int = 100000, warm_start: bool = False, check_every: int = 32,
               reliable_delta: float = 0.1):
-    """Jacobi-PCG solve of (B + lambda I) c = g (rbf_solve).  Returns (coeffs, info)."""
+    """Jacobi-PCG solve of (B + lambda I) c = g, or of the bordered system of eq. 10
+    with a polynomial (rbf_solve).  Returns (coeffs [M + n_poly], info)."""
     if coeffs is None:
-        coeffs = torch.zeros(plan.m, dtype=torch.float64, device=plan.device)
-    _need(coeffs, "coeffs", (plan.m,))
+        coeffs = torch.zeros(plan.m + plan.n_poly, dtype=torch.float64, device=plan.device)
+    _need(coeffs, "coeffs", (plan.m + plan.n_poly,))
     opts = L.SolveOpts(float(rtol), int(max_iter), int(bool(warm_start)), int(check_every),
                        float(reliable_delta))
     info = L.SolveInfo()
@@ -165,12 +184,13 @@ def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1
 
 def rbf_eval(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
              out: Optional[torch.Tensor] = None, values: Optional[torch.Tensor] = None):
-    """f at the query points (eq. 3), and the RMSE against `values` when given."""
+    """f at the query points (eq. 3, or eq. 6 with a polynomial), and the RMSE
+    against `values` when given."""
     _need(queries, "queries")
     if queries.dim() != 2 or queries.shape[0] != plan.dim:
         raise ValueError("queries must be (dim, Q)")
     nq = int(queries.shape[1])
-    _need(coeffs, "coeffs", (plan.m,))
+    _need(coeffs, "coeffs", (plan.m + plan.n_poly,))
     if out is None:
         out = torch.empty(nq, dtype=torch.float64, device=plan.device)
     _need(out, "out", (nq,))

@@ -82,6 +82,8 @@ struct rbf_plan {
   int64_t n = 0, m = 0;
   int32_t min_support = 1;
   double lambda_rel = 0.0;
+  int32_t npoly = 0;       // d + 1 with linear polynomial reproduction, else 0
+  rbf::PolyBasis pbasis{};  // its scaled basis (centre and half-extent of the points' box)
   rbf::Grid grid{};
   double cell_size = 0.0;
   double cbox[6] = {0, 0, 0, 0, 0, 0};  // centres' bounding box {min_0, max_0, ...}
@@ -134,8 +136,15 @@ struct rbf_plan {
   double* xhi = nullptr;
   double* r64 = nullptr;
   rbf::CgScalars* sc = nullptr;
-  double* part_it = nullptr;   // [2][6 * kCgMaxBlocks] partials of the iterations
-  double* part_ref = nullptr;  // [6 * kCgMaxBlocks] partials of a refresh
+  double* part_it = nullptr;   // [2][kCgParts * kCgMaxBlocks] partials of the iterations
+  double* part_ref = nullptr;  // [kCgParts * kCgMaxBlocks] partials of a refresh
+  // polynomial block (npoly > 0)
+  double* q64 = nullptr;  // Q = A^T P, [npoly][ms] by solver row
+  float* q32 = nullptr;   // its float32 copy for the mixed solve
+  double* gram_part = nullptr;
+  rbf::PolySys* psys = nullptr;
+  rbf::PolyState* pst = nullptr;  // [2], by state buffer
+  double* xpoly = nullptr;        // [kMaxPoly] polynomial unknowns in the scaled basis
   void* vec64[4] = {};         // state buffers 0 and 1 (4 per row), p, x_lo
   void* vec32[4] = {};
   double* cs_sorted = nullptr;
@@ -336,6 +345,12 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
                                                       : k < 2 * dim ? "point coordinate"
                                                                     : "support radius");
   const double rho_min = host[3 * 2 * dim], rho_max = host[3 * 2 * dim + 1];
+  for (int k = 0; k < 3; ++k) {
+    const double lo = k < dim ? host[3 * (dim + k)] : 0.0, hi = k < dim ? host[3 * (dim + k) + 1] : 0.0;
+    const double half = 0.5 * (hi - lo);
+    P->pbasis.o[k] = 0.5 * (lo + hi);
+    P->pbasis.s[k] = half > 0.0 ? half : 1.0;
+  }
   if (!(rho_min > 0.0)) return fail(RBF_ERR_INVALID, "support radius must be > 0");
 
   // grid: cells of size >= max radius over the centres' box widened by 1.5 cells
@@ -480,9 +495,16 @@ rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   a.r64 = P->r64;
   a.sc = P->sc;
   a.part[0] = P->part_it;
-  a.part[1] = P->part_it + 6 * rbf::kCgMaxBlocks;
+  a.part[1] = P->part_it + rbf::kCgParts * rbf::kCgMaxBlocks;
   a.part_ref = P->part_ref;
   rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
+  a.np = P->npoly;
+  a.Q = P->npoly ? (sizeof(XT) == 4 ? (const XT*)(const void*)P->q32 : (const XT*)(const void*)P->q64)
+                 : nullptr;
+  a.psys = P->psys;
+  a.pst[0] = P->pst;
+  a.pst[1] = P->pst ? P->pst + 1 : nullptr;
+  a.xpoly = P->xpoly;
   return a;
 }
 
@@ -493,8 +515,8 @@ int ensure_solver(rbf_plan* P, bool fp32) {
     GET(P->r64, m);
     GET(P->g_s, m);
     GET(P->sc, 1);
-    GET(P->part_it, 12 * rbf::kCgMaxBlocks);
-    GET(P->part_ref, 6 * rbf::kCgMaxBlocks);
+    GET(P->part_it, 2 * rbf::kCgParts * rbf::kCgMaxBlocks);
+    GET(P->part_ref, rbf::kCgParts * rbf::kCgMaxBlocks);
   }
   void** vec = fp32 ? P->vec32 : P->vec64;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
@@ -559,6 +581,20 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
   HIPCHK(rbf::launch_finalize(P->m, P->active, P->ms, P->srow, P->sptr, P->lanes, P->lower_cnt,
                               P->diag, P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64, s));
+  if (P->npoly) {
+    // the polynomial blocks of eq. 10, phi in the same precision as B and g
+    const int nb = rbf::poly_gram_blocks(P->n);
+    if (!P->psys) {
+      GET(P->q64, (int64_t)P->npoly * std::max<int64_t>(P->ms, 1));
+      GET(P->gram_part, 14 * 1024);
+      GET(P->psys, 1);
+      GET(P->pst, 2);
+      GET(P->xpoly, rbf::kMaxPoly);
+    }
+    if (fp32 && !P->q32) GET(P->q32, (int64_t)P->npoly * std::max<int64_t>(P->ms, 1));
+    HIPCHK(rbf::launch_poly_system(v, phi, P->pbasis, P->ms, P->hs, P->q64,
+                                   fp32 ? P->q32 : nullptr, P->gram_part, nb, P->psys, s));
+  }
   return RBF_OK;
 }
 
@@ -734,6 +770,8 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
     return fail(d->rho > 0.0 ? RBF_ERR_NONFINITE : RBF_ERR_INVALID,
                 "rho must be finite and > 0");
   if (d->min_support < 1) return fail(RBF_ERR_INVALID, "min_support must be >= 1");
+  if (d->polynomial != 0 && d->polynomial != 1)
+    return fail(RBF_ERR_INVALID, "polynomial must be 0 (none) or 1 (linear)");
   if (!(d->lambda_rel >= 0.0 && isfinite(d->lambda_rel)))
     return fail(RBF_ERR_INVALID, "lambda_rel must be finite and >= 0");
   if (allocator && (!allocator->alloc || !allocator->release))
@@ -749,6 +787,7 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
   P->m = d->n_centers;
   P->min_support = d->min_support;
   P->lambda_rel = d->lambda_rel;
+  P->npoly = d->polynomial ? d->dim + 1 : 0;
   const int rc = build_plan(P, d);
   if (rc != RBF_OK) {
     delete P;
@@ -797,6 +836,7 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->solver_entries = P->nsell;
   o->solver_col_bytes = P->col16 ? 2 : 4;
   o->solver_lanes = P->lanes;
+  o->n_poly = P->npoly;
   return RBF_OK;
 }
 
@@ -889,6 +929,62 @@ int rbf_system_export(const rbf_plan* P, double* val_upper_h, double* g_h, doubl
   return RBF_OK;
 }
 
+int rbf_poly_export(const rbf_plan* P, double* q_h, double* c_h, double* e_h) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!P->npoly) return fail(RBF_ERR_INVALID, "the plan has no polynomial");
+  if (P->prec < 0 || !P->psys) return fail(RBF_ERR_INVALID, "nothing assembled");
+  const int np = P->npoly, dim = P->dim;
+  const int64_t m = P->m, ms = P->ms;
+  rbf::PolySys S;
+  std::vector<double> q((size_t)np * std::max<int64_t>(ms, 1));
+  std::vector<int32_t> amap(m);
+  HIPCHK(hipMemcpyAsync(&S, P->psys, sizeof S, hipMemcpyDeviceToHost, P->stream));
+  if (q_h) {
+    if (ms > 0)
+      HIPCHK(hipMemcpyAsync(q.data(), P->q64, sizeof(double) * np * ms, hipMemcpyDeviceToHost,
+                            P->stream));
+    HIPCHK(hipMemcpyAsync(amap.data(), P->amap, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                          P->stream));
+  }
+  HIPCHK(hipStreamSynchronize(P->stream));
+  // the paper's basis (x^T, 1) is the scaled one times T: T[d][d] = s_d,
+  // T[dim][d] = o_d, T[dim][dim] = 1; Q T, T^T C T and T^T e
+  double T[rbf::kMaxPoly][rbf::kMaxPoly] = {};
+  for (int d = 0; d < dim; ++d) {
+    T[d][d] = P->pbasis.s[d];
+    T[dim][d] = P->pbasis.o[d];
+  }
+  T[dim][dim] = 1.0;
+  if (q_h) {
+    for (int64_t j = 0; j < m; ++j) {
+      const int32_t k = amap[j];
+      for (int t = 0; t < np; ++t) {
+        double v = 0.0;
+        if (k >= 0)
+          for (int u = 0; u < np; ++u) v += q[(size_t)u * ms + k] * T[u][t];
+        q_h[j * np + t] = v;
+      }
+    }
+  }
+  if (c_h) {
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b) {
+        double v = 0.0;
+        for (int u = 0; u < np; ++u)
+          for (int w = 0; w < np; ++w) v += T[u][a] * S.C[u][w] * T[w][b];
+        c_h[a * np + b] = v;
+      }
+  }
+  if (e_h) {
+    for (int a = 0; a < np; ++a) {
+      double v = 0.0;
+      for (int u = 0; u < np; ++u) v += T[u][a] * S.e[u];
+      e_h[a] = v;
+    }
+  }
+  return RBF_OK;
+}
+
 int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (!coeffs) return fail(RBF_ERR_INVALID, "coeffs is NULL");
@@ -907,9 +1003,26 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   int rc = ensure_solver(P, fp32);
   if (rc) return rc;
   hipStream_t s = P->stream;
+  if (P->npoly) {
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, &P->psys->bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad)
+      return fail(RBF_ERR_SINGULAR,
+                  "P^T P of the linear polynomial is singular (points on a line or plane)");
+    if (o.warm_start)
+      HIPCHK(rbf::launch_poly_coeffs(coeffs + P->m, P->pbasis, P->dim, false, P->xpoly, s));
+    else
+      HIPCHK(hipMemsetAsync(P->xpoly, 0, sizeof(double) * rbf::kMaxPoly, s));
+  }
   if (P->ms == 0) {
-    // no centre has a support: every coefficient is 0, nothing to solve
+    // no centre has a support: every coefficient is 0, the polynomial (if
+    // any) fits alone
     HIPCHK(hipMemsetAsync(coeffs, 0, sizeof(double) * P->m, s));
+    if (P->npoly) {
+      HIPCHK(rbf::launch_poly_only(P->psys, P->xpoly, s));
+      HIPCHK(rbf::launch_poly_coeffs(P->xpoly, P->pbasis, P->dim, true, coeffs + P->m, s));
+    }
     double lam = 0.0;
     HIPCHK(hipMemcpyAsync(&lam, P->lam, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -954,6 +1067,8 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   }
   if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;
   HIPCHK(rbf::launch_scatter_rows(P->xhi, P->amap, P->m, coeffs, s));
+  if (P->npoly)
+    HIPCHK(rbf::launch_poly_coeffs(P->xpoly, P->pbasis, P->dim, true, coeffs + P->m, s));
   const int rcr = read_scalars(P);
   if (rcr) return rcr;
   double lam = 0.0;
@@ -983,7 +1098,7 @@ int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double
   if (nq > 0) {
     HIPCHK(rbf::launch_gather(coeffs, P->cperm, P->m, P->cs_sorted, s));
     HIPCHK(rbf::launch_eval(P->view(), P->phi < 0 ? 1 : P->phi, nq, queries, P->cs_sorted,
-                            P->rho2_s, P->irho_s, out, s));
+                            P->rho2_s, P->irho_s, P->npoly ? coeffs + P->m : nullptr, out, s));
   }
   if (values) {
     if (nq == 0) {

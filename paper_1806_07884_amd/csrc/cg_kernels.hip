@@ -216,15 +216,43 @@ __device__ __forceinline__ XT finish_slice(const SliceHead<XT>& h, const CgMatri
   return a;
 }
 
-template <typename VT, typename XT, typename CT, int L, int BS>
+// The replicated polynomial block of an iteration (see PolySys): from the
+// state (r, s_old, p_old) of state buffer q and w, forms u = C^-1 r.
+__device__ __forceinline__ void poly_u(const PolySys& S, int np, const double* r, double* u) {
+#pragma unroll
+  for (int t = 0; t < kMaxPoly; ++t) {
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxPoly; ++k)
+      if (k < np) a += S.Ci[t][k] * r[k];
+    u[t] = t < np ? a : 0.0;
+  }
+}
+
+// w = Q^T u (reduced partials) + C u over the polynomial unknowns.
+__device__ __forceinline__ void poly_w(const PolySys& S, int np, const double* qtu,
+                                       const double* u, double* w) {
+#pragma unroll
+  for (int t = 0; t < kMaxPoly; ++t) {
+    double a = qtu[t];
+#pragma unroll
+    for (int k = 0; k < kMaxPoly; ++k)
+      if (k < np) a += S.C[t][k] * u[k];
+    w[t] = t < np ? a : 0.0;
+  }
+}
+
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
 __global__ __launch_bounds__(BS) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
     XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc,
     const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int q,
-    int fixed) {
+    int fixed, int np, const XT* __restrict__ Q, const PolySys* __restrict__ psys,
+    const PolyState* __restrict__ pin, PolyState* __restrict__ pout) {
   constexpr int W = BS / kWave;
-  __shared__ double ws[6][W];
-  __shared__ double ws_out[6][W];
+  constexpr int NP = POLY ? kCgParts : 6;
+  __shared__ double ws[NP][W];
+  __shared__ double ws_out[NP][W];
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -246,11 +274,13 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
       x_old = xlo[h.row];
     }
   }
-  double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) red[t] = 0.0;
   if (!fixed) {
     for (int k = threadIdx.x; k < n_in; k += BS) {
 #pragma unroll
-      for (int t = 0; t < 6; ++t) red[t] += part_in[6 * k + t];
+      for (int t = 0; t < NP; ++t) red[t] += part_in[NP * k + t];
     }
   }
   const double gam_prev = sc->gam[q ^ 1];
@@ -259,19 +289,47 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
   const double falpha = sc->fix_alpha, fbeta = sc->fix_beta;
   // one barrier publishes both the block's partial sums and the flag
 #pragma unroll
-  for (int t = 0; t < 6; ++t) red[t] = wave_sum(red[t]);
+  for (int t = 0; t < NP; ++t) red[t] = wave_sum(red[t]);
   if (lane == 0) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) ws[t][wave] = red[t];
+    for (int t = 0; t < NP; ++t) ws[t][wave] = red[t];
   }
   if (threadIdx.x == 0) s_flag = sc->done;
   __syncthreads();
   if (s_flag) return;
-  for (int t = 0; t < 6; ++t) {
+  for (int t = 0; t < NP; ++t) {
     double v = 0.0;
 #pragma unroll 4
     for (int w = 0; w < W; ++w) v += ws[t][w];
     red[t] = v;
+  }
+  // polynomial unknowns: state of buffer q, u = C^-1 r and w = Q^T u + C u
+  // (w from the refresh after one)
+  double pr[kMaxPoly], pw[kMaxPoly], ps[kMaxPoly], pp[kMaxPoly], px[kMaxPoly], pu[kMaxPoly];
+  if constexpr (POLY) {
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) {
+      pr[t] = pin->r[t];
+      ps[t] = pin->s[t];
+      pp[t] = pin->p[t];
+      px[t] = pin->x[t];
+    }
+    poly_u(*psys, np, pr, pu);
+    if (fixed) {
+#pragma unroll
+      for (int t = 0; t < kMaxPoly; ++t) pw[t] = pin->w[t];
+    } else {
+      poly_w(*psys, np, red + 6, pu, pw);
+#pragma unroll
+      for (int t = 0; t < kMaxPoly; ++t) {
+        red[0] += pr[t] * pu[t];
+        red[1] += pw[t] * pu[t];
+        red[2] += pr[t] * pr[t];
+        red[3] += pu[t] * ps[t];
+        red[4] += pp[t] * pw[t];
+        red[5] += pp[t] * ps[t];
+      }
+    }
   }
   const double gamma = fixed ? fgamma : red[0];
   const double rr = fixed ? frr : red[2];
@@ -299,16 +357,55 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
     return;
   }
   const XT alpha = (XT)alpha_d, beta = (XT)beta_d;
+  // the polynomial unknowns' step, and their next u for the rows of B
+  XT uq[kMaxPoly];
+  if constexpr (POLY) {
+    double rn[kMaxPoly], un[kMaxPoly];
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) {
+      pp[t] = pu[t] + beta_d * pp[t];
+      ps[t] = pw[t] + beta_d * ps[t];
+      px[t] = px[t] + alpha_d * pp[t];
+      rn[t] = pr[t] - alpha_d * ps[t];
+    }
+    poly_u(*psys, np, rn, un);
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) uq[t] = (XT)un[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+      for (int t = 0; t < kMaxPoly; ++t) {
+        pout->r[t] = rn[t];
+        pout->w[t] = pw[t];
+        pout->s[t] = ps[t];
+        pout->p[t] = pp[t];
+        pout->x[t] = px[t];
+      }
+    }
+  }
   auto u_next = [&](int32_t l) -> XT {
     const CgState<XT> t = sin[l];
     return t.d * r_next(t.r, s_next(t.w, t.s, beta), alpha);
   };
-  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double part[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) part[t] = 0.0;
   auto own_row = [&](int64_t row, XT wn, const CgState<XT>& t, XT po, XT xo) {
     const XT pn = t.d * t.r + beta * po;
     const XT sn = s_next(t.w, t.s, beta);
     const XT rn = r_next(t.r, sn, alpha);
     const XT un = t.d * rn;
+    if constexpr (POLY) {
+      // w of a row of B takes the polynomial columns Q u; Q^T u is the
+      // polynomial unknowns' share of the next w
+#pragma unroll
+      for (int k = 0; k < kMaxPoly; ++k) {
+        if (k < np) {
+          const XT qv = Q[k * m + row];
+          wn += qv * uq[k];
+          part[6 + k] += (double)qv * (double)un;
+        }
+      }
+    }
     p[row] = pn;
     xlo[row] = xo + alpha * pn;
     CgState<XT> o;
@@ -334,10 +431,10 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
         own_row(h.row, wn2, sin[h.row], p[h.row], xlo[h.row]);
     }
   }
-  block_sums<6, W, false>(part, ws_out);
+  block_sums<NP, W, false>(part, ws_out);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) part_out[6 * blockIdx.x + t] = part[t];
+    for (int t = 0; t < NP; ++t) part_out[NP * blockIdx.x + t] = part[t];
     if (blockIdx.x == 0) {
       sc->gam[q] = gamma;
       sc->alp[q] = alpha_d;
@@ -357,18 +454,30 @@ __global__ void k_fold_solution(int64_t m, double* __restrict__ xhi, XT* __restr
 }
 
 // Float64 residual of the stored system: r64 = g - (B + lambda I) x_hi, and
-// r = (XT) r64 into the state record (one wave per slice).
-template <typename VT, typename XT, typename CT, int L, int BS>
+// r = (XT) r64 into the state record (one wave per slice).  With the
+// polynomial block, r64 -= Q x_poly and the block's partials of Q^T x_hi go
+// to part_out (kMaxPoly per block).
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
 __global__ __launch_bounds__(BS) void k_true_residual(int64_t m, CgMatrix A,
                                                             const double* __restrict__ xhi,
                                                             const double* __restrict__ g,
                                                             double* __restrict__ r64,
-                                                            CgState<XT>* __restrict__ st) {
+                                                            CgState<XT>* __restrict__ st, int np,
+                                                            const XT* __restrict__ Q,
+                                                            const PolyState* __restrict__ pin,
+                                                            double* __restrict__ part_out) {
   constexpr int S = kWave / L;
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
   const int lane = threadIdx.x & (kWave - 1);
   constexpr int W = BS / kWave;
+  __shared__ double ws[kMaxPoly][W];
+  double xq[kMaxPoly], qx[kMaxPoly];
+#pragma unroll
+  for (int t = 0; t < kMaxPoly; ++t) {
+    xq[t] = POLY ? pin->x[t] : 0.0;
+    qx[t] = 0.0;
+  }
   for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
        slice += (int64_t)gridDim.x * W) {
     const int64_t row = slice * S + lane / L;
@@ -383,38 +492,109 @@ __global__ __launch_bounds__(BS) void k_true_residual(int64_t m, CgMatrix A,
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((lane & (L - 1)) == 0 && row < m) {
-      const double rv = g[row] - acc;
+      double rv = g[row] - acc;
+      if constexpr (POLY) {
+        const double xj = xhi[row];
+#pragma unroll
+        for (int t = 0; t < kMaxPoly; ++t) {
+          if (t < np) {
+            const double qv = (double)Q[t * m + row];
+            rv -= qv * xq[t];
+            qx[t] += qv * xj;
+          }
+        }
+      }
       r64[row] = rv;
       st[row].r = (XT)rv;
+    }
+  }
+  if constexpr (POLY) {
+    block_sums<kMaxPoly, W, false>(qx, ws);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int t = 0; t < kMaxPoly; ++t) part_out[kMaxPoly * blockIdx.x + t] = qx[t];
+    }
+  }
+}
+
+// The polynomial unknowns' float64 residual e - Q^T x_hi - C x_poly (single
+// block; the partials of k_true_residual reduced in a fixed order), into the
+// state of buffer q.
+__global__ __launch_bounds__(kCgLargeBlock) void k_poly_residual(const PolySys* __restrict__ S,
+                                                                 const double* __restrict__ part,
+                                                                 int n, PolyState* __restrict__ st) {
+  constexpr int W = kCgLargeBlock / kWave;
+  __shared__ double ws[kMaxPoly][W];
+  double v[kMaxPoly] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += kCgLargeBlock) {
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) v[t] += part[kMaxPoly * k + t];
+  }
+  block_sums<kMaxPoly, W, false>(v, ws);
+  if (threadIdx.x == 0) {
+    const int np = S->np;
+    for (int t = 0; t < kMaxPoly; ++t) {
+      double r = 0.0;
+      if (t < np) {
+        r = S->e[t] - v[t];
+        for (int k = 0; k < np; ++k) r -= S->C[t][k] * st->x[k];
+      }
+      st->r[t] = r;
     }
   }
 }
 
 // w = B D^-1 r from the records of st[q] (r just replaced), written with the
 // carried s and d into the other buffer; partials of r.u, w.u, r64.r64,
-// p.w, u.s and p.s.
-template <typename VT, typename XT, typename CT, int L, int BS>
+// p.w, u.s and p.s (and, with the polynomial block, of Q^T u; the block's
+// own u = C^-1 r feeds w of every row through Q).
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
 __global__ __launch_bounds__(BS) void k_cg_refresh(int64_t m, CgMatrix A,
                                                          const CgState<XT>* __restrict__ sin,
                                                          CgState<XT>* __restrict__ sout,
                                                          const XT* __restrict__ p,
                                                          const double* __restrict__ r64,
-                                                         double* __restrict__ part_out) {
+                                                         double* __restrict__ part_out, int np,
+                                                         const XT* __restrict__ Q,
+                                                         const PolySys* __restrict__ psys,
+                                                         const PolyState* __restrict__ pin) {
   constexpr int W = BS / kWave;
-  __shared__ double ws[6][W];
+  constexpr int NP = POLY ? kCgParts : 6;
+  __shared__ double ws[NP][W];
   auto u_of = [&](int32_t l) -> XT {
     const CgState<XT> t = sin[l];
     return t.d * t.r;
   };
+  XT uq[kMaxPoly];
+  if constexpr (POLY) {
+    double pr[kMaxPoly], pu[kMaxPoly];
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) pr[t] = pin->r[t];
+    poly_u(*psys, np, pr, pu);
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) uq[t] = (XT)pu[t];
+  }
   const int lane = threadIdx.x & (kWave - 1);
-  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double part[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) part[t] = 0.0;
   for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
        slice += (int64_t)gridDim.x * W) {
     int64_t row;
-    const XT wn = slice_sum<VT, XT, CT, L>(m, slice, A, u_of, &row);
+    XT wn = slice_sum<VT, XT, CT, L>(m, slice, A, u_of, &row);
     if ((lane & (L - 1)) == 0 && row < m) {
       const CgState<XT> t = sin[row];
       const XT u = t.d * t.r;
+      if constexpr (POLY) {
+#pragma unroll
+        for (int k = 0; k < kMaxPoly; ++k) {
+          if (k < np) {
+            const XT qv = Q[k * m + row];
+            wn += qv * uq[k];
+            part[6 + k] += (double)qv * (double)u;
+          }
+        }
+      }
       const XT pj = p[row];
       CgState<XT> o;
       o.r = t.r;
@@ -431,29 +611,58 @@ __global__ __launch_bounds__(BS) void k_cg_refresh(int64_t m, CgMatrix A,
       part[5] += (double)pj * (double)t.s;
     }
   }
-  block_sums<6, W, false>(part, ws);
+  block_sums<NP, W, false>(part, ws);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) part_out[6 * blockIdx.x + k] = part[k];
+    for (int k = 0; k < NP; ++k) part_out[NP * blockIdx.x + k] = part[k];
   }
 }
 
 // After a refresh: the true residual norm, the convergence flag, the next
 // trigger and the scalars of the next iteration (restart: beta = 0, so
 // p = u and s = w; otherwise beta = gamma / gamma_prev with the direction
-// kept, and alpha = gamma / (p . s) from the expanded product).
-__global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(CgScalars* __restrict__ sc,
-                                                              const double* __restrict__ part,
-                                                              int n, int q_prev, int restart) {
+// kept, and alpha = gamma / (p . s) from the expanded product).  With the
+// polynomial block: its w = Q^T u + C u and its share of every product, its
+// state carried to buffer q ^ 1, and its solution to xpoly.
+template <bool POLY>
+__global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(
+    CgScalars* __restrict__ sc, const double* __restrict__ part, int n, int q_prev, int restart,
+    const PolySys* __restrict__ psys, const PolyState* __restrict__ pin,
+    PolyState* __restrict__ pout, double* __restrict__ xpoly) {
   constexpr int W = kCgLargeBlock / kWave;
-  __shared__ double ws[6][W];
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  constexpr int NP = POLY ? kCgParts : 6;
+  __shared__ double ws[NP][W];
+  double v[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) v[t] = 0.0;
   for (int k = threadIdx.x; k < n; k += kCgLargeBlock) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) v[t] += part[6 * k + t];
+    for (int t = 0; t < NP; ++t) v[t] += part[NP * k + t];
   }
-  block_sums<6, W, false>(v, ws);
+  block_sums<NP, W, false>(v, ws);
   if (threadIdx.x == 0) {
+    if constexpr (POLY) {
+      const int np = psys->np;
+      double pr[kMaxPoly], pu[kMaxPoly], pw[kMaxPoly];
+      for (int t = 0; t < kMaxPoly; ++t) pr[t] = pin->r[t];
+      poly_u(*psys, np, pr, pu);
+      poly_w(*psys, np, v + 6, pu, pw);
+      for (int t = 0; t < kMaxPoly; ++t) {
+        const double pp = pin->p[t], ps = pin->s[t];
+        v[0] += pr[t] * pu[t];
+        v[1] += pw[t] * pu[t];
+        v[2] += pr[t] * pr[t];
+        v[3] += pp * pw[t];
+        v[4] += pu[t] * ps;
+        v[5] += pp * ps;
+        pout->r[t] = pr[t];
+        pout->w[t] = pw[t];
+        pout->s[t] = ps;
+        pout->p[t] = pp;
+        pout->x[t] = pin->x[t];
+        xpoly[t] = pin->x[t];
+      }
+    }
     const double gamma = v[0], delta = v[1], rr = v[2];
     const double beta = restart ? 0.0 : gamma / sc->gam[q_prev];
     const double ps = delta + beta * (v[3] + v[4]) + beta * beta * v[5];
@@ -479,12 +688,20 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(CgScalars* __
 }
 
 // Start of a solve: x_lo, p and both state buffers cleared (s = 0), d = D^-1
-// in both.
+// in both; the polynomial unknowns' states cleared likewise, with x from xpoly.
 template <typename XT>
 __global__ void k_cg_clear(int64_t m, const XT* __restrict__ dinv, XT* __restrict__ xlo,
                            XT* __restrict__ p, CgState<XT>* __restrict__ s0,
-                           CgState<XT>* __restrict__ s1) {
+                           CgState<XT>* __restrict__ s1, PolyState* __restrict__ p0,
+                           PolyState* __restrict__ p1, const double* __restrict__ xpoly) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p0 && j == 0) {
+    for (int t = 0; t < kMaxPoly; ++t) {
+      p0->r[t] = p0->w[t] = p0->s[t] = p0->p[t] = 0.0;
+      p1->r[t] = p1->w[t] = p1->s[t] = p1->p[t] = 0.0;
+      p0->x[t] = p1->x[t] = xpoly[t];
+    }
+  }
   if (j >= m) return;
   xlo[j] = (XT)0;
   p[j] = (XT)0;
@@ -497,8 +714,10 @@ __global__ void k_cg_clear(int64_t m, const XT* __restrict__ dinv, XT* __restric
   s1[j] = t;
 }
 
-// ||g||^2 and the initial state of the scalars (single block, fixed order).
+// ||g||^2 (with ||e||^2 of the polynomial block) and the initial state of the
+// scalars (single block, fixed order).
 __global__ __launch_bounds__(kCgLargeBlock) void k_cg_init(int64_t m, const double* __restrict__ g,
+                                                      const PolySys* __restrict__ psys,
                                                       CgScalars* __restrict__ sc, double rtol,
                                                       double delta) {
   constexpr int W = kCgLargeBlock / kWave;
@@ -507,6 +726,8 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_cg_init(int64_t m, const doub
   for (int64_t j = threadIdx.x; j < m; j += kCgLargeBlock) v[0] += g[j] * g[j];
   block_sums<1, W, false>(v, ws);
   if (threadIdx.x == 0) {
+    if (psys)
+      for (int t = 0; t < psys->np; ++t) v[0] += psys->e[t] * psys->e[t];
     sc->gg = v[0];
     sc->tol2 = rtol * rtol * v[0];
     sc->delta2 = delta * delta;
@@ -520,19 +741,32 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_cg_init(int64_t m, const doub
   }
 }
 
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
+void launch_iter_p(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                   hipEvent_t e1, hipStream_t s) {
+  const PolyState* pin = POLY ? a.pst[q] : nullptr;
+  PolyState* pout = POLY ? a.pst[q ^ 1] : nullptr;
+  if (e0) {
+    // the extended launch stamps the events at the kernel's own start and end
+    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s,
+                          e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p,
+                          a.xlo, a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, q,
+                          fixed, a.np, a.Q, a.psys, pin, pout);
+  } else {
+    hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+                       A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed, a.np, a.Q,
+                       a.psys, pin, pout);
+  }
+}
+
 template <typename VT, typename XT, typename CT, int L, int BS>
 void launch_iter_b(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
                    hipEvent_t e1, hipStream_t s) {
-  if (e0) {
-    // the extended launch stamps the events at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, e0, e1,
-                          0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
-                          (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
-  } else {
-    hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m, A,
-                       (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
-                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
-  }
+  if (a.np > 0)
+    launch_iter_p<VT, XT, CT, L, BS, true>(a, A, q, fixed, e0, e1, s);
+  else
+    launch_iter_p<VT, XT, CT, L, BS, false>(a, A, q, fixed, e0, e1, s);
 }
 
 template <typename VT, typename XT, typename CT, int L>
@@ -544,14 +778,27 @@ void launch_iter_l(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hip
     launch_iter_b<VT, XT, CT, L, kCgLargeBlock>(a, A, q, fixed, e0, e1, s);
 }
 
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
+void launch_refresh_p(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q,
+                      hipStream_t s) {
+  const PolyState* pin = POLY ? a.pst[q] : nullptr;
+  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s,
+                     a.m, A, (const double*)a.xhi, g, a.r64, a.st[q], a.np, a.Q, pin, a.part_ref);
+  if (POLY)
+    hipLaunchKernelGGL(k_poly_residual, dim3(1), dim3(kCgLargeBlock), 0, s, a.psys,
+                       (const double*)a.part_ref, a.blocks, a.pst[q]);
+  hipLaunchKernelGGL((k_cg_refresh<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+                     A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], (const XT*)a.p,
+                     (const double*)a.r64, a.part_ref, a.np, a.Q, a.psys, pin);
+}
+
 template <typename VT, typename XT, typename CT, int L, int BS>
 void launch_refresh_b(const CgArgs<XT>& a, const CgMatrix& A, const double* g, int q,
                       hipStream_t s) {
-  hipLaunchKernelGGL((k_true_residual<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m,
-                     A, (const double*)a.xhi, g, a.r64, a.st[q]);
-  hipLaunchKernelGGL((k_cg_refresh<VT, XT, CT, L, BS>), dim3(a.blocks), dim3(BS), 0, s, a.m, A,
-                     (const CgState<XT>*)a.st[q], a.st[q ^ 1], (const XT*)a.p,
-                     (const double*)a.r64, a.part_ref);
+  if (a.np > 0)
+    launch_refresh_p<VT, XT, CT, L, BS, true>(a, A, g, q, s);
+  else
+    launch_refresh_p<VT, XT, CT, L, BS, false>(a, A, g, q, s);
 }
 
 template <typename VT, typename XT, typename CT, int L>
@@ -585,9 +832,11 @@ void refresh_dispatch(const CgArgs<XT>& a, const CgMatrix& A, const double* g, i
 
 template <typename XT>
 bool args_ok(const CgArgs<XT>& a, const CgMatrix& A) {
+  const bool poly_ok = a.np == 0 || (a.np >= 3 && a.np <= kMaxPoly && a.Q && a.psys &&
+                                     a.pst[0] && a.pst[1] && a.xpoly);
   return a.blocks >= 1 && a.blocks <= kCgMaxBlocks && A.nslices >= 1 &&
          (a.threads == kCgSmallBlock || a.threads == kCgLargeBlock) &&
-         (A.lanes == 2 || A.lanes == 4 || A.lanes == 8);
+         (A.lanes == 2 || A.lanes == 4 || A.lanes == 8) && poly_ok;
 }
 
 }  // namespace
@@ -634,8 +883,14 @@ hipError_t cg_refresh(const CgArgs<XT>& a, const CgMatrix& A, const double* g, i
     refresh_dispatch<VT, XT, int16_t>(a, A, g, q, s);
   else
     refresh_dispatch<VT, XT, int32_t>(a, A, g, q, s);
-  hipLaunchKernelGGL(k_refresh_scalars, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
-                     (const double*)a.part_ref, a.blocks, q_prev, restart);
+  if (a.np > 0)
+    hipLaunchKernelGGL(k_refresh_scalars<true>, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                       (const double*)a.part_ref, a.blocks, q_prev, restart, a.psys,
+                       (const PolyState*)a.pst[q], a.pst[q ^ 1], a.xpoly);
+  else
+    hipLaunchKernelGGL(k_refresh_scalars<false>, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                       (const double*)a.part_ref, a.blocks, q_prev, restart, nullptr, nullptr,
+                       nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -645,8 +900,10 @@ hipError_t cg_setup(const CgArgs<XT>& a, const double* g, double rtol, double de
   const int bs = 256;
   const dim3 eg((unsigned)((a.m + bs - 1) / bs));
   hipLaunchKernelGGL(k_cg_clear<XT>, eg, dim3(bs), 0, s, a.m, a.dinv, a.xlo, a.p, a.st[0],
-                     a.st[1]);
-  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kCgLargeBlock), 0, s, a.m, g, a.sc, rtol, delta);
+                     a.st[1], a.np ? a.pst[0] : nullptr, a.np ? a.pst[1] : nullptr,
+                     (const double*)a.xpoly);
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kCgLargeBlock), 0, s, a.m, g,
+                     a.np ? a.psys : nullptr, a.sc, rtol, delta);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Evaluation of the approximant (Section 2, eq. 3):
 //     f(y) = sum_j c_j phi(||y - xi_j|| / rho_j)   over centres with y in supp(j),
-// one thread per query point, centres found through the centre hash, plus
-// the root-mean-square error against given values.
+// plus, with polynomial reproduction, a^T y + a_0 (Section 3, eq. 6-7); one
+// thread per query point, centres found through the centre hash, and the
+// root-mean-square error against given values.
 #include "plan_kernels.h"
 
 namespace rbf {
@@ -12,6 +13,7 @@ __global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const doub
                                               const double* __restrict__ cs,
                                               const double* __restrict__ rho2_s,
                                               const double* __restrict__ irho_s,
+                                              const double* __restrict__ kpoly,
                                               double* __restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
@@ -34,6 +36,12 @@ __global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const doub
         if (s < rho2_s[i]) acc += cs[i] * wendland<PHI, double>(__builtin_sqrt(s) * irho_s[i]);
       }
     }
+  }
+  if (kpoly) {
+    double pv = kpoly[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pv += kpoly[d] * p[d];
+    acc += pv;
   }
   out[q] = acc;
 }
@@ -88,14 +96,15 @@ __global__ __launch_bounds__(kRed) void k_sum_final(const double* __restrict__ p
 
 template <int DIM>
 void eval_dim(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
-              const double* rho2_s, const double* irho_s, double* out, hipStream_t s) {
+              const double* rho2_s, const double* irho_s, const double* kp, double* out,
+              hipStream_t s) {
   const int bs = 256;
   const dim3 grid((unsigned)((nq + bs - 1) / bs));
   switch (phi) {
-    case 0: hipLaunchKernelGGL((k_eval<DIM, 0>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
-    case 1: hipLaunchKernelGGL((k_eval<DIM, 1>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
-    case 2: hipLaunchKernelGGL((k_eval<DIM, 2>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
-    default: hipLaunchKernelGGL((k_eval<DIM, 3>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, out); break;
+    case 0: hipLaunchKernelGGL((k_eval<DIM, 0>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
+    case 1: hipLaunchKernelGGL((k_eval<DIM, 1>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
+    case 2: hipLaunchKernelGGL((k_eval<DIM, 2>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
+    default: hipLaunchKernelGGL((k_eval<DIM, 3>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
   }
 }
 
@@ -120,12 +129,13 @@ hipError_t launch_scatter_rows(const double* src, const int32_t* amap, int64_t m
 }
 
 hipError_t launch_eval(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
-                       const double* rho2_s, const double* irho_s, double* out, hipStream_t s) {
+                       const double* rho2_s, const double* irho_s, const double* kpoly,
+                       double* out, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   if (P.dim == 2)
-    eval_dim<2>(P, phi, nq, y, cs, rho2_s, irho_s, out, s);
+    eval_dim<2>(P, phi, nq, y, cs, rho2_s, irho_s, kpoly, out, s);
   else
-    eval_dim<3>(P, phi, nq, y, cs, rho2_s, irho_s, out, s);
+    eval_dim<3>(P, phi, nq, y, cs, rho2_s, irho_s, kpoly, out, s);
   return hipGetLastError();
 }
 

@@ -166,9 +166,29 @@ hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, doub
 // dst[j] = amap[j] >= 0 ? src[amap[j]] : 0 for j < m.
 hipError_t launch_scatter_rows(const double* src, const int32_t* amap, int64_t m, double* dst,
                                hipStream_t s);
+// kpoly: NULL, or device [dim + 1] coefficients (a, a_0) of the linear
+// polynomial (eq. 7) added to every value.
 hipError_t launch_eval(const PlanView& P, int phi, int64_t nq, const double* y, const double* cs,
-                       const double* rho2_s, const double* irho_s, double* out, hipStream_t s);
+                       const double* rho2_s, const double* irho_s, const double* kpoly,
+                       double* out, hipStream_t s);
 int sq_err_blocks(int64_t n);
 hipError_t launch_sq_err(const double* f, const double* h, int64_t n, double* part, int nb,
                          double* out, hipStream_t s);
+// poly_kernels.hip (PolySys and PolyBasis in solver.h)
+struct PolySys;
+struct PolyBasis;
+int poly_gram_blocks(int64_t n);
+// Q (float64 [dim+1][ms] by solver row, and its float32 copy when q32 is not
+// NULL: then phi is evaluated in float32, as the mixed assembly does), C, e
+// and C^-1 into S, for basis `phi` and sorted values hs; part holds
+// poly_gram_blocks(n) * 14 doubles.
+hipError_t launch_poly_system(const PlanView& P, int phi, const PolyBasis& B, int64_t ms,
+                              const double* hs, double* q64, float* q32, double* part, int nb,
+                              PolySys* S, hipStream_t s);
+// out = the coefficients of `in` in the paper's basis (to_paper) or in the
+// scaled basis (dim + 1 values each); in and out may not alias.
+hipError_t launch_poly_coeffs(const double* in, const PolyBasis& B, int dim, bool to_paper,
+                              double* out, hipStream_t s);
+// x = C^-1 e (the fit when no centre is active).
+hipError_t launch_poly_only(const PolySys* S, double* x, hipStream_t s);
 }  // namespace rbf

@@ -47,6 +47,34 @@ struct alignas(4 * sizeof(XT)) CgState {
   XT r, w, s, d;
 };
 
+// Linear polynomial reproduction (Section 3, eq. 10) borders B with the
+// blocks Q = A^T P (one column per basis function, per solver row),
+// C = P^T P and e = P^T h, in the scaled basis P_i = ((x_i - o) / s, 1) with
+// o and s the centre and half-extent of the points' bounding box.  Those d + 1
+// unknowns are few, so every CG block keeps and updates them itself, in
+// float64, from the same inputs in the same order: a replicated block of the
+// iteration.  Their preconditioner block is C^-1 (block Jacobi), the rows of B
+// keep D^-1.
+constexpr int kMaxPoly = 4;
+struct PolySys {
+  double C[kMaxPoly][kMaxPoly];   // P^T P, zero past np
+  double Ci[kMaxPoly][kMaxPoly];  // its inverse, zero past np
+  double e[kMaxPoly];             // P^T h
+  int32_t np;                     // d + 1
+  int32_t bad;                    // P^T P is not positive definite
+};
+// The polynomial unknowns' share of the CG state (see CgState), with the
+// search direction p and the solution x, which the rows of B keep apart.
+struct PolyState {
+  double r[kMaxPoly], w[kMaxPoly], s[kMaxPoly], p[kMaxPoly], x[kMaxPoly];
+};
+// Partial sums per block: the six dot products, then Q^T u (or Q^T x).
+constexpr int kCgParts = 6 + kMaxPoly;
+// The scaled basis: coordinate d enters as (x_d - o[d]) / s[d].
+struct PolyBasis {
+  double o[3], s[3];
+};
+
 template <typename XT>
 struct CgArgs {
   int64_t m;
@@ -57,10 +85,16 @@ struct CgArgs {
   double* xhi;         // float64 solution
   double* r64;         // float64 true residual
   CgScalars* sc;
-  double* part[2];     // [6 * blocks] partials of an iteration, by state buffer
-  double* part_ref;    // [6 * blocks] partials of a refresh
+  double* part[2];     // [kCgParts * blocks] partials of an iteration, by state buffer
+  double* part_ref;    // [kCgParts * blocks] partials of a refresh
   int blocks;          // grid of every slice kernel
   int threads;         // its block size: kCgSmallBlock or kCgLargeBlock
+  // polynomial block (np = 0: none)
+  int np;
+  const XT* Q;            // [np][m], Q[t * m + row]
+  const PolySys* psys;
+  PolyState* pst[2];      // by state buffer, as st
+  double* xpoly;          // [kMaxPoly] solution at the last refresh (start value on entry)
 };
 
 // The stored matrix in the solver's sliced-ELL layout.  Rows are taken in
