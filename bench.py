@@ -18,6 +18,7 @@ with both held-out RMSEs (matched when they agree to 0.1 %).
 ``--workload field3d`` (N = 2^22 in 3D, 64^3 centres, scored at 10^6
 uniform queries against the clean field) time the same step on the larger
 workloads; the oracle baseline is taken for terrain2d only.
+``--polynomial`` fits with linear polynomial reproduction (Section 3).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -44,12 +45,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def iter_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int) -> int:
+def iter_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int,
+               n_poly: int = 0) -> int:
     """Algorithmic HBM bytes of one CG iteration launch: every nonzero of B
     once (value and column index, padding excluded) and, per solver row (an
     active centre), its state record (r, w, s, d) read and written plus p and
-    x read and written."""
-    return nnz_full * (val_bytes + col_bytes) + 12 * m * vec_bytes
+    x read and written, and with a polynomial its n_poly entries of A^T P."""
+    return nnz_full * (val_bytes + col_bytes) + (12 + n_poly) * m * vec_bytes
 
 
 def kernel_digest() -> str:
@@ -104,6 +106,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=float, default=0.7)
     ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
+    ap.add_argument("--polynomial", action="store_true",
+                    help="linear polynomial reproduction (bordered system of eq. 10)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -139,7 +143,8 @@ def main() -> int:
     torch.cuda.synchronize()
 
     def fit(prec: str, profile: bool = False):
-        plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL)
+        plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL,
+                                polynomial=args.polynomial)
         if profile:
             rbf.rbf_profile(plan, True)
         rbf.rbf_assemble(plan, prob.phi, prec, vals)
@@ -181,13 +186,14 @@ def main() -> int:
 
     # the solver's rows are the active centres
     nnz, m, cb = stats["nnz_full"], stats["n_active"], stats["solver_col_bytes"]
+    npoly = stats["n_poly"]
     # kernel time from start/stop events of sampled launches on the plan's stream
     kern32 = max(avg32, 1e-3) * 1e-6
-    bytes32 = iter_bytes(nnz, m, 4, cb, 4)
+    bytes32 = iter_bytes(nnz, m, 4, cb, 4, npoly)
     achieved = bytes32 / kern32
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"cg_iter_fp32_{wl}_traffic.json")
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and not npoly:
         with open(tfile) as fh:
             t = json.load(fh)
         if t.get("kernel_digest") == kernel_digest():
@@ -198,10 +204,10 @@ def main() -> int:
                 "avg_kernel_us": kern32 * 1e6, "timed_launches": n32,
                 "solver_entries": stats["solver_entries"], "solver_lanes": stats["solver_lanes"]}
     kern64 = max(avg64, 1e-3) * 1e-6
-    b64 = iter_bytes(nnz, m, 8, cb, 8)
+    b64 = iter_bytes(nnz, m, 8, cb, 8, npoly)
 
     cpu = None
-    if not args.no_cpu_baseline and wl == "terrain2d":
+    if not args.no_cpu_baseline and wl == "terrain2d" and not args.polynomial:
         log("timing the oracle on a window of the workload")
         cpu = cpu_baseline(prob, args.cpu_window)
         log(f"oracle: {cpu['value']:.0f} pts/s ({cpu['seconds']:.1f} s)")
@@ -215,7 +221,8 @@ def main() -> int:
                    "n_train": int(n_train), "n_centers": int(stats["n_centers"]),
                    "n_active": int(m), "grid": prob.grid,
                    "phi": prob.phi, "rho": prob.rho, "lambda_rel": LAMBDA_REL, "rtol": RTOL,
-                   "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates"},
+                   "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates",
+                   "polynomial": "linear" if npoly else "none"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": {"ms_per_fit": dt32 * 1e3, "iterations": per32[-1][0]["iterations"],
