@@ -169,6 +169,15 @@ int rbf_plan_pattern(const rbf_plan* plan, int64_t* row_ptr_h, int32_t* col_h,
  * block.  Errors: INVALID (bad phi/prec, NULL values), HIP. */
 int rbf_assemble(rbf_plan* plan, rbf_phi phi, rbf_precision prec, const double* values);
 
+/* New sample values (device [N], caller's point order) for the assembled
+ * system: g = A^T h (and P^T h with a polynomial) recomputed, B, lambda and
+ * the preconditioner kept.  g is bit for bit what rbf_assemble computes for
+ * the same values and precision.  Vector-valued data (h_i in E^p, Section 2)
+ * share A and B across components: assemble once, then per component
+ * rbf_set_values and rbf_solve.  Stream-ordered.  Errors: INVALID (nothing
+ * assembled, NULL values), HIP. */
+int rbf_set_values(rbf_plan* plan, const double* values);
+
 /* Copy the polynomial blocks of eq. 10 to host memory, in the paper's basis
  * P_i = (x_i^T, 1): q_h [M][n_poly] row-major = A^T P (rows of inactive
  * centres 0), c_h [n_poly][n_poly] = P^T P, e_h [n_poly] = P^T h; float64 as

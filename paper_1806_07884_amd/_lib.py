@@ -84,6 +84,7 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "rbf_poly_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "rbf_set_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rbf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
                                  ctypes.POINTER(SolveInfo)]),
     "rbf_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,

@@ -137,6 +137,16 @@ def rbf_assemble(plan: Plan, phi: str, prec: str, values: torch.Tensor) -> None:
     plan._keep = [values]
 
 
+def rbf_set_values(plan: Plan, values: torch.Tensor) -> None:
+    """New sample values for the assembled system: g = A^T h (and P^T h) only,
+    B kept (rbf_set_values); one call per component of vector-valued data."""
+    _need(values, "values", (plan.n,))
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_set_values(plan.handle, values.data_ptr())
+    L.check(st, "rbf_set_values")
+    plan._keep = [values]
+
+
 def rbf_system_export(plan: Plan):
     """(upper values of B + lambda I [nnz_upper], g [M], lambda) on the host."""
     info = rbf_plan_info(plan)

@@ -132,6 +132,7 @@ struct rbf_plan {
   float* dinv32 = nullptr;
   int phi = -1;
   int prec = -1;
+  bool grouped = false;  // the assembly took the grouped path
   // solver workspace
   double* xhi = nullptr;
   double* r64 = nullptr;
@@ -572,7 +573,8 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   // rows wider than one wave on average: the grouped path (see assemble_kernels.hip)
   const double upper_mean =
       (double)(P->nnz_full + P->ms) / (2.0 * (double)std::max<int64_t>(P->ms, 1));
-  HIPCHK(rbf::launch_assemble(v, phi, fp32, upper_mean > 64.0, P->hs, P->row_ptr, P->lower_cnt,
+  P->grouped = upper_mean > 64.0;
+  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->grouped, P->hs, P->row_ptr, P->lower_cnt,
                               P->col, P->sptr, P->lanes, val, P->g, P->diag, s));
   if (P->prof_on) {
     HIPCHK(hipEventRecord(e1, s));
@@ -886,6 +888,20 @@ int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* val
   if (rc) return rc;
   P->phi = (int)phi;
   P->prec = (int)prec;
+  return RBF_OK;
+}
+
+int rbf_set_values(rbf_plan* P, const double* values) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (P->prec < 0) return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_set_values");
+  if (!values) return fail(RBF_ERR_INVALID, "values is NULL");
+  hipStream_t s = P->stream;
+  HIPCHK(rbf::launch_gather(values, P->pperm, P->n, P->hs, s));
+  HIPCHK(rbf::launch_rhs(P->view(), P->phi, P->prec == RBF_PREC_FP32_REFINE, P->grouped, P->hs,
+                         P->g, s));
+  if (P->npoly)
+    HIPCHK(rbf::launch_poly_gram(P->view(), P->pbasis, P->hs, P->gram_part,
+                                 rbf::poly_gram_blocks(P->n), P->psys, s));
   return RBF_OK;
 }
 

@@ -302,6 +302,50 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
   }
 }
 
+// g = A^T h alone, for new sample values with B kept (vector-valued data):
+// the same support stream, chunk size, lane assignment and accumulator as the
+// assembly's first column pass, so g is bit for bit what k_assemble gives.
+template <int DIM, int PHI, typename T, bool GROUPED>
+__global__ __launch_bounds__(kWave* kAsmWaves) void k_rhs(PlanView P,
+                                                         const double* __restrict__ hs,
+                                                         double* __restrict__ g) {
+  constexpr int kChunk = GROUPED ? kAsmChunk / 2 : kAsmChunk;
+  __shared__ double sp[kAsmWaves][DIM][kChunk];
+  __shared__ int32_t sidx[kAsmWaves][kChunk];
+  __shared__ double gred[kAsmWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t j = blockIdx.x;
+  if (!P.active[j]) {
+    if (threadIdx.x == 0) g[j] = 0.0;
+    return;
+  }
+  double xj[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xj[d] = P.ctr[d * P.m + j];
+  const double r2j = P.rho2[j], irj = P.irho[j];
+  Acc<T> gacc;
+  double(*wsp)[kChunk] = sp[w];
+  const int32_t* widx = sidx[w];
+  stream_support_part<DIM, kChunk>(P, xj, r2j, w, kAsmWaves, wsp, sidx[w], [&](int np) {
+    for (int q = lane; q < np; q += kWave) {
+      double p[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+      const T phij = wendland<PHI, T>(scaled_r<T>(sqdist<DIM>(p, xj), irj));
+      gacc.add(phij * (T)hs[widx[q]]);
+    }
+  });
+  const double gl = wave_sum(partial_value<T>(gacc));
+  if (lane == 0) gred[w] = gl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gs = 0.0;
+    for (int u = 0; u < kAsmWaves; ++u) gs += gred[u];
+    g[j] = gs;
+  }
+}
+
 constexpr int kRed = 256;
 
 // lambda = lambda_rel * mean(diag over active centres), written to lam[0].
@@ -409,6 +453,39 @@ hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, 
                                        (float*)val, g, diag, s)
               : assemble_dim<3, double>(P, phi, grouped, hs, row_ptr, lower_cnt, col, sptr, lanes,
                                         (double*)val, g, diag, s);
+}
+
+template <int DIM, typename T, bool GROUPED>
+void rhs_phi(const PlanView& P, int phi, const double* hs, double* g, hipStream_t s) {
+  const dim3 grid((unsigned)P.m), block(kWave * kAsmWaves);
+  switch (phi) {
+    case 0: hipLaunchKernelGGL((k_rhs<DIM, 0, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
+    case 1: hipLaunchKernelGGL((k_rhs<DIM, 1, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
+    case 2: hipLaunchKernelGGL((k_rhs<DIM, 2, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
+    default: hipLaunchKernelGGL((k_rhs<DIM, 3, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
+  }
+}
+
+template <int DIM>
+void rhs_dim(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs, double* g,
+             hipStream_t s) {
+  if (fp32) {
+    if (grouped) rhs_phi<DIM, float, true>(P, phi, hs, g, s);
+    else rhs_phi<DIM, float, false>(P, phi, hs, g, s);
+  } else {
+    if (grouped) rhs_phi<DIM, double, true>(P, phi, hs, g, s);
+    else rhs_phi<DIM, double, false>(P, phi, hs, g, s);
+  }
+}
+
+hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
+                      double* g, hipStream_t s) {
+  if (P.m <= 0) return hipSuccess;
+  if (P.dim == 2)
+    rhs_dim<2>(P, phi, fp32, grouped, hs, g, s);
+  else
+    rhs_dim<3>(P, phi, fp32, grouped, hs, g, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,

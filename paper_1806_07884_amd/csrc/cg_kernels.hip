@@ -243,7 +243,7 @@ __device__ __forceinline__ void poly_w(const PolySys& S, int np, const double* q
 }
 
 template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
-__global__ __launch_bounds__(BS) void k_cg_iter(
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1))) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
     XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc,
     const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int q,
@@ -252,7 +252,10 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
   constexpr int W = BS / kWave;
   constexpr int NP = POLY ? kCgParts : 6;
   __shared__ double ws[NP][W];
-  __shared__ double ws_out[NP][W];
+  __shared__ double ws_out[6][W];
+  // the polynomial rows' partials Q^T u, per wave (added slice by slice, so
+  // that they hold no registers across the streamed loop)
+  __shared__ double ws_poly[POLY ? kMaxPoly : 1][POLY ? W : 1];
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -386,9 +389,14 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
     const CgState<XT> t = sin[l];
     return t.d * r_next(t.r, s_next(t.w, t.s, beta), alpha);
   };
-  double part[NP];
+  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if constexpr (POLY) {
+    if (lane == 0) {
 #pragma unroll
-  for (int t = 0; t < NP; ++t) part[t] = 0.0;
+      for (int k = 0; k < kMaxPoly; ++k) ws_poly[k][wave] = 0.0;
+    }
+  }
+  double qtu[kMaxPoly];
   auto own_row = [&](int64_t row, XT wn, const CgState<XT>& t, XT po, XT xo) {
     const XT pn = t.d * t.r + beta * po;
     const XT sn = s_next(t.w, t.s, beta);
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
         if (k < np) {
           const XT qv = Q[k * m + row];
           wn += qv * uq[k];
-          part[6 + k] += (double)qv * (double)un;
+          qtu[k] = (double)qv * (double)un;
         }
       }
     }
@@ -421,20 +429,44 @@ __global__ __launch_bounds__(BS) void k_cg_iter(
     part[4] += (double)pn * (double)wn;
     part[5] += (double)pn * (double)sn;
   };
+  // the wave's Q^T u of one slice into its LDS slot
+  auto poly_slice_sums = [&]() {
+    if constexpr (POLY) {
+#pragma unroll
+      for (int k = 0; k < kMaxPoly; ++k) {
+        const double v = wave_sum(qtu[k]);
+        if (lane == 0) ws_poly[k][wave] += v;
+      }
+    }
+  };
   if (have) {
+#pragma unroll
+    for (int k = 0; k < kMaxPoly; ++k) qtu[k] = 0.0;
     const XT wn = finish_slice<VT, XT, CT, L>(h, A, u_next);
     if ((lane & (L - 1)) == 0 && h.row < m) own_row(h.row, wn, own, p_old, x_old);
+    poly_slice_sums();
     for (slice += wstride; slice < A.nslices; slice += wstride) {
       open_slice<VT, XT, CT, L>(m, slice, A, h);
+#pragma unroll
+      for (int k = 0; k < kMaxPoly; ++k) qtu[k] = 0.0;
       const XT wn2 = finish_slice<VT, XT, CT, L>(h, A, u_next);
       if ((lane & (L - 1)) == 0 && h.row < m)
         own_row(h.row, wn2, sin[h.row], p[h.row], xlo[h.row]);
+      poly_slice_sums();
     }
   }
-  block_sums<NP, W, false>(part, ws_out);
+  block_sums<6, W, false>(part, ws_out);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int t = 0; t < NP; ++t) part_out[NP * blockIdx.x + t] = part[t];
+    for (int t = 0; t < 6; ++t) part_out[NP * blockIdx.x + t] = part[t];
+    if constexpr (POLY) {
+      // block_sums ended with a barrier after every wave's last LDS add
+      for (int k = 0; k < kMaxPoly; ++k) {
+        double v = 0.0;
+        for (int w = 0; w < W; ++w) v += ws_poly[k][w];
+        part_out[NP * blockIdx.x + 6 + k] = v;
+      }
+    }
     if (blockIdx.x == 0) {
       sc->gam[q] = gamma;
       sc->alp[q] = alpha_d;

@@ -154,6 +154,9 @@ hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, 
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
                            const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s);
+// g = A^T h alone (same sums as launch_assemble's g for the same fp32/grouped).
+hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
+                      double* g, hipStream_t s);
 // lambda from the diagonals of the m centres, then, over the ms solver rows,
 // the diagonal entries + lambda and the Jacobi scales dinv[k] (in solver rows).
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,
@@ -189,6 +192,9 @@ hipError_t launch_poly_system(const PlanView& P, int phi, const PolyBasis& B, in
 // scaled basis (dim + 1 values each); in and out may not alias.
 hipError_t launch_poly_coeffs(const double* in, const PolyBasis& B, int dim, bool to_paper,
                               double* out, hipStream_t s);
+// C, e and C^-1 alone (new sample values, Q kept).
+hipError_t launch_poly_gram(const PlanView& P, const PolyBasis& B, const double* hs, double* part,
+                            int nb, PolySys* S, hipStream_t s);
 // x = C^-1 e (the fit when no centre is active).
 hipError_t launch_poly_only(const PolySys* S, double* x, hipStream_t s);
 }  // namespace rbf

@@ -261,6 +261,11 @@ hipError_t launch_poly_system(const PlanView& P, int phi, const PolyBasis& B, in
                          (const double*)q64, q32, cnt);
     }
   }
+  return launch_poly_gram(P, B, hs, part, nb, S, s);
+}
+
+hipError_t launch_poly_gram(const PlanView& P, const PolyBasis& B, const double* hs, double* part,
+                            int nb, PolySys* S, hipStream_t s) {
   if (P.dim == 2)
     hipLaunchKernelGGL(k_poly_gram<2>, dim3(nb), dim3(kRed), 0, s, P.ps, hs, P.n, B, part);
   else

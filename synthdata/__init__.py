@@ -26,6 +26,7 @@ __all__ = [
     "streams", "uniform_points", "gaussian_mixture_points", "franke",
     "terrain_modes", "terrain_values", "grid_centers", "heldout_split",
     "Problem", "make_problem", "CONFIGS", "support_radius_for_k", "scoring_queries",
+    "halton_points",
 ]
 
 
@@ -112,6 +113,24 @@ def franke(p: np.ndarray) -> np.ndarray:
     f3 = 0.50 * np.exp(-((9 * x1 - 7) ** 2) / 4 - ((9 * x2 - 3) ** 2) / 4)
     f4 = 0.20 * np.exp(-((9 * x1 - 4) ** 2) - ((9 * x2 - 7) ** 2))
     return f1 + f2 + f3 - f4
+
+
+def halton_points(n: int, dim: int = 2, bases=(2, 3, 5)) -> np.ndarray:
+    """The first ``n`` Halton points in [0,1]^dim (radical inverses of 1..n in
+    the first ``dim`` primes), SoA ``(dim, n)``: the point set of the paper's
+    synthetic experiment (Section 6, Table 1: 1089 Halton points).  The start
+    index is not printed; 1 is taken."""
+    out = np.empty((dim, n))
+    for d in range(dim):
+        b = bases[d]
+        for i in range(n):
+            f, r, k = 1.0, 0.0, i + 1
+            while k > 0:
+                f /= b
+                r += f * (k % b)
+                k //= b
+            out[d, i] = r
+    return out
 
 
 @dataclasses.dataclass

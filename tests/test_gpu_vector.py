@@ -1,0 +1,110 @@
+"""Vector-valued data (Section 2: values h_i in E^p) through rbf_set_values.
+
+A and B depend on the points and reference points only, so the components of
+vector-valued data share them: the library assembles once and replaces g = A^T h
+(and P^T h) per component.
+
+Bars: g after rbf_set_values is bit for bit g of a fresh rbf_assemble with the
+same values (both assembly paths, float64 and float32), the coefficients of a
+component then equal those of a fresh fit bit for bit (the solver is
+deterministic), and each component's fit matches the oracle's Cholesky fit of
+that component (fitted values within 1e-9, as in test_gpu_parity).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synthdata as sd
+from oracle import rbf_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rbf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1806_07884_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def components(p):
+    return [sd.franke(p), np.sin(4 * p[0]) * np.cos(3 * p[1]), 2.0 * p[0] - p[1] + 0.5]
+
+
+@pytest.mark.parametrize("k_cover,prec", [(10.0, "fp64"), (10.0, "fp32"), (40.0, "fp64"),
+                                          (40.0, "fp32")])
+def test_set_values_equals_assembly(rbf, k_cover, prec):
+    rng = np.random.default_rng(12)
+    p = rng.random((2, 20000))
+    g_side = 40
+    ctr = sd.grid_centers(g_side, 2)
+    rho = sd.support_radius_for_k(g_side, 2, k_cover)
+    h1, h2, _ = components(p)
+    plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho, lambda_rel=1e-6)
+    info = rbf.rbf_plan_info(plan)
+    upper_mean = (info["nnz_full"] + info["n_active"]) / (2 * info["n_active"])
+    say("set_values", k_cover, prec, "upper row mean", upper_mean)
+    assert (upper_mean > 64) == (k_cover > 20)      # both assembly paths are covered
+    rbf.rbf_assemble(plan, "w31", prec, dev(h1))
+    rbf.rbf_set_values(plan, dev(h2))
+    val_a, g_a, lam_a = rbf.rbf_system_export(plan)
+    c_a, _ = rbf.rbf_solve(plan, rtol=1e-10)
+    rbf.rbf_assemble(plan, "w31", prec, dev(h2))
+    val_b, g_b, lam_b = rbf.rbf_system_export(plan)
+    c_b, _ = rbf.rbf_solve(plan, rtol=1e-10)
+    assert np.array_equal(g_a, g_b) and np.array_equal(val_a, val_b) and lam_a == lam_b
+    assert torch.equal(c_a, c_b)
+    plan.close()
+
+
+@pytest.mark.parametrize("poly", [False, True])
+def test_vector_valued_fit(rbf, poly):
+    prob = sd.make_problem("franke2d", scale=0.5)
+    p, ctr, rho = prob.points, prob.centers, prob.rho
+    H = components(p)
+    say("vector-valued", len(H), "components", "poly" if poly else "")
+    plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho, polynomial=poly)
+    rbf.rbf_assemble(plan, "w31", "fp64", dev(H[0]))
+    m = ctr.shape[1]
+    for i, h in enumerate(H):
+        if i > 0:
+            rbf.rbf_set_values(plan, dev(h))
+        ck, info = rbf.rbf_solve(plan, rtol=1e-13, max_iter=50000)
+        assert info["status"] == 0
+        ck = ck.cpu().numpy()
+        ne = orc.normal_equations(p, h, ctr, rho, "w31")
+        if poly:
+            ps = orc.poly_system(ne, p, h)
+            q, cmat, e = rbf.rbf_poly_export(plan)
+            P1 = np.abs(orc.poly_basis(p)) + 1.0
+            assert np.all(np.abs(e - ps.e) <= 1e-12 * (P1.T @ np.abs(h)))
+            c_ref, k_ref = orc.solve_poly(ne, ps)
+            P = orc.poly_basis(p)
+            ref = ne.A @ c_ref + P @ k_ref
+            fit = np.linalg.norm(ne.A @ ck[:m] + P @ ck[m:] - ref) / np.linalg.norm(ref)
+        else:
+            c_ref = orc.solve(ne)
+            ref = ne.A @ c_ref
+            fit = np.linalg.norm(ne.A @ ck - ref) / np.linalg.norm(ref)
+        say(f"component {i}: fit {fit:.2e}, iterations {info['iterations']}")
+        assert fit <= 1e-9
+    plan.close()
+
+
+def test_set_values_needs_assembly(rbf):
+    from paper_1806_07884_amd._lib import RbfError
+    plan = rbf.rbf_fit_plan(dev(np.random.rand(2, 50)), dev(sd.grid_centers(4, 2)), rho=0.3)
+    with pytest.raises(RbfError, match="assemble"):
+        rbf.rbf_set_values(plan, dev(np.random.rand(50)))

@@ -41,3 +41,13 @@ def test_radius_covers_k_centres():
 def test_franke_config_uses_printed_radius():
     p = sd.make_problem("franke2d")
     assert p.rho == 0.12 and p.points.shape == (2, 10_000) and p.centers.shape == (2, 1024)
+
+
+def test_halton_points_radical_inverse():
+    # radical inverses of 1..6 in bases 2 and 3, written out
+    p = sd.halton_points(6, 2)
+    np.testing.assert_array_equal(p[0], [1 / 2, 1 / 4, 3 / 4, 1 / 8, 5 / 8, 3 / 8])
+    np.testing.assert_allclose(p[1], [1 / 3, 2 / 3, 1 / 9, 4 / 9, 7 / 9, 2 / 9], rtol=1e-15)
+    q = sd.halton_points(1089, 2)
+    assert q.shape == (2, 1089) and np.all((q > 0) & (q < 1))
+    assert len(np.unique(q[0])) == 1089
