@@ -242,6 +242,45 @@ __device__ __forceinline__ void poly_w(const PolySys& S, int np, const double* q
   }
 }
 
+// Writes the polynomial unknowns' state (r, w, s, p, x) and the products an
+// iteration's blocks read (see PolyState).
+__device__ __forceinline__ void poly_store(const PolySys& S, int np, const double* r,
+                                           const double* w, const double* s, const double* p,
+                                           const double* x, PolyState* __restrict__ out) {
+  double u[kMaxPoly], cis[kMaxPoly], cu[kMaxPoly];
+  poly_u(S, np, r, u);
+  poly_u(S, np, s, cis);
+  const double zero[kMaxPoly] = {0.0, 0.0, 0.0, 0.0};
+  poly_w(S, np, zero, u, cu);
+  double ru = 0.0, rr = 0.0, us = 0.0, ps = 0.0, ucu = 0.0, pcu = 0.0;
+  for (int t = 0; t < kMaxPoly; ++t) {
+    out->r[t] = r[t];
+    out->w[t] = w[t];
+    out->s[t] = s[t];
+    out->p[t] = p[t];
+    out->x[t] = x[t];
+    out->u[t] = u[t];
+    out->cis[t] = cis[t];
+    out->cu[t] = cu[t];
+    ru += r[t] * u[t];
+    rr += r[t] * r[t];
+    us += u[t] * s[t];
+    ps += p[t] * s[t];
+    ucu += u[t] * cu[t];
+    pcu += p[t] * cu[t];
+  }
+  out->ru = ru;
+  out->rr = rr;
+  out->us = us;
+  out->ps = ps;
+  out->ucu = ucu;
+  out->pcu = pcu;
+}
+
+// With the polynomial block the grid has one more block than the slice
+// kernels' (n_in): it streams no slice and writes no partials, but forms the
+// polynomial unknowns' next state from the same scalars as every other block,
+// so that the others keep only a few of its values in registers.
 template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1))) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
@@ -259,8 +298,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int64_t wstride = (int64_t)gridDim.x * W;
+  const int64_t wstride = (int64_t)(POLY ? n_in : gridDim.x) * W;
   int64_t slice = (int64_t)blockIdx.x * W + wave;
+  const bool poly_block = POLY && (int)blockIdx.x == n_in;
 
   // Loads that do not depend on this iteration's scalars go out first: the
   // first slice's geometry and first batch, the row's own state, the
@@ -268,7 +308,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   SliceHead<XT> h;
   CgState<XT> own;
   XT p_old = (XT)0, x_old = (XT)0;
-  const bool have = slice < A.nslices;
+  const bool have = !poly_block && slice < A.nslices;
   if (have) {
     open_slice<VT, XT, CT, L>(m, slice, A, h);
     if ((lane & (L - 1)) == 0 && h.row < m) {
@@ -290,6 +330,25 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   const double trigger2 = sc->trigger2;
   const double fgamma = sc->fix_gamma, frr = sc->fix_rr;
   const double falpha = sc->fix_alpha, fbeta = sc->fix_beta;
+  // the polynomial record of state buffer q, loaded before the barrier
+  double rw[kMaxPoly], ru_[kMaxPoly], rp_[kMaxPoly], rcu[kMaxPoly], rcis[kMaxPoly];
+  double rsum[6];
+  if constexpr (POLY) {
+#pragma unroll
+    for (int t = 0; t < kMaxPoly; ++t) {
+      rw[t] = pin->w[t];
+      ru_[t] = pin->u[t];
+      rp_[t] = pin->p[t];
+      rcu[t] = pin->cu[t];
+      rcis[t] = pin->cis[t];
+    }
+    rsum[0] = pin->ru;
+    rsum[1] = pin->ucu;
+    rsum[2] = pin->rr;
+    rsum[3] = pin->us;
+    rsum[4] = pin->pcu;
+    rsum[5] = pin->ps;
+  }
   // one barrier publishes both the block's partial sums and the flag
 #pragma unroll
   for (int t = 0; t < NP; ++t) red[t] = wave_sum(red[t]);
@@ -306,32 +365,28 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
     for (int w = 0; w < W; ++w) v += ws[t][w];
     red[t] = v;
   }
-  // polynomial unknowns: state of buffer q, u = C^-1 r and w = Q^T u + C u
-  // (w from the refresh after one)
-  double pr[kMaxPoly], pw[kMaxPoly], ps[kMaxPoly], pp[kMaxPoly], px[kMaxPoly], pu[kMaxPoly];
+  // polynomial unknowns: w = Q^T u + C u (from the refresh after one) and
+  // their share of every product, from the record of state buffer q
+  double pw[kMaxPoly];
   if constexpr (POLY) {
-#pragma unroll
-    for (int t = 0; t < kMaxPoly; ++t) {
-      pr[t] = pin->r[t];
-      ps[t] = pin->s[t];
-      pp[t] = pin->p[t];
-      px[t] = pin->x[t];
-    }
-    poly_u(*psys, np, pr, pu);
     if (fixed) {
 #pragma unroll
-      for (int t = 0; t < kMaxPoly; ++t) pw[t] = pin->w[t];
+      for (int t = 0; t < kMaxPoly; ++t) pw[t] = rw[t];
     } else {
-      poly_w(*psys, np, red + 6, pu, pw);
+      double a1 = 0.0, a4 = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxPoly; ++t) {
-        red[0] += pr[t] * pu[t];
-        red[1] += pw[t] * pu[t];
-        red[2] += pr[t] * pr[t];
-        red[3] += pu[t] * ps[t];
-        red[4] += pp[t] * pw[t];
-        red[5] += pp[t] * ps[t];
+        const double qs = red[6 + t];
+        pw[t] = qs + rcu[t];
+        a1 += qs * ru_[t];
+        a4 += rp_[t] * qs;
       }
+      red[0] += rsum[0];
+      red[1] += a1 + rsum[1];
+      red[2] += rsum[2];
+      red[3] += rsum[3];
+      red[4] += a4 + rsum[4];
+      red[5] += rsum[5];
     }
   }
   const double gamma = fixed ? fgamma : red[0];
@@ -360,29 +415,28 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
     return;
   }
   const XT alpha = (XT)alpha_d, beta = (XT)beta_d;
-  // the polynomial unknowns' step, and their next u for the rows of B
+  // the polynomial unknowns' next u for the rows of B:
+  // u' = C^-1 (r - alpha (w + beta s)) = u - alpha (C^-1 w + beta C^-1 s)
   XT uq[kMaxPoly];
   if constexpr (POLY) {
-    double rn[kMaxPoly], un[kMaxPoly];
+    double ciw[kMaxPoly];
+    poly_u(*psys, np, pw, ciw);
 #pragma unroll
-    for (int t = 0; t < kMaxPoly; ++t) {
-      pp[t] = pu[t] + beta_d * pp[t];
-      ps[t] = pw[t] + beta_d * ps[t];
-      px[t] = px[t] + alpha_d * pp[t];
-      rn[t] = pr[t] - alpha_d * ps[t];
-    }
-    poly_u(*psys, np, rn, un);
-#pragma unroll
-    for (int t = 0; t < kMaxPoly; ++t) uq[t] = (XT)un[t];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-#pragma unroll
-      for (int t = 0; t < kMaxPoly; ++t) {
-        pout->r[t] = rn[t];
-        pout->w[t] = pw[t];
-        pout->s[t] = ps[t];
-        pout->p[t] = pp[t];
-        pout->x[t] = px[t];
+    for (int t = 0; t < kMaxPoly; ++t)
+      uq[t] = (XT)(ru_[t] - alpha_d * (ciw[t] + beta_d * rcis[t]));
+    if (poly_block) {
+      // the state of the next iteration, written by the extra block
+      if (threadIdx.x == 0) {
+        double rn[kMaxPoly], sn[kMaxPoly], pn[kMaxPoly], xn[kMaxPoly];
+        for (int t = 0; t < kMaxPoly; ++t) {
+          pn[t] = pin->u[t] + beta_d * pin->p[t];
+          sn[t] = pw[t] + beta_d * pin->s[t];
+          xn[t] = pin->x[t] + alpha_d * pn[t];
+          rn[t] = pin->r[t] - alpha_d * sn[t];
+        }
+        poly_store(*psys, np, rn, pw, sn, pn, xn, pout);
       }
+      return;
     }
   }
   auto u_next = [&](int32_t l) -> XT {
@@ -679,21 +733,20 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_refresh_scalars(
       for (int t = 0; t < kMaxPoly; ++t) pr[t] = pin->r[t];
       poly_u(*psys, np, pr, pu);
       poly_w(*psys, np, v + 6, pu, pw);
+      double ps[kMaxPoly], pp[kMaxPoly], px[kMaxPoly];
       for (int t = 0; t < kMaxPoly; ++t) {
-        const double pp = pin->p[t], ps = pin->s[t];
+        pp[t] = pin->p[t];
+        ps[t] = pin->s[t];
+        px[t] = pin->x[t];
         v[0] += pr[t] * pu[t];
         v[1] += pw[t] * pu[t];
         v[2] += pr[t] * pr[t];
-        v[3] += pp * pw[t];
-        v[4] += pu[t] * ps;
-        v[5] += pp * ps;
-        pout->r[t] = pr[t];
-        pout->w[t] = pw[t];
-        pout->s[t] = ps;
-        pout->p[t] = pp;
-        pout->x[t] = pin->x[t];
-        xpoly[t] = pin->x[t];
+        v[3] += pp[t] * pw[t];
+        v[4] += pu[t] * ps[t];
+        v[5] += pp[t] * ps[t];
+        xpoly[t] = px[t];
       }
+      poly_store(*psys, np, pr, pw, ps, pp, px, pout);
     }
     const double gamma = v[0], delta = v[1], rr = v[2];
     const double beta = restart ? 0.0 : gamma / sc->gam[q_prev];
@@ -728,10 +781,13 @@ __global__ void k_cg_clear(int64_t m, const XT* __restrict__ dinv, XT* __restric
                            PolyState* __restrict__ p1, const double* __restrict__ xpoly) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p0 && j == 0) {
-    for (int t = 0; t < kMaxPoly; ++t) {
-      p0->r[t] = p0->w[t] = p0->s[t] = p0->p[t] = 0.0;
-      p1->r[t] = p1->w[t] = p1->s[t] = p1->p[t] = 0.0;
-      p0->x[t] = p1->x[t] = xpoly[t];
+    for (PolyState* st : {p0, p1}) {
+      for (int t = 0; t < kMaxPoly; ++t) {
+        st->r[t] = st->w[t] = st->s[t] = st->p[t] = 0.0;
+        st->u[t] = st->cis[t] = st->cu[t] = 0.0;
+        st->x[t] = xpoly[t];
+      }
+      st->ru = st->rr = st->us = st->ps = st->ucu = st->pcu = 0.0;
     }
   }
   if (j >= m) return;
@@ -780,12 +836,13 @@ void launch_iter_p(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hip
   PolyState* pout = POLY ? a.pst[q ^ 1] : nullptr;
   if (e0) {
     // the extended launch stamps the events at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s,
-                          e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p,
+    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
+                          dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p,
                           a.xlo, a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, q,
                           fixed, a.np, a.Q, a.psys, pin, pout);
   } else {
-    hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+    hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
+                       dim3(BS), 0, s, a.m,
                        A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed, a.np, a.Q,
                        a.psys, pin, pout);

@@ -64,9 +64,14 @@ struct PolySys {
   int32_t bad;                    // P^T P is not positive definite
 };
 // The polynomial unknowns' share of the CG state (see CgState), with the
-// search direction p and the solution x, which the rows of B keep apart.
+// search direction p and the solution x, which the rows of B keep apart,
+// and what an iteration's blocks need of it, formed once by the launch that
+// writes the state: u = C^-1 r, C^-1 s, C u and the products r.u, r.r, u.s,
+// p.s, u.C u, p.C u.
 struct PolyState {
   double r[kMaxPoly], w[kMaxPoly], s[kMaxPoly], p[kMaxPoly], x[kMaxPoly];
+  double u[kMaxPoly], cis[kMaxPoly], cu[kMaxPoly];
+  double ru, rr, us, ps, ucu, pcu;
 };
 // Partial sums per block: the six dot products, then Q^T u (or Q^T x).
 constexpr int kCgParts = 6 + kMaxPoly;
