@@ -33,6 +33,14 @@
 // stored system, recomputes w = B D^-1 r and sets alpha, beta of the next
 // iteration from the same expanded product, the direction kept (or reset).
 //
+// With linear polynomial reproduction (Section 3, eq. 10) the system is
+// bordered by Q = A^T P and C = P^T P.  The d + 1 polynomial unknowns are a
+// replicated float64 block (PolyState): every block reads its record, a row of
+// B adds Q_j u_poly to its w, and Q^T u joins the partial sums, from which the
+// next launch forms the polynomial rows' w and their share of every product.
+// One extra block per launch writes the block's next state.  Preconditioner:
+// D^-1 on B's rows, C^-1 on the polynomial block.
+//
 // Precision: matrix and iterated vectors are VT / XT (float64, or float32
 // for the mixed path); every dot product is a float64 sum of float64
 // products; the solution is accumulated in float64 at every reliable update.
