@@ -19,6 +19,11 @@ with both held-out RMSEs (matched when they agree to 0.1 %).
 uniform queries against the clean field) time the same step on the larger
 workloads; the oracle baseline is taken for terrain2d only.
 ``--polynomial`` fits with linear polynomial reproduction (Section 3).
+``--components p`` fits vector-valued data (p terrain fields of the same
+points): one plan and assembly, then rbf_set_values and rbf_solve per
+component (or, with ``--batch``, rbf_solve_batch: all components in one CG
+kernel per iteration); throughput counts N points per fit of all p
+components.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -108,6 +113,10 @@ def main() -> int:
     ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
     ap.add_argument("--polynomial", action="store_true",
                     help="linear polynomial reproduction (bordered system of eq. 10)")
+    ap.add_argument("--components", type=int, default=1,
+                    help="vector-valued data: components sharing the points (B assembled once)")
+    ap.add_argument("--batch", action="store_true",
+                    help="with --components 2..4: solve all components in one batched CG")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -142,14 +151,35 @@ def main() -> int:
     n_train = prob.points.shape[1]
     torch.cuda.synchronize()
 
+    # further components of vector-valued data: other terrain fields of the same points
+    extra = []
+    for k in range(1, max(1, args.components)):
+        r = sd.streams(7000 + k, 2)
+        modes = sd.terrain_modes(r[0], 256 if prob.dim == 2 else 128, prob.dim)
+        hk = sd.terrain_values(modes, prob.points) + 1e-3 * r[1].standard_normal(n_train)
+        qk = sd.terrain_values(modes, q)
+        extra.append((dev(hk), dev(qk)))
+    stacked = torch.stack([vals] + [hk for hk, _ in extra]) if args.batch and extra else None
+    torch.cuda.synchronize()
+
     def fit(prec: str, profile: bool = False):
         plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL,
                                 polynomial=args.polynomial)
         if profile:
             rbf.rbf_profile(plan, True)
         rbf.rbf_assemble(plan, prob.phi, prec, vals)
+        if stacked is not None:
+            C, infos = rbf.rbf_solve_batch(plan, stacked, rtol=RTOL, max_iter=200000)
+            _, rmse = rbf.rbf_eval(plan, tpts, C[0].contiguous(), values=tvals)
+            for k in range(1, C.shape[0]):
+                rbf.rbf_eval(plan, tpts, C[k].contiguous())
+            return plan, infos[0], rmse
         c, info = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
         _, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+        for hk, qk in extra:
+            rbf.rbf_set_values(plan, hk)
+            ck, _ = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
+            rbf.rbf_eval(plan, tpts, ck)
         return plan, info, rmse
 
     def timed(prec: str, steps: int, warm: int):
@@ -162,7 +192,7 @@ def main() -> int:
         spmv_n, spmv_ms, asm_ms = 0, 0.0, 0.0
         for _ in range(steps):
             plan, info, rmse = fit(prec, profile=True)
-            n, ms = rbf.rbf_profile_read(plan, "cg_iter")
+            n, ms = rbf.rbf_profile_read(plan, "cg_iter_batch" if stacked is not None else "cg_iter")
             _, ams = rbf.rbf_profile_read(plan, "assemble")
             spmv_n += n
             spmv_ms += ms
@@ -222,7 +252,9 @@ def main() -> int:
                    "n_active": int(m), "grid": prob.grid,
                    "phi": prob.phi, "rho": prob.rho, "lambda_rel": LAMBDA_REL, "rtol": RTOL,
                    "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates",
-                   "polynomial": "linear" if npoly else "none"},
+                   "polynomial": "linear" if npoly else "none",
+                   "components": max(1, args.components),
+                   "batched_solve": stacked is not None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": {"ms_per_fit": dt32 * 1e3, "iterations": per32[-1][0]["iterations"],

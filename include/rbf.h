@@ -209,6 +209,23 @@ int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, do
  * NULL. */
 int rbf_solve(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info);
 
+/* Solve for nrhs right-hand sides at once (vector-valued data, h_i in E^p,
+ * Section 2): component k of the samples at values + k N (device [nrhs][N],
+ * caller's point order), its coefficients at coeffs + k M (device
+ * [nrhs][M]; input too when opts->warm_start); info: host [nrhs] or NULL.
+ * Uses B and the precision of the last rbf_assemble; each component's g is
+ * formed as rbf_set_values forms it (the plan is left holding the last
+ * component's values).  One CG kernel per iteration serves every component,
+ * so B is streamed once per iteration for all of them; a reliable update of
+ * one refreshes all, and a component whose float64 residual meets rtol at a
+ * refresh stops while the others go on (info[k].iterations: the iteration at
+ * which it did).  2 <= nrhs <= 4; no polynomial block (call rbf_set_values and
+ * rbf_solve per component instead); no float64 fallback: a stalled mixed
+ * solve ends at max_iter with WARN_MAXITER.  Blocks the host as rbf_solve.
+ * Errors: INVALID, BREAKDOWN, HIP, OOM. */
+int rbf_solve_batch(rbf_plan* plan, int32_t nrhs, const double* values,
+                    const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info);
+
 /* Evaluate the approximant (eq. 3) at n_query points: out[q] =
  * sum_j coeffs[j] phi(||y_q - xi_j|| / rho_j) over centres with y_q in their
  * support (plus a^T y_q + a_0 with a polynomial, eq. 6), basis of the last
@@ -229,6 +246,7 @@ int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
  * summed duration in milliseconds.  Both block the host (stream sync).
  * Kernel ids: */
 #define RBF_KERNEL_CG_ITER 0   /* one CG iteration: vector updates, w = B D^-1 r, dot products */
+#define RBF_KERNEL_CG_ITER_BATCH 1  /* one iteration of rbf_solve_batch (all right-hand sides) */
 #define RBF_KERNEL_ASSEMBLE 2  /* numeric assembly of B and g */
 int rbf_profile(rbf_plan* plan, int32_t enable);
 int rbf_profile_read(rbf_plan* plan, int32_t kernel, int64_t* launches, double* total_ms);

@@ -11,6 +11,7 @@ step of the computation runs in the HIP kernels of librbf.so:
 """
 from .binding import (Plan, rbf_assemble, rbf_eval, rbf_fit_plan, rbf_plan_info,  # noqa: F401
                       rbf_plan_pattern, rbf_solve, rbf_system_export, rbf_poly_export, rbf_set_values,
+                      rbf_solve_batch,
                       rbf_plan_destroy,
                       rbf_profile, rbf_profile_read, rbf_density_features, rbf_block_sq_err,
                       rbf_radius_broadcast, Mlp)

@@ -21,7 +21,7 @@ RBF_ERR_BREAKDOWN = -4
 RBF_ERR_HIP = -5
 RBF_ERR_OOM = -6
 
-KERNEL = {"cg_iter": 0, "assemble": 2}
+KERNEL = {"cg_iter": 0, "cg_iter_batch": 1, "assemble": 2}
 MLP_PARAMS = 5313
 MLP_INPUTS = 16
 MAX_RADII = 8
@@ -85,6 +85,9 @@ SIGNATURES = {
     "rbf_poly_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
     "rbf_set_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rbf_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.POINTER(SolveOpts), ctypes.c_void_p,
+                                       ctypes.POINTER(SolveInfo)]),
     "rbf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
                                  ctypes.POINTER(SolveInfo)]),
     "rbf_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,

@@ -192,6 +192,33 @@ def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1
                     "status": info.status}
 
 
+def rbf_solve_batch(plan: Plan, values: torch.Tensor, coeffs: Optional[torch.Tensor] = None,
+                    rtol: float = 1e-10, max_iter: int = 100000, warm_start: bool = False,
+                    check_every: int = 32, reliable_delta: float = 0.1):
+    """All components of vector-valued data at once (rbf_solve_batch): values
+    (p, N) with 2 <= p <= 4.  Returns (coeffs (p, M), [info per component])."""
+    _need(values, "values")
+    if values.dim() != 2 or values.shape[1] != plan.n:
+        raise ValueError("values must be (p, N)")
+    nr = int(values.shape[0])
+    if coeffs is None:
+        coeffs = torch.zeros((nr, plan.m), dtype=torch.float64, device=plan.device)
+    _need(coeffs, "coeffs", (nr, plan.m))
+    opts = L.SolveOpts(float(rtol), int(max_iter), int(bool(warm_start)), int(check_every),
+                       float(reliable_delta))
+    infos = (L.SolveInfo * max(nr, 1))()
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_solve_batch(plan.handle, nr, values.data_ptr(), ctypes.byref(opts),
+                                     coeffs.data_ptr(), infos)
+    L.check(st, "rbf_solve_batch")
+    plan._keep = [values]
+    out = [{"iterations": f.iterations, "reliable_updates": f.reliable_updates,
+            "rel_residual": f.rel_residual, "lambda": f.lambda_,
+            "precision": "fp64" if f.precision == 0 else "fp32", "status": f.status}
+           for f in infos[:nr]]
+    return coeffs, out
+
+
 def rbf_eval(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
              out: Optional[torch.Tensor] = None, values: Optional[torch.Tensor] = None):
     """f at the query points (eq. 3, or eq. 6 with a polynomial), and the RMSE

@@ -146,6 +146,16 @@ struct rbf_plan {
   rbf::PolySys* psys = nullptr;
   rbf::PolyState* pst = nullptr;  // [2], by state buffer
   double* xpoly = nullptr;        // [kMaxPoly] polynomial unknowns in the scaled basis
+  // batched solve (several right-hand sides; sized for kMaxRhs)
+  void* bst[2][2] = {};           // [precision: 0 float64, 1 float32][state buffer]
+  void* bvec[2][2] = {};          // [precision][p, x_lo], [kMaxRhs][ms]
+  double* bxhi = nullptr;         // [kMaxRhs][ms]
+  double* br64 = nullptr;
+  double* bg = nullptr;
+  double* bpart_it = nullptr;     // [2][6 kMaxRhs kCgMaxBlocks]
+  double* bpart_ref = nullptr;
+  rbf::CgScalarsN* bsc = nullptr;
+  rbf::CgScalarsN* host_bsc = nullptr;  // pinned, two snapshot slots
   void* vec64[4] = {};         // state buffers 0 and 1 (4 per row), p, x_lo
   void* vec32[4] = {};
   double* cs_sorted = nullptr;
@@ -254,6 +264,7 @@ struct rbf_plan {
     if (stream) (void)hipStreamSynchronize(stream);
     while (!bufs.empty()) release(bufs.back().p);
     if (host_sc) pinned_release(host_sc);
+    if (host_bsc) (void)hipHostFree(host_bsc);
     for (hipEvent_t e : snap_ev)
       if (e) (void)hipEventDestroy(e);
     for (const Pending& q : pending) {
@@ -736,6 +747,172 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   }
 }
 
+// Batched solve of nr right-hand sides (see run_cg; one CG kernel per
+// iteration serves all of them).  A trigger of any right-hand side refreshes
+// them all; a converged one is frozen by the refresh.  The float64 solutions
+// are left in P->bxhi.
+template <typename VT, typename XT>
+int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
+            const rbf_solve_opts& o, int64_t* iters, int64_t* updates) {
+  hipStream_t s = P->stream;
+  rbf::CgArgsN<XT> a;
+  a.m = P->ms;
+  a.nr = nr;
+  a.st[0] = P->bst[prec_idx][0];
+  a.st[1] = P->bst[prec_idx][1];
+  a.p = (XT*)P->bvec[prec_idx][0];
+  a.xlo = (XT*)P->bvec[prec_idx][1];
+  a.dinv = dinv;
+  a.xhi = P->bxhi;
+  a.r64 = P->br64;
+  a.sc = P->bsc;
+  a.part[0] = P->bpart_it;
+  a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
+  a.part_ref = P->bpart_ref;
+  rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
+  rbf::CgMatrix A;
+  A.sptr = P->sptr;
+  A.slen = P->slen;
+  A.nslices = P->nslices;
+  A.col = P->scol;
+  A.col16 = P->col16;
+  A.val = val;
+  A.lanes = P->lanes;
+  HIPCHK(rbf::cgn_setup<XT>(a, P->bg, o.rtol, o.reliable_delta, s));
+  // start: float64 residuals of the initial x on state buffer 0
+  HIPCHK(rbf::cgn_refresh<VT, XT>(a, A, P->bg, 0, 1, 1, s));
+  int64_t refreshes = 1, launched = 0;
+  const int64_t budget = o.max_iter;
+  bool fixed = true;
+  bool near = false;
+  // queue one chunk and its snapshot into slot `slot`
+  auto enqueue = [&](int slot, bool* queued) -> int {
+    *queued = false;
+    const int64_t step = near ? std::min<int64_t>(o.check_every, 8) : o.check_every;
+    const int64_t chunk = std::min<int64_t>(budget - launched, step);
+    if (chunk <= 0) return RBF_OK;
+    for (int64_t it = 0; it < chunk; ++it) {
+      const int q = (int)((launched + refreshes) & 1);
+      const bool timed = P->prof_on && (it & 3) == 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = P->event();
+        e1 = P->event();
+        if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
+      }
+      HIPCHK(rbf::cgn_iterate<VT, XT>(a, A, q, fixed ? 1 : 0, e0, e1, s));
+      if (timed) P->pending.push_back({1, launched, e0, e1});
+      fixed = false;
+      ++launched;
+    }
+    HIPCHK(hipMemcpyAsync(P->host_bsc + slot, P->bsc, sizeof(rbf::CgScalarsN),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(P->snap_ev[slot], s));
+    *queued = true;
+    return RBF_OK;
+  };
+  // chunks shrink once some active right-hand side nears its trigger
+  auto seen = [&](const rbf::CgScalarsN& h) {
+    near = false;
+    for (int k = 0; k < nr; ++k)
+      if (h.active[k] && h.rr[k] <= 3.0 * h.trigger2[k]) near = true;
+  };
+  int cur = 0;
+  bool cur_q = false;
+  int rc = enqueue(cur, &cur_q);
+  if (rc) return rc;
+  for (;;) {
+    rbf::CgScalarsN h;
+    if (cur_q) {
+      bool next_q = false;
+      rc = enqueue(cur ^ 1, &next_q);
+      if (rc) return rc;
+      HIPCHK(hipEventSynchronize(P->snap_ev[cur]));
+      h = P->host_bsc[cur];
+      seen(h);
+      if (h.done == 0 && next_q) {
+        *iters = h.iter;
+        if (P->prof_on) P->resolve(h.iter, false);
+        cur ^= 1;
+        continue;
+      }
+      // a flag is up (or the budget is spent): take the latest state
+      if (next_q) {
+        HIPCHK(hipEventSynchronize(P->snap_ev[cur ^ 1]));
+        h = P->host_bsc[cur ^ 1];
+      }
+    } else {
+      HIPCHK(hipMemcpyAsync(P->host_bsc, P->bsc, sizeof(rbf::CgScalarsN), hipMemcpyDeviceToHost,
+                            s));
+      HIPCHK(hipStreamSynchronize(s));
+      h = *P->host_bsc;
+    }
+    *iters = h.iter;
+    if (P->prof_on) P->resolve(h.iter, true);
+    const int q = (int)((h.iter + refreshes) & 1);
+    if (h.done == 3) return RBF_OK;
+    if (h.done == 2) return fail(RBF_ERR_BREAKDOWN, "CG breakdown after %lld iterations",
+                                 (long long)h.iter);
+    if (h.done == 1) {
+      HIPCHK(rbf::cgn_refresh<VT, XT>(a, A, P->bg, q, q ^ 1, 0, s));
+      ++refreshes;
+      *updates += 1;
+      fixed = true;
+      near = false;
+      launched = h.iter;  // every queued launch has run; later ones returned at entry
+      cur = 0;
+      rc = enqueue(cur, &cur_q);
+      if (rc) return rc;
+      if (cur_q) continue;
+    }
+    // iteration budget spent: the float64 residuals decide
+    HIPCHK(rbf::cgn_refresh<VT, XT>(a, A, P->bg, q, q ^ 1, 1, s));
+    HIPCHK(hipMemcpyAsync(P->host_bsc, P->bsc, sizeof(rbf::CgScalarsN), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    return P->host_bsc->done == 3 ? RBF_OK : RBF_WARN_MAXITER;
+  }
+}
+
+// Buffers of the batched solve (sized for kMaxRhs right-hand sides).
+int ensure_batch(rbf_plan* P, bool fp32) {
+  const int64_t m = std::max<int64_t>(P->ms, 1);
+  const int64_t nb = (int64_t)rbf::kMaxRhs * m;
+  if (!P->bsc) {
+    GET(P->bxhi, nb);
+    GET(P->br64, nb);
+    GET(P->bg, nb);
+    GET(P->bpart_it, 2 * 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks);
+    GET(P->bpart_ref, 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks);
+    GET(P->bsc, 1);
+  }
+  const int pi = fp32 ? 1 : 0;
+  const size_t rec = fp32 ? sizeof(rbf::CgStateN<float, rbf::kMaxRhs>)
+                          : sizeof(rbf::CgStateN<double, rbf::kMaxRhs>);
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  for (int b = 0; b < 2; ++b) {
+    if (!P->bst[pi][b]) {
+      P->bst[pi][b] = P->alloc_bytes(rec * (size_t)m);
+      if (!P->bst[pi][b]) return fail(RBF_ERR_OOM, "batched solver state allocation failed");
+    }
+    if (!P->bvec[pi][b]) {
+      P->bvec[pi][b] = P->alloc_bytes(es * (size_t)nb);
+      if (!P->bvec[pi][b]) return fail(RBF_ERR_OOM, "batched solver vector allocation failed");
+    }
+  }
+  if (!P->host_bsc) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 2 * sizeof(rbf::CgScalarsN), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RBF_ERR_OOM, "pinned host allocation failed");
+    }
+    P->host_bsc = static_cast<rbf::CgScalarsN*>(h);
+  }
+  for (hipEvent_t& e : P->snap_ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return RBF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1100,6 +1277,83 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
     info->status = rc;
   }
   return rc;
+}
+
+int rbf_solve_batch(rbf_plan* P, int32_t nrhs, const double* values,
+                    const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!values || !coeffs) return fail(RBF_ERR_INVALID, "values/coeffs is NULL");
+  if (nrhs < 2 || nrhs > rbf::kMaxRhs)
+    return fail(RBF_ERR_INVALID, "nrhs must be in [2, %d]", rbf::kMaxRhs);
+  if (P->prec < 0) return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_solve_batch");
+  if (P->npoly)
+    return fail(RBF_ERR_INVALID,
+                "the batched solve takes no polynomial block (use rbf_set_values and "
+                "rbf_solve per component)");
+  rbf_solve_opts o;
+  o.rtol = 1e-10;
+  o.max_iter = 100000;
+  o.warm_start = 0;
+  o.check_every = 32;
+  o.reliable_delta = 0.1;
+  if (opts) o = *opts;
+  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 ||
+      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0))
+    return fail(RBF_ERR_INVALID, "bad solve options");
+  const bool fp32 = P->prec == RBF_PREC_FP32_REFINE;
+  int rc = ensure_solver(P, fp32);
+  if (rc) return rc;
+  rc = ensure_batch(P, fp32);
+  if (rc) return rc;
+  hipStream_t s = P->stream;
+  const int64_t m = P->m, ms = P->ms;
+  double lam = 0.0;
+  int64_t iters = 0, updates = 0;
+  if (ms == 0) {
+    // no centre has a support: every coefficient is 0
+    HIPCHK(hipMemsetAsync(coeffs, 0, sizeof(double) * m * nrhs, s));
+  } else {
+    // g of every component as rbf_set_values forms it, over the solver rows
+    for (int k = 0; k < nrhs; ++k) {
+      HIPCHK(rbf::launch_gather(values + (int64_t)k * P->n, P->pperm, P->n, P->hs, s));
+      HIPCHK(rbf::launch_rhs(P->view(), P->phi, fp32, P->grouped, P->hs, P->g, s));
+      HIPCHK(rbf::launch_gather(P->g, P->srow, ms, P->bg + (int64_t)k * ms, s));
+      if (o.warm_start)
+        HIPCHK(rbf::launch_gather(coeffs + (int64_t)k * m, P->srow, ms,
+                                  P->bxhi + (int64_t)k * ms, s));
+    }
+    if (!o.warm_start) HIPCHK(hipMemsetAsync(P->bxhi, 0, sizeof(double) * ms * nrhs, s));
+    if (fp32)
+      rc = run_cgn<float, float>(P, P->val32, P->dinv32, nrhs, 1, o, &iters, &updates);
+    else
+      rc = run_cgn<double, double>(P, P->val64, P->dinv64, nrhs, 0, o, &iters, &updates);
+    if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;
+    for (int k = 0; k < nrhs; ++k)
+      HIPCHK(rbf::launch_scatter_rows(P->bxhi + (int64_t)k * ms, P->amap, m,
+                                      coeffs + (int64_t)k * m, s));
+    HIPCHK(hipMemcpyAsync(P->host_bsc, P->bsc, sizeof(rbf::CgScalarsN), hipMemcpyDeviceToHost,
+                          s));
+  }
+  HIPCHK(hipMemcpyAsync(&lam, P->lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    for (int k = 0; k < nrhs; ++k) {
+      rbf_solve_info& f = info[k];
+      f.reliable_updates = updates;
+      f.lambda = lam;
+      f.precision = P->prec;
+      f.status = ms == 0 ? RBF_OK : rc;
+      if (ms == 0) {
+        f.iterations = 0;
+        f.rel_residual = 0.0;
+        continue;
+      }
+      const rbf::CgScalarsN& h = *P->host_bsc;
+      f.iterations = h.conv_iter[k] >= 0 ? h.conv_iter[k] : iters;
+      f.rel_residual = h.gg[k] > 0 ? sqrt(h.rr_true[k] / h.gg[k]) : 0.0;
+    }
+  }
+  return ms == 0 ? RBF_OK : rc;
 }
 
 int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,

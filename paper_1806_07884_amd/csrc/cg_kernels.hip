@@ -1017,4 +1017,645 @@ template hipError_t cg_setup<double>(const CgArgs<double>&, const double*, doubl
 template hipError_t cg_setup<float>(const CgArgs<float>&, const double*, double, double,
                                     hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides (vector-valued data): NR independent solves of the
+// same system in one kernel per iteration, each exactly the iteration above
+// with its own scalars.  The matrix is streamed once for all of them; a
+// neighbour's record holds its d and the (r, w, s) of every right-hand side,
+// so it is gathered once per stored entry.
+namespace {
+
+// Steps per batch: the gathered records are (1 + 3 NR) values wide, so the
+// batches are shorter than the single solve's to keep the same registers.
+template <typename XT, int NR>
+constexpr int kBatchN = sizeof(XT) == 4 ? (NR <= 2 ? 8 : 4) : (NR <= 2 ? 4 : 2);
+
+template <typename XT, int U>
+struct SliceHeadU {
+  int64_t row, base;
+  int32_t rowc;
+  int steps;
+  int32_t l[U];
+  XT v[U];
+};
+
+template <typename VT, typename XT, typename CT, int U>
+__device__ __forceinline__ void load_batch_u(const CgMatrix& A, int64_t base, int32_t rowc, int st,
+                                             int steps, int32_t* l, XT* v) {
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  // unconditional loads (at most 7 steps past a slice, inside the zeroed tail)
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const int64_t o = base + (int64_t)(st + t) * kWave;
+    const int32_t c = (int32_t)col[o];
+    const XT x = (XT)val[o];
+    const bool in = st + t < steps;
+    l[t] = rowc + (in ? c : 0);
+    v[t] = in ? x : (XT)0;
+  }
+}
+
+template <typename VT, typename XT, typename CT, int L, int U>
+__device__ __forceinline__ void open_slice_u(int64_t m, int64_t slice, const CgMatrix& A,
+                                             SliceHeadU<XT, U>& h) {
+  constexpr int S = kWave / L;
+  const int lane = threadIdx.x & (kWave - 1);
+  h.row = slice * S + lane / L;
+  h.rowc = (int32_t)(h.row < m ? h.row : m - 1);
+  h.base = A.sptr[slice] + lane;
+  h.steps = A.slen[slice] / L;
+  load_batch_u<VT, XT, CT, U>(A, h.base, h.rowc, 0, h.steps, h.l, h.v);
+}
+
+// Row sums of an opened slice for every right-hand side: wn[k] =
+// sum_e b_e u_k(col_e), complete in the lane with (lane % L) == 0.
+template <typename VT, typename XT, typename CT, int L, int U, int NR>
+__device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const CgMatrix& A,
+                                               const CgStateN<XT, NR>* __restrict__ sin,
+                                               const XT* alpha, const XT* beta, XT* wn) {
+  XT acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = (XT)0;
+  int32_t cl[U], nl[U];
+  XT cv[U], nv[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    cl[t] = h.l[t];
+    cv[t] = h.v[t];
+  }
+  for (int st = U;; st += U) {
+    const bool more = st < h.steps;
+    if (more) load_batch_u<VT, XT, CT, U>(A, h.base, h.rowc, st, h.steps, nl, nv);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const CgStateN<XT, NR> r = sin[cl[t]];
+#pragma unroll
+      for (int k = 0; k < NR; ++k)
+        acc[k] += cv[t] * (r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k]));
+    }
+    if (!more) break;
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      cl[t] = nl[t];
+      cv[t] = nv[t];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    XT a = acc[k];
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+    wn[k] = a;
+  }
+}
+
+template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_cgn_iter(
+    int64_t m, CgMatrix A, const CgStateN<XT, NR>* __restrict__ sin,
+    CgStateN<XT, NR>* __restrict__ sout, XT* __restrict__ p, XT* __restrict__ xlo,
+    CgScalarsN* __restrict__ sc, const double* __restrict__ part_in,
+    double* __restrict__ part_out, int n_in, int q, int fixed) {
+  constexpr int W = BS / kWave;
+  constexpr int NPT = 6 * NR;
+  constexpr int U = kBatchN<XT, NR>;
+  __shared__ double ws[NPT][W];
+  // this iteration's partials, per wave (added slice by slice, so that they
+  // hold no registers across the streamed loop)
+  __shared__ double ws_acc[NPT][W];
+  __shared__ int s_flag;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int64_t wstride = (int64_t)gridDim.x * W;
+  int64_t slice = (int64_t)blockIdx.x * W + wave;
+  SliceHeadU<XT, U> h;
+  const bool have = slice < A.nslices;
+  if (have) open_slice_u<VT, XT, CT, L, U>(m, slice, A, h);
+  // the previous kernel's partials, one right-hand side at a time
+  if (!fixed) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int b = threadIdx.x; b < n_in; b += BS) {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) r6[t] += part_in[(int64_t)b * NPT + 6 * k + t];
+      }
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const double v = wave_sum(r6[t]);
+        if (lane == 0) ws[6 * k + t][wave] = v;
+      }
+    }
+  }
+  if (threadIdx.x == 0) s_flag = sc->done;
+  __syncthreads();
+  if (s_flag) return;
+  XT alpha[NR], beta[NR];
+  double alpha_d[NR], gamma_d[NR], rr_d[NR];
+  bool act[NR];
+  int flag = 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    act[k] = sc->active[k] != 0;
+    double gamma, rr, a, b;
+    if (fixed) {
+      gamma = sc->fix_gamma[k];
+      rr = sc->fix_rr[k];
+      a = sc->fix_alpha[k];
+      b = sc->fix_beta[k];
+    } else {
+      double v[6];
+      for (int t = 0; t < 6; ++t) {
+        double x = 0.0;
+#pragma unroll 4
+        for (int w = 0; w < W; ++w) x += ws[6 * k + t][w];
+        v[t] = x;
+      }
+      gamma = v[0];
+      rr = v[2];
+      b = gamma / sc->gam[q ^ 1][k];
+      a = gamma / (v[1] + b * (v[3] + v[4]) + b * b * v[5]);
+    }
+    if (act[k]) {
+      if (!__builtin_isfinite(rr) || !__builtin_isfinite(gamma)) {
+        flag = 2;
+      } else if (rr <= sc->trigger2[k]) {
+        flag = flag > 1 ? flag : 1;
+      } else if (!(a > 0.0) || !__builtin_isfinite(a) || !__builtin_isfinite(b)) {
+        flag = 2;
+      }
+    } else {
+      a = 0.0;
+      b = 0.0;
+    }
+    alpha_d[k] = a;
+    gamma_d[k] = gamma;
+    rr_d[k] = rr;
+    alpha[k] = (XT)a;
+    beta[k] = (XT)b;
+  }
+  if (flag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      for (int k = 0; k < NR; ++k) sc->rr[k] = rr_d[k];
+      sc->done = flag;
+    }
+    return;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) ws_acc[t][wave] = 0.0;
+  }
+  for (; have && slice < A.nslices; slice += wstride) {
+    if (slice != (int64_t)blockIdx.x * W + wave) open_slice_u<VT, XT, CT, L, U>(m, slice, A, h);
+    XT wn[NR];
+    finish_slice_n<VT, XT, CT, L, U, NR>(h, A, sin, alpha, beta, wn);
+    double part[NPT];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) part[t] = 0.0;
+    if ((lane & (L - 1)) == 0 && h.row < m) {
+      const int64_t row = h.row;
+      const CgStateN<XT, NR> t = sin[row];
+      CgStateN<XT, NR> o;
+      o.d = t.d;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        if (act[k]) {
+          const XT pn = t.d * t.r[k] + beta[k] * p[k * m + row];
+          const XT sn = s_next(t.w[k], t.s[k], beta[k]);
+          const XT rn = r_next(t.r[k], sn, alpha[k]);
+          const XT un = t.d * rn;
+          p[k * m + row] = pn;
+          xlo[k * m + row] = xlo[k * m + row] + alpha[k] * pn;
+          o.r[k] = rn;
+          o.w[k] = wn[k];
+          o.s[k] = sn;
+          part[6 * k + 0] += (double)rn * (double)un;
+          part[6 * k + 1] += (double)wn[k] * (double)un;
+          part[6 * k + 2] += (double)rn * (double)rn;
+          part[6 * k + 3] += (double)un * (double)sn;
+          part[6 * k + 4] += (double)pn * (double)wn[k];
+          part[6 * k + 5] += (double)pn * (double)sn;
+        } else {
+          o.r[k] = t.r[k];
+          o.w[k] = t.w[k];
+          o.s[k] = t.s[k];
+        }
+      }
+      sout[row] = o;
+    }
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const double v = wave_sum(part[t]);
+      if (lane == 0) ws_acc[t][wave] += v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 0; t < NPT; ++t) {
+      double v = 0.0;
+      for (int w = 0; w < W; ++w) v += ws_acc[t][w];
+      part_out[(int64_t)blockIdx.x * NPT + t] = v;
+    }
+    if (blockIdx.x == 0) {
+      for (int k = 0; k < NR; ++k) {
+        sc->gam[q][k] = gamma_d[k];
+        sc->rr[k] = rr_d[k];
+      }
+      sc->iter += 1;
+    }
+  }
+  (void)alpha_d;
+}
+
+// x_hi += x_lo and x_lo = 0 for every right-hand side ([nr][m]).
+template <typename XT>
+__global__ void k_cgn_fold(int64_t n, double* __restrict__ xhi, XT* __restrict__ xlo) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  xhi[j] += (double)xlo[j];
+  xlo[j] = (XT)0;
+}
+
+// Float64 residuals r64_k = g_k - (B + lambda I) x_hi,k, and r_k = (XT) r64_k
+// into the records of st.
+template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+__global__ __launch_bounds__(BS) void k_cgn_true_residual(int64_t m, CgMatrix A,
+                                                          const double* __restrict__ xhi,
+                                                          const double* __restrict__ g,
+                                                          double* __restrict__ r64,
+                                                          CgStateN<XT, NR>* __restrict__ st) {
+  constexpr int S = kWave / L;
+  constexpr int W = BS / kWave;
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
+       slice += (int64_t)gridDim.x * W) {
+    const int64_t row = slice * S + lane / L;
+    const int32_t rowc = (int32_t)(row < m ? row : m - 1);
+    const int64_t base = A.sptr[slice] + lane;
+    const int steps = A.slen[slice] / L;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (int s = 0; s < steps; ++s) {
+      const int64_t o = base + (int64_t)s * kWave;
+      const double b = (double)val[o];
+      const int32_t l = rowc + (int32_t)col[o];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] += b * xhi[k * m + l];
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, kWave);
+    }
+    if ((lane & (L - 1)) == 0 && row < m) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const double rv = g[k * m + row] - acc[k];
+        r64[k * m + row] = rv;
+        st[row].r[k] = (XT)rv;
+      }
+    }
+  }
+}
+
+// w_k = B D^-1 r_k from the records of sin, written with the carried s and d
+// to sout; partials of r.u, w.u, r64.r64, p.w, u.s, p.s per right-hand side.
+template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+__global__ __launch_bounds__(BS) void k_cgn_refresh(int64_t m, CgMatrix A,
+                                                    const CgStateN<XT, NR>* __restrict__ sin,
+                                                    CgStateN<XT, NR>* __restrict__ sout,
+                                                    const XT* __restrict__ p,
+                                                    const double* __restrict__ r64,
+                                                    double* __restrict__ part_out) {
+  constexpr int S = kWave / L;
+  constexpr int W = BS / kWave;
+  constexpr int NPT = 6 * NR;
+  __shared__ double ws[NPT][W];
+  const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const VT* __restrict__ val = static_cast<const VT*>(A.val);
+  const int lane = threadIdx.x & (kWave - 1);
+  double part[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) part[t] = 0.0;
+  for (int64_t slice = (int64_t)blockIdx.x * W + threadIdx.x / kWave; slice < A.nslices;
+       slice += (int64_t)gridDim.x * W) {
+    const int64_t row = slice * S + lane / L;
+    const int32_t rowc = (int32_t)(row < m ? row : m - 1);
+    const int64_t base = A.sptr[slice] + lane;
+    const int steps = A.slen[slice] / L;
+    XT acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = (XT)0;
+    for (int s = 0; s < steps; ++s) {
+      const int64_t o = base + (int64_t)s * kWave;
+      const XT b = (XT)val[o];
+      const CgStateN<XT, NR> r = sin[rowc + (int32_t)col[o]];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] += b * (r.d * r.r[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, kWave);
+    }
+    if ((lane & (L - 1)) == 0 && row < m) {
+      const CgStateN<XT, NR> t = sin[row];
+      CgStateN<XT, NR> o = t;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const XT u = t.d * t.r[k];
+        const XT pj = p[k * m + row];
+        o.w[k] = acc[k];
+        const double r64j = r64[k * m + row];
+        part[6 * k + 0] += (double)t.r[k] * (double)u;
+        part[6 * k + 1] += (double)acc[k] * (double)u;
+        part[6 * k + 2] += r64j * r64j;
+        part[6 * k + 3] += (double)pj * (double)acc[k];
+        part[6 * k + 4] += (double)u * (double)t.s[k];
+        part[6 * k + 5] += (double)pj * (double)t.s[k];
+      }
+      sout[row] = o;
+    }
+  }
+  block_sums<NPT, W, false>(part, ws);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) part_out[(int64_t)blockIdx.x * NPT + t] = part[t];
+  }
+}
+
+// After a refresh, per right-hand side: the true residual, convergence
+// (a converged solve is frozen), the next trigger and the scalars of the next
+// iteration (as k_refresh_scalars); done for the batch.
+template <int NR>
+__global__ __launch_bounds__(kCgLargeBlock) void k_cgn_refresh_scalars(
+    CgScalarsN* __restrict__ sc, const double* __restrict__ part, int n, int q_prev,
+    int restart) {
+  constexpr int W = kCgLargeBlock / kWave;
+  constexpr int NPT = 6 * NR;
+  __shared__ double ws[NPT][W];
+  double v[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) v[t] = 0.0;
+  for (int b = threadIdx.x; b < n; b += kCgLargeBlock) {
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) v[t] += part[(int64_t)b * NPT + t];
+  }
+  block_sums<NPT, W, false>(v, ws);
+  if (threadIdx.x != 0) return;
+  int bad = 0, left = 0;
+  for (int k = 0; k < NR; ++k) {
+    if (!sc->active[k]) {
+      sc->fix_gamma[k] = sc->fix_alpha[k] = sc->fix_beta[k] = sc->fix_rr[k] = 0.0;
+      continue;
+    }
+    const double gamma = v[6 * k], delta = v[6 * k + 1], rr = v[6 * k + 2];
+    const double beta = restart ? 0.0 : gamma / sc->gam[q_prev][k];
+    const double ps = delta + beta * (v[6 * k + 3] + v[6 * k + 4]) + beta * beta * v[6 * k + 5];
+    const double alpha = gamma / ps;
+    sc->rr_true[k] = rr;
+    sc->rr[k] = rr;
+    sc->fix_rr[k] = rr;
+    sc->fix_gamma[k] = gamma;
+    sc->fix_beta[k] = beta;
+    sc->fix_alpha[k] = alpha;
+    const double trig = sc->delta2 * rr;
+    sc->trigger2[k] = trig > sc->tol2[k] ? trig : sc->tol2[k];
+    if (!__builtin_isfinite(rr) || !__builtin_isfinite(gamma)) {
+      bad = 1;
+    } else if (rr <= sc->tol2[k]) {
+      sc->active[k] = 0;
+      sc->conv_iter[k] = sc->iter;
+      sc->fix_alpha[k] = sc->fix_beta[k] = 0.0;
+    } else if (!(ps > 0.0) || !__builtin_isfinite(alpha) || !__builtin_isfinite(beta)) {
+      bad = 1;
+    } else {
+      ++left;
+    }
+  }
+  sc->done = bad ? 2 : (left == 0 ? 3 : 0);
+}
+
+template <typename XT, int NR>
+__global__ void k_cgn_clear(int64_t m, const XT* __restrict__ dinv, XT* __restrict__ xlo,
+                            XT* __restrict__ p, CgStateN<XT, NR>* __restrict__ s0,
+                            CgStateN<XT, NR>* __restrict__ s1) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  CgStateN<XT, NR> t;
+  t.d = dinv[j];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    xlo[k * m + j] = (XT)0;
+    p[k * m + j] = (XT)0;
+    t.r[k] = t.w[k] = t.s[k] = (XT)0;
+  }
+  s0[j] = t;
+  s1[j] = t;
+}
+
+// ||g_k||^2 and the initial scalars (single block, fixed order).
+__global__ __launch_bounds__(kCgLargeBlock) void k_cgn_init(int64_t m, int nr,
+                                                           const double* __restrict__ g,
+                                                           CgScalarsN* __restrict__ sc,
+                                                           double rtol, double delta) {
+  constexpr int W = kCgLargeBlock / kWave;
+  __shared__ double ws[1][W];
+  for (int k = 0; k < nr; ++k) {
+    double v[1] = {0.0};
+    for (int64_t j = threadIdx.x; j < m; j += kCgLargeBlock) v[0] += g[k * m + j] * g[k * m + j];
+    block_sums<1, W, true>(v, ws);
+    if (threadIdx.x == 0) {
+      sc->gg[k] = v[0];
+      sc->tol2[k] = rtol * rtol * v[0];
+      sc->trigger2[k] = sc->tol2[k];
+      sc->rr[k] = sc->rr_true[k] = v[0];
+      sc->gam[0][k] = sc->gam[1][k] = 1.0;
+      sc->fix_gamma[k] = sc->fix_alpha[k] = sc->fix_beta[k] = sc->fix_rr[k] = 0.0;
+      sc->active[k] = 1;
+      sc->conv_iter[k] = -1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int k = nr; k < kMaxRhs; ++k) sc->active[k] = 0;
+    sc->delta2 = delta * delta;
+    sc->done = 0;
+    sc->iter = 0;
+  }
+}
+
+template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+void cgn_iter_launch(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                     hipEvent_t e1, hipStream_t s) {
+  using St = CgStateN<XT, NR>;
+  if (e0) {
+    hipExtLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0, s,
+                          e0, e1, 0, a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo,
+                          a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
+  } else {
+    hipLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+                       A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
+  }
+}
+
+template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+void cgn_refresh_launch(const CgArgsN<XT>& a, const CgMatrix& A, const double* g, int q,
+                        hipStream_t s) {
+  using St = CgStateN<XT, NR>;
+  hipLaunchKernelGGL((k_cgn_true_residual<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0,
+                     s, a.m, A, (const double*)a.xhi, g, a.r64, (St*)a.st[q]);
+  hipLaunchKernelGGL((k_cgn_refresh<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0, s, a.m,
+                     A, (const St*)a.st[q], (St*)a.st[q ^ 1], (const XT*)a.p,
+                     (const double*)a.r64, a.part_ref);
+}
+
+// Dispatch over (lanes, block size, right-hand sides); `Op` is one of the two
+// launchers above.
+template <typename VT, typename XT, typename CT, int L, int BS, typename F>
+void cgn_nr(int nr, F&& f) {
+  switch (nr) {
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 3: f(std::integral_constant<int, 3>()); break;
+    default: f(std::integral_constant<int, 4>()); break;
+  }
+}
+
+template <typename XT>
+bool argsn_ok(const CgArgsN<XT>& a, const CgMatrix& A) {
+  return a.blocks >= 1 && a.blocks <= kCgMaxBlocks && A.nslices >= 1 && a.nr >= 2 &&
+         a.nr <= kMaxRhs && (a.threads == kCgSmallBlock || a.threads == kCgLargeBlock) &&
+         (A.lanes == 2 || A.lanes == 4 || A.lanes == 8);
+}
+
+template <typename VT, typename XT, typename CT, int L>
+void cgn_iter_l(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                hipEvent_t e1, hipStream_t s) {
+  auto go = [&](auto nr) {
+    if (a.threads == kCgSmallBlock)
+      cgn_iter_launch<VT, XT, CT, L, kCgSmallBlock, decltype(nr)::value>(a, A, q, fixed, e0, e1,
+                                                                        s);
+    else
+      cgn_iter_launch<VT, XT, CT, L, kCgLargeBlock, decltype(nr)::value>(a, A, q, fixed, e0, e1,
+                                                                        s);
+  };
+  cgn_nr<VT, XT, CT, L, 0>(a.nr, go);
+}
+
+template <typename VT, typename XT, typename CT, int L>
+void cgn_refresh_l(const CgArgsN<XT>& a, const CgMatrix& A, const double* g, int q,
+                   hipStream_t s) {
+  auto go = [&](auto nr) {
+    if (a.threads == kCgSmallBlock)
+      cgn_refresh_launch<VT, XT, CT, L, kCgSmallBlock, decltype(nr)::value>(a, A, g, q, s);
+    else
+      cgn_refresh_launch<VT, XT, CT, L, kCgLargeBlock, decltype(nr)::value>(a, A, g, q, s);
+  };
+  cgn_nr<VT, XT, CT, L, 0>(a.nr, go);
+}
+
+template <typename VT, typename XT, typename CT>
+void cgn_iter_c(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                hipEvent_t e1, hipStream_t s) {
+  switch (A.lanes) {
+    case 2: cgn_iter_l<VT, XT, CT, 2>(a, A, q, fixed, e0, e1, s); break;
+    case 4: cgn_iter_l<VT, XT, CT, 4>(a, A, q, fixed, e0, e1, s); break;
+    default: cgn_iter_l<VT, XT, CT, 8>(a, A, q, fixed, e0, e1, s); break;
+  }
+}
+
+template <typename VT, typename XT, typename CT>
+void cgn_refresh_c(const CgArgsN<XT>& a, const CgMatrix& A, const double* g, int q,
+                   hipStream_t s) {
+  switch (A.lanes) {
+    case 2: cgn_refresh_l<VT, XT, CT, 2>(a, A, g, q, s); break;
+    case 4: cgn_refresh_l<VT, XT, CT, 4>(a, A, g, q, s); break;
+    default: cgn_refresh_l<VT, XT, CT, 8>(a, A, g, q, s); break;
+  }
+}
+
+}  // namespace
+
+template <typename VT, typename XT>
+hipError_t cgn_iterate(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed,
+                       hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+  if (!argsn_ok(a, A) || (q != 0 && q != 1)) return hipErrorInvalidValue;
+  if (A.col16)
+    cgn_iter_c<VT, XT, int16_t>(a, A, q, fixed, e0, e1, s);
+  else
+    cgn_iter_c<VT, XT, int32_t>(a, A, q, fixed, e0, e1, s);
+  return hipGetLastError();
+}
+
+template <typename VT, typename XT>
+hipError_t cgn_refresh(const CgArgsN<XT>& a, const CgMatrix& A, const double* g, int q,
+                       int q_prev, int restart, hipStream_t s) {
+  if (!argsn_ok(a, A) || (q != 0 && q != 1) || (q_prev != 0 && q_prev != 1))
+    return hipErrorInvalidValue;
+  const int bs = 256;
+  const int64_t n = (int64_t)a.nr * a.m;
+  hipLaunchKernelGGL(k_cgn_fold<XT>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, n,
+                     a.xhi, a.xlo);
+  if (A.col16)
+    cgn_refresh_c<VT, XT, int16_t>(a, A, g, q, s);
+  else
+    cgn_refresh_c<VT, XT, int32_t>(a, A, g, q, s);
+  switch (a.nr) {
+    case 2:
+      hipLaunchKernelGGL(k_cgn_refresh_scalars<2>, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                         (const double*)a.part_ref, a.blocks, q_prev, restart);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_cgn_refresh_scalars<3>, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                         (const double*)a.part_ref, a.blocks, q_prev, restart);
+      break;
+    default:
+      hipLaunchKernelGGL(k_cgn_refresh_scalars<4>, dim3(1), dim3(kCgLargeBlock), 0, s, a.sc,
+                         (const double*)a.part_ref, a.blocks, q_prev, restart);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename XT>
+hipError_t cgn_setup(const CgArgsN<XT>& a, const double* g, double rtol, double delta,
+                     hipStream_t s) {
+  if (a.nr < 2 || a.nr > kMaxRhs) return hipErrorInvalidValue;
+  const int bs = 256;
+  const dim3 eg((unsigned)((a.m + bs - 1) / bs));
+  switch (a.nr) {
+    case 2:
+      hipLaunchKernelGGL((k_cgn_clear<XT, 2>), eg, dim3(bs), 0, s, a.m, a.dinv, a.xlo, a.p,
+                         (CgStateN<XT, 2>*)a.st[0], (CgStateN<XT, 2>*)a.st[1]);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_cgn_clear<XT, 3>), eg, dim3(bs), 0, s, a.m, a.dinv, a.xlo, a.p,
+                         (CgStateN<XT, 3>*)a.st[0], (CgStateN<XT, 3>*)a.st[1]);
+      break;
+    default:
+      hipLaunchKernelGGL((k_cgn_clear<XT, 4>), eg, dim3(bs), 0, s, a.m, a.dinv, a.xlo, a.p,
+                         (CgStateN<XT, 4>*)a.st[0], (CgStateN<XT, 4>*)a.st[1]);
+      break;
+  }
+  hipLaunchKernelGGL(k_cgn_init, dim3(1), dim3(kCgLargeBlock), 0, s, a.m, a.nr, g, a.sc, rtol,
+                     delta);
+  return hipGetLastError();
+}
+
+template hipError_t cgn_iterate<double, double>(const CgArgsN<double>&, const CgMatrix&, int, int,
+                                                hipEvent_t, hipEvent_t, hipStream_t);
+template hipError_t cgn_iterate<float, float>(const CgArgsN<float>&, const CgMatrix&, int, int,
+                                              hipEvent_t, hipEvent_t, hipStream_t);
+template hipError_t cgn_refresh<double, double>(const CgArgsN<double>&, const CgMatrix&,
+                                                const double*, int, int, int, hipStream_t);
+template hipError_t cgn_refresh<float, float>(const CgArgsN<float>&, const CgMatrix&,
+                                              const double*, int, int, int, hipStream_t);
+template hipError_t cgn_setup<double>(const CgArgsN<double>&, const double*, double, double,
+                                      hipStream_t);
+template hipError_t cgn_setup<float>(const CgArgsN<float>&, const double*, double, double,
+                                     hipStream_t);
+
 }  // namespace rbf

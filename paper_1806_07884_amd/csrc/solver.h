@@ -150,4 +150,59 @@ template <typename XT>
 hipError_t cg_setup(const CgArgs<XT>& a, const double* g, double rtol, double delta,
                     hipStream_t s);
 
+// ---- several right-hand sides (vector-valued data) ------------------------
+// nr independent CG solves of the same B in one kernel per iteration: the
+// matrix is streamed once for all of them, and the state of a row for all
+// right-hand sides is one record, gathered together.
+constexpr int kMaxRhs = 4;
+
+template <typename XT, int NR>
+struct alignas(16) CgStateN {
+  XT d;
+  XT r[NR], w[NR], s[NR];
+};
+
+// Scalars of a batched solve: as CgScalars, per right-hand side.  A solve
+// whose float64 residual met its tolerance at a refresh is frozen (active 0):
+// its state is carried unchanged.  done: 0 running, 1 some trigger reached
+// (every right-hand side is refreshed), 2 breakdown, 3 all converged.
+struct CgScalarsN {
+  double gam[2][kMaxRhs];
+  double fix_gamma[kMaxRhs], fix_alpha[kMaxRhs], fix_beta[kMaxRhs], fix_rr[kMaxRhs];
+  double rr[kMaxRhs], rr_true[kMaxRhs], gg[kMaxRhs], tol2[kMaxRhs], trigger2[kMaxRhs];
+  double delta2;
+  int64_t iter;
+  int64_t conv_iter[kMaxRhs];  // iterations when the right-hand side converged
+  int32_t active[kMaxRhs];
+  int32_t done;
+  int32_t pad_;
+};
+
+template <typename XT>
+struct CgArgsN {
+  int64_t m;
+  int nr;
+  void* st[2];      // CgStateN<XT, nr> [m], double-buffered
+  XT* p;            // [nr][m]
+  XT* xlo;          // [nr][m]
+  const XT* dinv;   // [m]
+  double* xhi;      // [nr][m]
+  double* r64;      // [nr][m]
+  CgScalarsN* sc;
+  double* part[2];  // [blocks][6 nr] partials of an iteration, by state buffer
+  double* part_ref; // [blocks][6 nr] partials of a refresh
+  int blocks;
+  int threads;
+};
+template <typename VT, typename XT>
+hipError_t cgn_iterate(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed,
+                       hipEvent_t e0, hipEvent_t e1, hipStream_t s);
+// g: [nr][m]
+template <typename VT, typename XT>
+hipError_t cgn_refresh(const CgArgsN<XT>& a, const CgMatrix& A, const double* g, int q,
+                       int q_prev, int restart, hipStream_t s);
+template <typename XT>
+hipError_t cgn_setup(const CgArgsN<XT>& a, const double* g, double rtol, double delta,
+                     hipStream_t s);
+
 }  // namespace rbf
