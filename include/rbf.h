@@ -97,7 +97,13 @@ typedef struct {
                                    (>= 0) */
   int32_t polynomial;           /* 0: none; 1: linear polynomial reproduction
                                    (Section 3): dim + 1 more unknowns k */
+  uint32_t flags;               /* RBF_PLAN_* bits, 0 by default */
 } rbf_plan_desc;
+
+/* rbf_plan_desc.flags: the float64 CG iteration gathers every neighbour from
+ * global memory instead of staging the slices' neighbourhoods in LDS (same
+ * results bit for bit; for comparisons). */
+#define RBF_PLAN_NO_STAGING 1u
 
 typedef struct {
   int32_t dim;
@@ -116,6 +122,9 @@ typedef struct {
   int32_t solver_col_bytes;     /* bytes per stored column index (2 or 4) */
   int32_t solver_lanes;         /* lanes per row of the solver layout */
   int32_t n_poly;               /* dim + 1 with a linear polynomial, else 0 */
+  int32_t solver_staged;        /* most distinct columns one slice stages in LDS
+                                   for the float64 CG iteration (0: not staged;
+                                   built at the plan's first float64 solve) */
 } rbf_plan_stats;
 
 typedef struct {

@@ -22,6 +22,7 @@ RBF_ERR_HIP = -5
 RBF_ERR_OOM = -6
 
 KERNEL = {"cg_iter": 0, "cg_iter_batch": 1, "assemble": 2}
+PLAN_NO_STAGING = 1
 MLP_PARAMS = 5313
 MLP_INPUTS = 16
 MAX_RADII = 8
@@ -36,7 +37,8 @@ class PlanDesc(ctypes.Structure):
                 ("n_centers", ctypes.c_int64), ("points", ctypes.c_void_p),
                 ("centers", ctypes.c_void_p), ("rho", ctypes.c_double),
                 ("rho_per_center", ctypes.c_void_p), ("min_support", ctypes.c_int32),
-                ("lambda_rel", ctypes.c_double), ("polynomial", ctypes.c_int32)]
+                ("lambda_rel", ctypes.c_double), ("polynomial", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -48,7 +50,7 @@ class PlanStats(ctypes.Structure):
                 ("support_max", ctypes.c_int32), ("row_max", ctypes.c_int32),
                 ("cell_size", ctypes.c_double), ("solver_entries", ctypes.c_int64),
                 ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32),
-                ("n_poly", ctypes.c_int32)]
+                ("n_poly", ctypes.c_int32), ("solver_staged", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):

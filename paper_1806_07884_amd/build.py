@@ -21,7 +21,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["sort_scan.hip", "plan_kernels.hip", "assemble_kernels.hip", "cg_kernels.hip",
-           "eval_kernels.hip", "mlp_kernels.hip", "poly_kernels.hip", "api.hip"]
+           "eval_kernels.hip", "mlp_kernels.hip", "poly_kernels.hip", "halo_kernels.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

@@ -120,6 +120,15 @@ struct rbf_plan {
   void* scol = nullptr;
   bool col16 = false;
   int64_t nsell = 0;
+  // neighbourhoods for the LDS-staged iteration (see CgMatrix); hslot null
+  // when the layout does not qualify
+  int16_t* hslot = nullptr;
+  int16_t* hrow = nullptr;
+  int64_t* hptr = nullptr;
+  int32_t* hcount = nullptr;
+  int32_t halo_max = 0;  // most distinct columns of a slice
+  bool staging = true;   // build them (RBF_PLAN_NO_STAGING clears it)
+  bool halo_tried = false;
   // system
   double* hs = nullptr;
   double* g = nullptr;
@@ -260,6 +269,24 @@ struct rbf_plan {
     v.amap = amap;
     return v;
   }
+  // The solver layout with values `val`; staged neighbourhoods when built and
+  // the iterates are float64 (xt_bytes 8).
+  rbf::CgMatrix matrix(const void* val, int xt_bytes) const {
+    rbf::CgMatrix A;
+    A.sptr = sptr;
+    A.slen = slen;
+    A.nslices = nslices;
+    A.col = scol;
+    A.col16 = col16;
+    A.val = val;
+    A.lanes = lanes;
+    const bool staged = hslot && halo_max <= rbf::kHaloCap && xt_bytes == 8;
+    A.hslot = staged ? hslot : nullptr;
+    A.hrow = staged ? hrow : nullptr;
+    A.hptr = staged ? hptr : nullptr;
+    A.hcount = staged ? hcount : nullptr;
+    return A;
+  }
   ~rbf_plan() {
     if (stream) (void)hipStreamSynchronize(stream);
     while (!bufs.empty()) release(bufs.back().p);
@@ -316,6 +343,55 @@ int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, 
   P->release(va);
   P->release(kb);
   P->release(ka);
+  return RBF_OK;
+}
+
+// Neighbourhoods of the solver's slices (see CgMatrix).  A layout with a slice
+// that does not qualify keeps hslot null: the iteration then gathers from
+// global memory.
+int build_halo(rbf_plan* P) {
+  hipStream_t s = P->stream;
+  // once per plan, for grids of one slice per wave
+  if (P->halo_tried || !P->staging || P->ms <= 0) return RBF_OK;
+  P->halo_tried = true;
+  int blocks = 0, threads = 0;
+  rbf::cg_grid(P->nslices, &blocks, &threads);
+  if (threads != rbf::kCgSmallBlock) return RBF_OK;
+  const int64_t ns = P->nslices;
+  const rbf::CgMatrix A = P->matrix(nullptr, 0);
+  int32_t* hc;
+  GET(hc, ns);
+  HIPCHK(rbf::launch_halo_count(A, P->ms, rbf::kHaloCap, hc, s));
+  std::vector<int32_t> cnt(ns);
+  std::vector<int64_t> ptr(ns + 1);
+  HIPCHK(hipMemcpyAsync(cnt.data(), hc, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t total = 0;
+  int32_t mx = 0;
+  for (int64_t k = 0; k < ns; ++k) {
+    if (cnt[k] < 0) {
+      P->release(hc);
+      return RBF_OK;
+    }
+    ptr[k] = total;
+    total += cnt[k];
+    mx = std::max(mx, cnt[k]);
+  }
+  ptr[ns] = total;
+  int64_t* hp;
+  int16_t *hr, *hs;
+  GET(hp, ns + 1);
+  GET(hr, std::max<int64_t>(total, 1));
+  GET(hs, P->nsell + rbf::kSellTail);
+  HIPCHK(hipMemcpyAsync(hp, ptr.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(hs, 0, sizeof(int16_t) * (P->nsell + rbf::kSellTail), s));
+  HIPCHK(rbf::launch_halo_fill(A, P->ms, hc, hp, hr, hs, s));
+  HIPCHK(hipStreamSynchronize(s));  // ptr is read by the copy above
+  P->hcount = hc;
+  P->hptr = hp;
+  P->hrow = hr;
+  P->hslot = hs;
+  P->halo_max = mx;
   return RBF_OK;
 }
 
@@ -624,14 +700,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
            int64_t* iters, int64_t* updates, bool allow_stall_exit) {
   hipStream_t s = P->stream;
   rbf::CgArgs<XT> a = make_args<XT>(P, vec, dinv);
-  rbf::CgMatrix A;
-  A.sptr = P->sptr;
-  A.slen = P->slen;
-  A.nslices = P->nslices;
-  A.col = P->scol;
-  A.col16 = P->col16;
-  A.val = val;
-  A.lanes = P->lanes;
+  const rbf::CgMatrix A = P->matrix(val, (int)sizeof(XT));
   HIPCHK(rbf::cg_setup<XT>(a, P->g_s, o.rtol, o.reliable_delta, s));
   // start: float64 residual of the initial x on state buffer 0, direction reset
   HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g_s, 0, 1, 1, s));
@@ -770,14 +839,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
   a.part_ref = P->bpart_ref;
   rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
-  rbf::CgMatrix A;
-  A.sptr = P->sptr;
-  A.slen = P->slen;
-  A.nslices = P->nslices;
-  A.col = P->scol;
-  A.col16 = P->col16;
-  A.val = val;
-  A.lanes = P->lanes;
+  const rbf::CgMatrix A = P->matrix(val, 0);  // the batched kernels gather from global memory
   HIPCHK(rbf::cgn_setup<XT>(a, P->bg, o.rtol, o.reliable_delta, s));
   // start: float64 residuals of the initial x on state buffer 0
   HIPCHK(rbf::cgn_refresh<VT, XT>(a, A, P->bg, 0, 1, 1, s));
@@ -951,6 +1013,7 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
   if (d->min_support < 1) return fail(RBF_ERR_INVALID, "min_support must be >= 1");
   if (d->polynomial != 0 && d->polynomial != 1)
     return fail(RBF_ERR_INVALID, "polynomial must be 0 (none) or 1 (linear)");
+  if (d->flags & ~RBF_PLAN_NO_STAGING) return fail(RBF_ERR_INVALID, "unknown plan flags");
   if (!(d->lambda_rel >= 0.0 && isfinite(d->lambda_rel)))
     return fail(RBF_ERR_INVALID, "lambda_rel must be finite and >= 0");
   if (allocator && (!allocator->alloc || !allocator->release))
@@ -967,6 +1030,7 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
   P->min_support = d->min_support;
   P->lambda_rel = d->lambda_rel;
   P->npoly = d->polynomial ? d->dim + 1 : 0;
+  P->staging = (d->flags & RBF_PLAN_NO_STAGING) == 0;
   const int rc = build_plan(P, d);
   if (rc != RBF_OK) {
     delete P;
@@ -1016,6 +1080,7 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->solver_col_bytes = P->col16 ? 2 : 4;
   o->solver_lanes = P->lanes;
   o->n_poly = P->npoly;
+  o->solver_staged = P->hslot ? P->halo_max : 0;
   return RBF_OK;
 }
 
@@ -1243,6 +1308,8 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
       // finish in float64 from the current float64 solution
       const int rc2 = ensure_solver(P, false);
       if (rc2) return rc2;
+      const int rch = build_halo(P);
+      if (rch) return rch;
       const int rc3 = assemble_into(P, P->phi, false);
       if (rc3) return rc3;
       const int64_t left = o.max_iter - iters;
@@ -1256,6 +1323,8 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
       }
     }
   } else {
+    rc = build_halo(P);
+    if (rc) return rc;
     rc = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters, &updates, false);
   }
   if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;

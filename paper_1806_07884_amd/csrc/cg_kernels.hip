@@ -145,69 +145,75 @@ __device__ __forceinline__ XT slice_sum(int64_t m, int64_t slice, const CgMatrix
 // Float64 records are twice as wide, so their batches are half as long.
 template <typename XT>
 constexpr int kBatch = sizeof(XT) == 4 ? 8 : 4;
+// Batches of the staged path (longer ones measured no faster: their
+// registers cost occupancy).
+template <typename XT, bool HALO>
+constexpr int kBatchH = kBatch<XT>;
 
 // One batch of a slice: the gathered column index and value of each of its
 // steps (index = the row itself and value 0 past the slice's end).
-template <typename XT>
+template <typename XT, int U = kBatch<XT>>
 struct Batch {
-  int32_t l[kBatch<XT>];
-  XT v[kBatch<XT>];
+  int32_t l[U];
+  XT v[U];
 };
 
-template <typename VT, typename XT, typename CT>
+// HALO: the entries' LDS slots (hslot) instead of their column deltas.
+template <typename VT, typename XT, typename CT, bool HALO = false>
 __device__ __forceinline__ void load_batch(const CgMatrix& A, int64_t base, int32_t rowc, int st,
-                                           int steps, Batch<XT>& b) {
+                                           int steps, Batch<XT, kBatchH<XT, HALO>>& b) {
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const int16_t* __restrict__ slot = A.hslot;
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
   // Loads are unconditional: past the slice's end they read the next slice or
   // the zeroed tail of the arrays (kSellTail), and the select drops them.
 #pragma unroll
-  for (int t = 0; t < kBatch<XT>; ++t) {
+  for (int t = 0; t < kBatchH<XT, HALO>; ++t) {
     const int64_t o = base + (int64_t)(st + t) * kWave;
-    const int32_t c = (int32_t)col[o];
+    const int32_t c = HALO ? (int32_t)slot[o] : (int32_t)col[o];
     const XT v = (XT)val[o];
     const bool in = st + t < steps;
-    b.l[t] = rowc + (in ? c : 0);
+    b.l[t] = HALO ? (in ? c : 0) : rowc + (in ? c : 0);
     b.v[t] = in ? v : (XT)0;
   }
 }
 
 // One slice of a wave: its geometry and its first batch, loaded before the
 // kernel's reduction so that their latency overlaps it.
-template <typename XT>
+template <typename XT, bool HALO = false>
 struct SliceHead {
   int64_t row, base;
   int32_t rowc;
   int steps;
-  Batch<XT> b;
+  Batch<XT, kBatchH<XT, HALO>> b;
 };
 
-template <typename VT, typename XT, typename CT, int L>
+template <typename VT, typename XT, typename CT, int L, bool HALO = false>
 __device__ __forceinline__ void open_slice(int64_t m, int64_t slice, const CgMatrix& A,
-                                           SliceHead<XT>& h) {
+                                           SliceHead<XT, HALO>& h) {
   constexpr int S = kWave / L;
   const int lane = threadIdx.x & (kWave - 1);
   h.row = slice * S + lane / L;
   h.rowc = (int32_t)(h.row < m ? h.row : m - 1);
   h.base = A.sptr[slice] + lane;
   h.steps = A.slen[slice] / L;
-  load_batch<VT, XT, CT>(A, h.base, h.rowc, 0, h.steps, h.b);
+  load_batch<VT, XT, CT, HALO>(A, h.base, h.rowc, 0, h.steps, h.b);
 }
 
 // Row sum of an opened slice, complete in the lane with (lane % L) == 0:
 // software-pipelined, the next batch's indices and values load while the
 // current batch is gathered.
-template <typename VT, typename XT, typename CT, int L, typename F>
-__device__ __forceinline__ XT finish_slice(const SliceHead<XT>& h, const CgMatrix& A, F f) {
-  constexpr int U = kBatch<XT>;
+template <typename VT, typename XT, typename CT, int L, bool HALO = false, typename F>
+__device__ __forceinline__ XT finish_slice(const SliceHead<XT, HALO>& h, const CgMatrix& A, F f) {
+  constexpr int U = kBatchH<XT, HALO>;
   XT acc[U];
 #pragma unroll
   for (int t = 0; t < U; ++t) acc[t] = (XT)0;
-  Batch<XT> cur = h.b;
+  Batch<XT, U> cur = h.b;
   for (int st = U;; st += U) {
     const bool more = st < h.steps;
-    Batch<XT> nxt;
-    if (more) load_batch<VT, XT, CT>(A, h.base, h.rowc, st, h.steps, nxt);
+    Batch<XT, U> nxt;
+    if (more) load_batch<VT, XT, CT, HALO>(A, h.base, h.rowc, st, h.steps, nxt);
 #pragma unroll
     for (int t = 0; t < U; ++t) acc[t] += cur.v[t] * f(cur.l[t]);
     if (!more) break;
@@ -289,7 +295,9 @@ __device__ __forceinline__ void poly_store(const PolySys& S, int np, const doubl
 // kernels' (n_in): it streams no slice and writes no partials, but forms the
 // polynomial unknowns' next state from the same scalars as every other block,
 // so that the others keep only a few of its values in registers.
-template <typename VT, typename XT, typename CT, int L, int BS, bool POLY>
+// HALO: every slice's neighbourhood is staged in LDS (one u per distinct
+// column, computed once) and the entries gather from there (see CgMatrix).
+template <typename VT, typename XT, typename CT, int L, int BS, bool POLY, bool HALO = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1))) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
     XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc,
@@ -303,6 +311,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   // the polynomial rows' partials Q^T u, per wave (added slice by slice, so
   // that they hold no registers across the streamed loop)
   __shared__ double ws_poly[POLY ? kMaxPoly : 1][POLY ? W : 1];
+  __shared__ XT us[HALO ? W : 1][HALO ? kHaloCap : 1];
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -313,16 +322,34 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   // Loads that do not depend on this iteration's scalars go out first: the
   // first slice's geometry and first batch, the row's own state, the
   // previous kernel's partials and the scalars.
-  SliceHead<XT> h;
+  SliceHead<XT, HALO> h;
   CgState<XT> own;
   XT p_old = (XT)0, x_old = (XT)0;
   const bool have = !poly_block && slice < A.nslices;
   if (have) {
-    open_slice<VT, XT, CT, L>(m, slice, A, h);
+    open_slice<VT, XT, CT, L, HALO>(m, slice, A, h);
     if ((lane & (L - 1)) == 0 && h.row < m) {
       own = sin[h.row];
       p_old = p[h.row];
       x_old = xlo[h.row];
+    }
+  }
+  // the first slice's neighbourhood records (they do not depend on this
+  // iteration's scalars): the first rounds go out before the reduction
+  constexpr int kStagePre = HALO ? (sizeof(XT) == 4 ? 8 : 4) : 1;
+  CgState<XT> srec[kStagePre];
+  int st_n = 0;
+  int64_t st_off = 0, st_first = 0;
+  if constexpr (HALO) {
+    if (have) {
+      st_n = A.hcount[slice];
+      st_off = A.hptr[slice];
+      st_first = slice * (kWave / L);
+#pragma unroll
+      for (int r = 0; r < kStagePre; ++r) {
+        const int i = lane + kWave * r;
+        if (i < st_n) srec[r] = sin[st_first + A.hrow[st_off + i]];
+      }
     }
   }
   double red[NP];
@@ -447,9 +474,32 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
       return;
     }
   }
-  auto u_next = [&](int32_t l) -> XT {
-    const CgState<XT> t = sin[l];
+  auto u_rec = [&](const CgState<XT>& t) -> XT {
     return t.d * r_next(t.r, s_next(t.w, t.s, beta), alpha);
+  };
+  auto u_next = [&](int32_t l) -> XT {
+    if constexpr (HALO) return us[wave][l];
+    else return u_rec(sin[l]);
+  };
+  // the slice's neighbourhood: u of each distinct column, once (the first
+  // slice's first rounds from the records loaded before the barrier)
+  auto stage = [&](int64_t sl) {
+    if constexpr (HALO) {
+      const int n = A.hcount[sl];
+      const int64_t off = A.hptr[sl], first = sl * (kWave / L);
+      wave_sync();
+      int i0 = lane;
+      if (sl == (int64_t)blockIdx.x * W + wave) {
+#pragma unroll
+        for (int r = 0; r < kStagePre; ++r) {
+          const int i = lane + kWave * r;
+          if (i < n) us[wave][i] = u_rec(srec[r]);
+        }
+        i0 = lane + kWave * kStagePre;
+      }
+      for (int i = i0; i < n; i += kWave) us[wave][i] = u_rec(sin[first + A.hrow[off + i]]);
+      wave_sync();
+    }
   };
   double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if constexpr (POLY) {
@@ -504,14 +554,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   if (have) {
 #pragma unroll
     for (int k = 0; k < kMaxPoly; ++k) qtu[k] = 0.0;
-    const XT wn = finish_slice<VT, XT, CT, L>(h, A, u_next);
+    stage(slice);
+    const XT wn = finish_slice<VT, XT, CT, L, HALO>(h, A, u_next);
     if ((lane & (L - 1)) == 0 && h.row < m) own_row(h.row, wn, own, p_old, x_old);
     poly_slice_sums();
     for (slice += wstride; slice < A.nslices; slice += wstride) {
-      open_slice<VT, XT, CT, L>(m, slice, A, h);
+      open_slice<VT, XT, CT, L, HALO>(m, slice, A, h);
 #pragma unroll
       for (int k = 0; k < kMaxPoly; ++k) qtu[k] = 0.0;
-      const XT wn2 = finish_slice<VT, XT, CT, L>(h, A, u_next);
+      stage(slice);
+      const XT wn2 = finish_slice<VT, XT, CT, L, HALO>(h, A, u_next);
       if ((lane & (L - 1)) == 0 && h.row < m)
         own_row(h.row, wn2, sin[h.row], p[h.row], xlo[h.row]);
       poly_slice_sums();
@@ -907,9 +959,39 @@ void launch_refresh_l(const CgArgs<XT>& a, const CgMatrix& A, const double* g, i
     launch_refresh_b<VT, XT, CT, L, kCgLargeBlock>(a, A, g, q, s);
 }
 
+template <typename VT, typename XT, int L>
+void launch_iter_halo(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                      hipEvent_t e1, hipStream_t s) {
+  constexpr int BS = kCgSmallBlock;
+  if (e0) {
+    hipExtLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks),
+                          dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q],
+                          a.st[q ^ 1], a.p, a.xlo, a.sc, (const double*)a.part[q ^ 1], a.part[q],
+                          a.blocks, q, fixed, 0, (const XT*)nullptr, (const PolySys*)nullptr,
+                          (const PolyState*)nullptr, (PolyState*)nullptr);
+  } else {
+    hipLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks), dim3(BS),
+                       0, s, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed, 0,
+                       (const XT*)nullptr, (const PolySys*)nullptr, (const PolyState*)nullptr,
+                       (PolyState*)nullptr);
+  }
+}
+
 template <typename VT, typename XT, typename CT>
 void iter_dispatch(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
                    hipEvent_t e1, hipStream_t s) {
+  // staged neighbourhoods: float64 single solve without the polynomial
+  // block, one slice per wave
+  if constexpr (sizeof(XT) == 8) {
+    if (A.hslot && a.np == 0 && a.threads == kCgSmallBlock) {
+      switch (A.lanes) {
+        case 2: launch_iter_halo<VT, XT, 2>(a, A, q, fixed, e0, e1, s); return;
+        case 4: launch_iter_halo<VT, XT, 4>(a, A, q, fixed, e0, e1, s); return;
+        default: launch_iter_halo<VT, XT, 8>(a, A, q, fixed, e0, e1, s); return;
+      }
+    }
+  }
   switch (A.lanes) {
     case 2: launch_iter_l<VT, XT, CT, 2>(a, A, q, fixed, e0, e1, s); break;
     case 4: launch_iter_l<VT, XT, CT, 4>(a, A, q, fixed, e0, e1, s); break;

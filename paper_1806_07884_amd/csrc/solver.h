@@ -118,7 +118,25 @@ struct CgMatrix {
   bool col16;
   const void* val;  // VT
   int lanes;        // L: lanes per row (2, 4 or 8)
+  // Neighbourhoods for the LDS-staged iteration (null when not built): per
+  // slice the sorted distinct columns its entries reference (hrow: offsets
+  // from the slice's first row, at hptr[s]; hcount[s] of them), and per
+  // stored entry the rank of its column among them (hslot).
+  const int16_t* hslot;
+  const int16_t* hrow;
+  const int64_t* hptr;
+  const int32_t* hcount;
 };
+// Column range (bits of a wave's bitmap) a slice may span to be staged, and
+// the most distinct columns one wave stages (its LDS holds one float64 u per
+// column).  Staging serves the float64 iteration only: with float32 records
+// the global gathers measured as fast.
+constexpr int kHaloSpan = 16384;
+constexpr int kHaloCap = 1024;
+hipError_t launch_halo_count(const CgMatrix& A, int64_t ms, int cap, int32_t* hcount,
+                             hipStream_t s);
+hipError_t launch_halo_fill(const CgMatrix& A, int64_t ms, const int32_t* hcount,
+                            const int64_t* hptr, int16_t* hrow, int16_t* hslot, hipStream_t s);
 
 __host__ __device__ inline int64_t sell_pos(const int64_t* sptr, int lanes, int64_t j, int64_t k) {
   const int64_t rows = 64 / lanes;

@@ -321,3 +321,23 @@ def test_invalid_inputs_raise(rbf):
     plan = rbf.rbf_fit_plan(dev(np.random.rand(2, 10)), ctr, rho=0.2)
     with pytest.raises(RbfError, match="assemble"):
         rbf.rbf_solve(plan)
+
+
+@pytest.mark.parametrize("name,scale", [("terrain2d", 1 / 64), ("franke2d", 1.0), ("terrain2d", 1 / 4)])
+def test_staged_iteration_is_bit_identical(rbf, name, scale):
+    # the float64 CG iteration staging each slice's neighbourhood in LDS
+    # computes the same numbers as the one gathering from global memory
+    p = sd.make_problem(name, scale=scale)
+    lam = 1e-4 if name == "terrain2d" else 0.0
+    res = {}
+    for staging in (True, False):
+        plan = rbf.rbf_fit_plan(dev(p.points), dev(p.centers), rho=p.rho, lambda_rel=lam,
+                                staging=staging)
+        rbf.rbf_assemble(plan, p.phi, "fp64", dev(p.values))
+        c, info = rbf.rbf_solve(plan, rtol=1e-10)
+        staged = rbf.rbf_plan_info(plan)["solver_staged"]
+        say(name, scale, "staging", staging, "staged columns per slice <=", staged)
+        assert (staged > 0) == staging
+        res[staging] = (c.cpu().numpy().tobytes(), info["iterations"])
+        plan.close()
+    assert res[True] == res[False]
