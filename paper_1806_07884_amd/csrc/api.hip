@@ -270,8 +270,9 @@ struct rbf_plan {
     return v;
   }
   // The solver layout with values `val`; staged neighbourhoods when built and
-  // the iterates are float64 (xt_bytes 8).
-  rbf::CgMatrix matrix(const void* val, int xt_bytes) const {
+  // the iterates are float64 (xt_bytes 8), or for a batched iteration of nr
+  // right-hand sides when every slice fits its LDS.
+  rbf::CgMatrix matrix(const void* val, int xt_bytes, int nr = 1) const {
     rbf::CgMatrix A;
     A.sptr = sptr;
     A.slen = slen;
@@ -280,7 +281,9 @@ struct rbf_plan {
     A.col16 = col16;
     A.val = val;
     A.lanes = lanes;
-    const bool staged = hslot && halo_max <= rbf::kHaloCap && xt_bytes == 8;
+    const bool staged =
+        hslot && ((nr == 1 && xt_bytes == 8 && halo_max <= rbf::kHaloCap) ||
+                  (nr > 1 && halo_max <= rbf::halo_cap_n(nr, xt_bytes)));
     A.hslot = staged ? hslot : nullptr;
     A.hrow = staged ? hrow : nullptr;
     A.hptr = staged ? hptr : nullptr;
@@ -839,7 +842,9 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
   a.part_ref = P->bpart_ref;
   rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
-  const rbf::CgMatrix A = P->matrix(val, 0);  // the batched kernels gather from global memory
+  const int rch = build_halo(P);
+  if (rch) return rch;
+  const rbf::CgMatrix A = P->matrix(val, (int)sizeof(XT), nr);
   HIPCHK(rbf::cgn_setup<XT>(a, P->bg, o.rtol, o.reliable_delta, s));
   // start: float64 residuals of the initial x on state buffer 0
   HIPCHK(rbf::cgn_refresh<VT, XT>(a, A, P->bg, 0, 1, 1, s));

@@ -1121,24 +1121,25 @@ struct SliceHeadU {
   XT v[U];
 };
 
-template <typename VT, typename XT, typename CT, int U>
+template <typename VT, typename XT, typename CT, int U, bool HALO = false>
 __device__ __forceinline__ void load_batch_u(const CgMatrix& A, int64_t base, int32_t rowc, int st,
                                              int steps, int32_t* l, XT* v) {
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
+  const int16_t* __restrict__ slot = A.hslot;
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
   // unconditional loads (at most 7 steps past a slice, inside the zeroed tail)
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const int64_t o = base + (int64_t)(st + t) * kWave;
-    const int32_t c = (int32_t)col[o];
+    const int32_t c = HALO ? (int32_t)slot[o] : (int32_t)col[o];
     const XT x = (XT)val[o];
     const bool in = st + t < steps;
-    l[t] = rowc + (in ? c : 0);
+    l[t] = HALO ? (in ? c : 0) : rowc + (in ? c : 0);
     v[t] = in ? x : (XT)0;
   }
 }
 
-template <typename VT, typename XT, typename CT, int L, int U>
+template <typename VT, typename XT, typename CT, int L, int U, bool HALO = false>
 __device__ __forceinline__ void open_slice_u(int64_t m, int64_t slice, const CgMatrix& A,
                                              SliceHeadU<XT, U>& h) {
   constexpr int S = kWave / L;
@@ -1147,15 +1148,17 @@ __device__ __forceinline__ void open_slice_u(int64_t m, int64_t slice, const CgM
   h.rowc = (int32_t)(h.row < m ? h.row : m - 1);
   h.base = A.sptr[slice] + lane;
   h.steps = A.slen[slice] / L;
-  load_batch_u<VT, XT, CT, U>(A, h.base, h.rowc, 0, h.steps, h.l, h.v);
+  load_batch_u<VT, XT, CT, U, HALO>(A, h.base, h.rowc, 0, h.steps, h.l, h.v);
 }
 
 // Row sums of an opened slice for every right-hand side: wn[k] =
 // sum_e b_e u_k(col_e), complete in the lane with (lane % L) == 0.
-template <typename VT, typename XT, typename CT, int L, int U, int NR>
+// HALO: us[k][slot] holds u_k of the slice's staged columns.
+template <typename VT, typename XT, typename CT, int L, int U, int NR, bool HALO = false>
 __device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const CgMatrix& A,
                                                const CgStateN<XT, NR>* __restrict__ sin,
-                                               const XT* alpha, const XT* beta, XT* wn) {
+                                               const XT* alpha, const XT* beta, XT* wn,
+                                               const XT (*us)[kHaloCapN<XT, NR>] = nullptr) {
   XT acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = (XT)0;
@@ -1168,13 +1171,18 @@ __device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const
   }
   for (int st = U;; st += U) {
     const bool more = st < h.steps;
-    if (more) load_batch_u<VT, XT, CT, U>(A, h.base, h.rowc, st, h.steps, nl, nv);
+    if (more) load_batch_u<VT, XT, CT, U, HALO>(A, h.base, h.rowc, st, h.steps, nl, nv);
 #pragma unroll
     for (int t = 0; t < U; ++t) {
-      const CgStateN<XT, NR> r = sin[cl[t]];
+      if constexpr (HALO) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k)
-        acc[k] += cv[t] * (r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k]));
+        for (int k = 0; k < NR; ++k) acc[k] += cv[t] * us[k][cl[t]];
+      } else {
+        const CgStateN<XT, NR> r = sin[cl[t]];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          acc[k] += cv[t] * (r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k]));
+      }
     }
     if (!more) break;
 #pragma unroll
@@ -1192,7 +1200,7 @@ __device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const
   }
 }
 
-template <typename VT, typename XT, typename CT, int L, int BS, int NR>
+template <typename VT, typename XT, typename CT, int L, int BS, int NR, bool HALO = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_cgn_iter(
     int64_t m, CgMatrix A, const CgStateN<XT, NR>* __restrict__ sin,
     CgStateN<XT, NR>* __restrict__ sout, XT* __restrict__ p, XT* __restrict__ xlo,
@@ -1205,6 +1213,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // this iteration's partials, per wave (added slice by slice, so that they
   // hold no registers across the streamed loop)
   __shared__ double ws_acc[NPT][W];
+  __shared__ XT us[HALO ? W : 1][HALO ? NR : 1][HALO ? kHaloCapN<XT, NR> : 1];
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -1212,7 +1221,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   int64_t slice = (int64_t)blockIdx.x * W + wave;
   SliceHeadU<XT, U> h;
   const bool have = slice < A.nslices;
-  if (have) open_slice_u<VT, XT, CT, L, U>(m, slice, A, h);
+  if (have) open_slice_u<VT, XT, CT, L, U, HALO>(m, slice, A, h);
   // the previous kernel's partials, one right-hand side at a time
   if (!fixed) {
 #pragma unroll
@@ -1288,9 +1297,25 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int t = 0; t < NPT; ++t) ws_acc[t][wave] = 0.0;
   }
   for (; have && slice < A.nslices; slice += wstride) {
-    if (slice != (int64_t)blockIdx.x * W + wave) open_slice_u<VT, XT, CT, L, U>(m, slice, A, h);
+    if (slice != (int64_t)blockIdx.x * W + wave)
+      open_slice_u<VT, XT, CT, L, U, HALO>(m, slice, A, h);
     XT wn[NR];
-    finish_slice_n<VT, XT, CT, L, U, NR>(h, A, sin, alpha, beta, wn);
+    if constexpr (HALO) {
+      // u of every right-hand side, once per distinct column of the slice
+      const int n = A.hcount[slice];
+      const int64_t off = A.hptr[slice], first = slice * (kWave / L);
+      wave_sync();
+      for (int i = lane; i < n; i += kWave) {
+        const CgStateN<XT, NR> r = sin[first + A.hrow[off + i]];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          us[wave][k][i] = r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k]);
+      }
+      wave_sync();
+      finish_slice_n<VT, XT, CT, L, U, NR, true>(h, A, sin, alpha, beta, wn, us[wave]);
+    } else {
+      finish_slice_n<VT, XT, CT, L, U, NR>(h, A, sin, alpha, beta, wn);
+    }
     double part[NPT];
 #pragma unroll
     for (int t = 0; t < NPT; ++t) part[t] = 0.0;
@@ -1569,19 +1594,32 @@ __global__ __launch_bounds__(kCgLargeBlock) void k_cgn_init(int64_t m, int nr,
   }
 }
 
+template <typename VT, typename XT, typename CT, int L, int BS, int NR, bool HALO>
+void cgn_iter_launch_h(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
+                       hipEvent_t e1, hipStream_t s) {
+  using St = CgStateN<XT, NR>;
+  if (e0) {
+    hipExtLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0,
+                          s, e0, e1, 0, a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo,
+                          a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
+  } else {
+    hipLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0, s,
+                       a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
+  }
+}
+
+// Staged neighbourhoods when the layout carries them (one slice per wave).
 template <typename VT, typename XT, typename CT, int L, int BS, int NR>
 void cgn_iter_launch(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed, hipEvent_t e0,
                      hipEvent_t e1, hipStream_t s) {
-  using St = CgStateN<XT, NR>;
-  if (e0) {
-    hipExtLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0, s,
-                          e0, e1, 0, a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo,
-                          a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
-  } else {
-    hipLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR>), dim3(a.blocks), dim3(BS), 0, s, a.m,
-                       A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc,
-                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, q, fixed);
+  if constexpr (BS == kCgSmallBlock) {
+    if (A.hslot) {
+      cgn_iter_launch_h<VT, XT, CT, L, BS, NR, true>(a, A, q, fixed, e0, e1, s);
+      return;
+    }
   }
+  cgn_iter_launch_h<VT, XT, CT, L, BS, NR, false>(a, A, q, fixed, e0, e1, s);
 }
 
 template <typename VT, typename XT, typename CT, int L, int BS, int NR>

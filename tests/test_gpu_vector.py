@@ -192,3 +192,26 @@ def test_batch_warm_start_and_errors(rbf):
     rbf.rbf_assemble(zplan, "w31", "fp64", dev(far[0]))
     Z, zi = rbf.rbf_solve_batch(zplan, dev(np.stack([far[0], far[1]])))
     assert torch.count_nonzero(Z).item() == 0 and zi[0]["status"] == 0
+
+
+@pytest.mark.parametrize("prec,nr", [("fp32", 2), ("fp32", 4), ("fp64", 2)])
+def test_batch_staged_is_bit_identical(rbf, prec, nr):
+    # the batched iteration staging the slices' neighbourhoods in LDS computes
+    # the same numbers as the one gathering every record from global memory
+    prob = sd.make_problem("terrain2d", scale=1 / 64)
+    rng = np.random.default_rng(2)
+    H = np.stack([prob.values] + [sd.terrain_values(sd.terrain_modes(rng, 64, 2), prob.points)
+                                  for _ in range(nr - 1)])
+    out = {}
+    for staging in (True, False):
+        plan = rbf.rbf_fit_plan(dev(prob.points), dev(prob.centers), rho=prob.rho,
+                                lambda_rel=1e-4, staging=staging)
+        rbf.rbf_assemble(plan, prob.phi, prec, dev(H[0]))
+        C, infos = rbf.rbf_solve_batch(plan, dev(H), rtol=1e-10)
+        staged = rbf.rbf_plan_info(plan)["solver_staged"]
+        say("batch", prec, nr, "staging", staging, "staged", staged,
+            [i["iterations"] for i in infos])
+        assert (staged > 0) == staging
+        out[staging] = (C.cpu().numpy().tobytes(), [i["iterations"] for i in infos])
+        plan.close()
+    assert out[True] == out[False]
