@@ -1153,12 +1153,17 @@ __device__ __forceinline__ void open_slice_u(int64_t m, int64_t slice, const CgM
 
 // Row sums of an opened slice for every right-hand side: wn[k] =
 // sum_e b_e u_k(col_e), complete in the lane with (lane % L) == 0.
-// HALO: us[k][slot] holds u_k of the slice's staged columns.
+// HALO: us[slot] holds u of every right-hand side for the slice's staged
+// columns (interleaved, padded to kRhsPad).
+template <typename XT, int NR>
+struct alignas(kRhsPad<NR> * sizeof(XT)) URec {
+  XT u[kRhsPad<NR>];
+};
 template <typename VT, typename XT, typename CT, int L, int U, int NR, bool HALO = false>
 __device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const CgMatrix& A,
                                                const CgStateN<XT, NR>* __restrict__ sin,
                                                const XT* alpha, const XT* beta, XT* wn,
-                                               const XT (*us)[kHaloCapN<XT, NR>] = nullptr) {
+                                               const URec<XT, NR>* us = nullptr) {
   XT acc[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = (XT)0;
@@ -1175,8 +1180,9 @@ __device__ __forceinline__ void finish_slice_n(const SliceHeadU<XT, U>& h, const
 #pragma unroll
     for (int t = 0; t < U; ++t) {
       if constexpr (HALO) {
+        const URec<XT, NR> r = us[cl[t]];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] += cv[t] * us[k][cl[t]];
+        for (int k = 0; k < NR; ++k) acc[k] += cv[t] * r.u[k];
       } else {
         const CgStateN<XT, NR> r = sin[cl[t]];
 #pragma unroll
@@ -1213,7 +1219,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // this iteration's partials, per wave (added slice by slice, so that they
   // hold no registers across the streamed loop)
   __shared__ double ws_acc[NPT][W];
-  __shared__ XT us[HALO ? W : 1][HALO ? NR : 1][HALO ? kHaloCapN<XT, NR> : 1];
+  __shared__ URec<XT, NR> us[HALO ? W : 1][HALO ? kHaloCapN<XT, NR> : 1];
   __shared__ int s_flag;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -1307,9 +1313,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
       wave_sync();
       for (int i = lane; i < n; i += kWave) {
         const CgStateN<XT, NR> r = sin[first + A.hrow[off + i]];
+        URec<XT, NR> o;
 #pragma unroll
-        for (int k = 0; k < NR; ++k)
-          us[wave][k][i] = r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k]);
+        for (int k = 0; k < kRhsPad<NR>; ++k)
+          o.u[k] = k < NR ? r.d * r_next(r.r[k], s_next(r.w[k], r.s[k], beta[k]), alpha[k])
+                          : (XT)0;
+        us[wave][i] = o;
       }
       wave_sync();
       finish_slice_n<VT, XT, CT, L, U, NR, true>(h, A, sin, alpha, beta, wn, us[wave]);

@@ -135,9 +135,13 @@ constexpr int kHaloSpan = 16384;
 constexpr int kHaloCap = 1024;
 // ... and for the batched iteration, which stages one u per right-hand side
 // in 8 KB of LDS per wave.
+// The u values of a column are interleaved (NR rounded up to a power of two),
+// so one LDS load serves every right-hand side.
+template <int NR>
+constexpr int kRhsPad = NR == 3 ? 4 : NR;
 template <typename XT, int NR>
-constexpr int kHaloCapN = 8192 / (NR * (int)sizeof(XT));
-inline int halo_cap_n(int nr, int xt_bytes) { return 8192 / (nr * xt_bytes); }
+constexpr int kHaloCapN = 8192 / (kRhsPad<NR> * (int)sizeof(XT));
+inline int halo_cap_n(int nr, int xt_bytes) { return 8192 / ((nr == 3 ? 4 : nr) * xt_bytes); }
 hipError_t launch_halo_count(const CgMatrix& A, int64_t ms, int cap, int32_t* hcount,
                              hipStream_t s);
 hipError_t launch_halo_fill(const CgMatrix& A, int64_t ms, const int32_t* hcount,
