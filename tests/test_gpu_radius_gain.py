@@ -6,7 +6,7 @@ plus noise, 10 % held out), 64 x 64 reference points, 4 x 4 blocks of
 16 x 16 centres, the 8 sweep radii covering 10..113 centres.  Labels come from
 the sweeps (held-out RMSE per block; blocks with fewer than 5 held-out
 queries carry no label); the network is trained on 18 sets with the
-project's kernels and judged on the other 6.
+project's kernels and evaluated on the other 6.
 
 For every test set the learned per-block radii are fitted once (CG work W_L
 = stored entries x iterations, held-out RMSE r_L).  The fixed-radius

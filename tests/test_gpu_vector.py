@@ -215,3 +215,22 @@ def test_batch_staged_is_bit_identical(rbf, prec, nr):
         out[staging] = (C.cpu().numpy().tobytes(), [i["iterations"] for i in infos])
         plan.close()
     assert out[True] == out[False]
+
+
+def test_batch_3d(rbf):
+    prob = sd.make_problem("field3d", scale=1 / 512)
+    p, ctr, rho = prob.points, prob.centers, prob.rho
+    H = [prob.values, np.sin(3 * p[0]) * np.cos(2 * p[2]) + p[1]]
+    plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho, lambda_rel=1e-5)
+    rbf.rbf_assemble(plan, prob.phi, "fp64", dev(H[0]))
+    C, infos = rbf.rbf_solve_batch(plan, dev(np.stack(H)), rtol=1e-12, max_iter=50000)
+    say("batched 3D", rbf.rbf_plan_info(plan)["solver_staged"], [i["iterations"] for i in infos])
+    C = C.cpu().numpy()
+    for k, h in enumerate(H):
+        assert infos[k]["status"] == 0
+        ne = orc.normal_equations(p, h, ctr, rho, prob.phi, lambda_rel=1e-5)
+        c_ref = orc.solve(ne)
+        fit = np.linalg.norm(ne.A @ (C[k] - c_ref)) / np.linalg.norm(ne.A @ c_ref)
+        say(k, "fit", fit)
+        assert fit <= 1e-8
+    plan.close()
