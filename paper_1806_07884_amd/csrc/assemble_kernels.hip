@@ -20,9 +20,12 @@
 // points are sorted by sub-cell within a hash cell); a group's bounding ball
 // selects the columns whose support can reach it; those columns are handed
 // to the lanes, and each lane runs through the group's points for its column,
-// accumulating into the wave's LDS accumulator of that column.  Groups a
-// column cannot reach contribute no term, so the sums are the same as when
-// every lane visits every point.
+// accumulating into the wave's LDS accumulator of that column.  When few
+// columns reach a group, two or four lanes share a column, each summing a
+// contiguous part of the group's points, and the parts are added to the
+// column's sum in order: every sum has a fixed order, so the result is
+// deterministic (its rounding differs from the ungrouped path's order by the
+// summation bound).
 //
 // FP64 variant: float64 phi and float64 accumulation.
 // FP32 variant: squared distance and support test in float64 (the pattern is
@@ -231,21 +234,65 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
           nn += __popcll(msk);
         }
         wave_sync();
-        for (int k0 = 0; k0 < nn; k0 += kWave) {
-          const int k = k0 + lane;
-          if (k < nn) {
-            const int t = nlist[w][k];
+        // lanes per column: when few columns reach the group, P lanes share
+        // one, each summing a contiguous part of the group's points; the
+        // parts are added to the column's sum in order
+        const int P = nn <= 16 ? 4 : (nn <= 32 ? 2 : 1);
+        if (P == 1) {
+          for (int k0 = 0; k0 < nn; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < nn) {
+              const int t = nlist[w][k];
+              double xt[DIM];
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) xt[d] = cxs[d][t];
+              const double r2t = cr2s[t], irt = cirs[t];
+              Acc<T> a = from_pod(cacc[w][t]);
+              for (int q = g0; q < g0 + n; ++q) {
+                double p[DIM];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+                const double s = sqdist<DIM>(p, xt);
+                if (s < r2t) a.add(wphi[q] * wendland<PHI, T>(scaled_r<T>(s, irt)));
+              }
+              cacc[w][t] = to_pod(a);
+            }
+          }
+        } else {
+          const int k = lane / P, part = lane - k * P;
+          const bool on = k < nn;
+          const int t = on ? nlist[w][k] : 0;
+          const int len = (n + P - 1) / P;
+          const int q0 = g0 + part * len;
+          const int q1 = q0 + len < g0 + n ? q0 + len : g0 + n;
+          Acc<T> a;
+          if (on) {
+            if (part == 0) a = from_pod(cacc[w][t]);
             double xt[DIM];
 #pragma unroll
             for (int d = 0; d < DIM; ++d) xt[d] = cxs[d][t];
             const double r2t = cr2s[t], irt = cirs[t];
-            Acc<T> a = from_pod(cacc[w][t]);
-            for (int q = g0; q < g0 + n; ++q) {
+            for (int q = q0; q < q1; ++q) {
               double p[DIM];
 #pragma unroll
               for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
               const double s = sqdist<DIM>(p, xt);
               if (s < r2t) a.add(wphi[q] * wendland<PHI, T>(scaled_r<T>(s, irt)));
+            }
+          }
+          // the parts of lanes lane+1 .. lane+P-1, added in order by part 0
+          const AccPod<T> mine = to_pod(a);
+          AccPod<T> nb[3];
+#pragma unroll
+          for (int j = 1; j < 4; ++j) {
+            const int src = lane + j < kWave ? lane + j : lane;
+            nb[j - 1].s = __shfl(mine.s, src, kWave);
+            nb[j - 1].c = __shfl(mine.c, src, kWave);
+          }
+          if (on && part == 0) {
+            for (int j = 1; j < P; ++j) {
+              a.add(nb[j - 1].s);
+              a.add(-nb[j - 1].c);
             }
             cacc[w][t] = to_pod(a);
           }
