@@ -247,7 +247,7 @@ int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
 
 /* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
  * starts timing, with HIP events on the plan's stream, the assembly launch
- * (events recorded around it) and every fourth CG iteration launch
+ * (events recorded around it) and one CG iteration launch in sixteen
  * (events stamped at the kernel's own start and end by the extended launch;
  * launches that returned at entry after convergence are not counted);
  * rbf_profile(plan, 0) stops.

@@ -19,6 +19,11 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// With timing on, one CG iteration launch in kProfPeriod carries start/stop
+// events.  Each stamped launch costs a few microseconds of extra gap on the
+// stream, so the sample is kept sparse (a terrain2d fit still times ~300).
+constexpr int64_t kProfPeriod = 16;
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -729,8 +734,8 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
     if (chunk <= 0) return RBF_OK;
     for (int64_t it = 0; it < chunk; ++it) {
       const int q = (int)((launched + refreshes) & 1);
-      // every fourth launch carries start/stop events when timing is on
-      const bool timed = P->prof_on && (it & 3) == 0;
+      // one launch in kProfPeriod carries start/stop events when timing is on
+      const bool timed = P->prof_on && launched % kProfPeriod == kProfPeriod - 1;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         e0 = P->event();
@@ -860,7 +865,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
     if (chunk <= 0) return RBF_OK;
     for (int64_t it = 0; it < chunk; ++it) {
       const int q = (int)((launched + refreshes) & 1);
-      const bool timed = P->prof_on && (it & 3) == 0;
+      const bool timed = P->prof_on && launched % kProfPeriod == kProfPeriod - 1;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         e0 = P->event();

@@ -262,6 +262,26 @@ def test_solve_mixed_matches_rmse(rbf):
     assert fit <= 1e-8
 
 
+def test_profile_counts(rbf):
+    # Timing on: the assembly launch and one CG iteration launch in sixteen
+    # are stamped; launches queued past convergence are not counted.
+    p = sd.make_problem("terrain2d", scale=1 / 64)
+    plan = rbf.rbf_fit_plan(dev(p.points), dev(p.centers), rho=p.rho, lambda_rel=1e-4)
+    for prec in ("fp32", "fp64"):
+        rbf.rbf_profile(plan, True)
+        rbf.rbf_assemble(plan, p.phi, prec, dev(p.values))
+        c, info = rbf.rbf_solve(plan, rtol=1e-10)
+        n_cg, ms_cg = rbf.rbf_profile_read(plan, "cg_iter")
+        n_asm, ms_asm = rbf.rbf_profile_read(plan, "assemble")
+        rbf.rbf_profile(plan, False)
+        it = info["iterations"]
+        say(prec, "iterations", it, "timed", n_cg, "avg us", 1e3 * ms_cg / max(n_cg, 1))
+        assert info["status"] == 0
+        assert n_asm == 1 and ms_asm > 0.0
+        assert abs(n_cg - it / 16) <= 2 + info["reliable_updates"]
+        assert 1e-4 < ms_cg / n_cg < 1.0
+
+
 def test_warm_start_and_maxiter(rbf):
     p = sd.make_problem("franke2d", scale=0.25)
     plan = rbf.rbf_fit_plan(dev(p.points), dev(p.centers), rho=p.rho)
