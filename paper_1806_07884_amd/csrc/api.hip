@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <mutex>
 #include <vector>
@@ -362,8 +363,8 @@ int build_halo(rbf_plan* P) {
   // once per plan, for grids of one slice per wave
   if (P->halo_tried || !P->staging || P->ms <= 0) return RBF_OK;
   P->halo_tried = true;
-  int blocks = 0, threads = 0;
-  rbf::cg_grid(P->nslices, &blocks, &threads);
+  int blocks = 0, threads = 0, xg = 0;
+  rbf::cg_grid(P->nslices, &blocks, &threads, &xg);
   if (threads != rbf::kCgSmallBlock) return RBF_OK;
   const int64_t ns = P->nslices;
   const rbf::CgMatrix A = P->matrix(nullptr, 0);
@@ -593,7 +594,7 @@ rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   a.part[0] = P->part_it;
   a.part[1] = P->part_it + rbf::kCgParts * rbf::kCgMaxBlocks;
   a.part_ref = P->part_ref;
-  rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
+  rbf::cg_grid(P->nslices, &a.blocks, &a.threads, &a.xg);
   a.np = P->npoly;
   a.Q = P->npoly ? (sizeof(XT) == 4 ? (const XT*)(const void*)P->q32 : (const XT*)(const void*)P->q64)
                  : nullptr;
@@ -695,14 +696,76 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   return RBF_OK;
 }
 
+// Sizes of the chunks of CG launches queued between host checks.  A launch
+// queued past a raised flag (reliable update, convergence) returns at entry
+// but still costs a few us, and the chunk after the one that raises the flag
+// is always queued too.  So chunks shrink as the flag nears: the decay of
+// ||r||^2 between the last two snapshots gives the iterations left to the
+// trigger (the soonest over the right-hand sides still iterating), and a
+// chunk takes half of what remains past the chunk still in flight, between
+// 4 launches and check_every.  Without a decay to go by (after a refresh,
+// which may have converged, or when ||r|| grew) chunks start small and double.
+struct ChunkPlanner {
+  int64_t cmin, cmax, ramp;
+  int nr = 0;
+  double rr0[rbf::kMaxRhs], rr1[rbf::kMaxRhs], trig[rbf::kMaxRhs];
+  bool on[rbf::kMaxRhs];
+  int64_t it0 = -1, it1 = -1;
+
+  explicit ChunkPlanner(int64_t check_every)
+      : cmin(std::min<int64_t>(4, check_every)), cmax(check_every), ramp(cmin) {}
+  void restart() {
+    it0 = it1 = -1;
+    ramp = cmin;
+  }
+  // a snapshot after `iter` iterations: ||r||^2, trigger and activity per
+  // right-hand side
+  void seen(int64_t iter, int n, const double* rr, const double* trigger2, const int32_t* active) {
+    nr = n;
+    it0 = it1;
+    it1 = iter;
+    for (int k = 0; k < n; ++k) {
+      rr0[k] = rr1[k];
+      rr1[k] = rr[k];
+      trig[k] = trigger2[k];
+      on[k] = active == nullptr || active[k] != 0;
+    }
+  }
+  int64_t next(int64_t inflight) {
+    double left = -1.0;
+    if (it0 >= 0 && it1 > it0) {
+      for (int k = 0; k < nr; ++k) {
+        if (!on[k]) continue;
+        if (!(rr0[k] > 0.0 && rr1[k] > 0.0 && rr1[k] < rr0[k] && trig[k] > 0.0)) {
+          left = -1.0;  // a right-hand side without a decay: no estimate
+          break;
+        }
+        const double rate = std::log(rr1[k] / rr0[k]) / (double)(it1 - it0);
+        const double lk = rr1[k] > trig[k] ? std::log(trig[k] / rr1[k]) / rate : 0.0;
+        if (left < 0.0 || lk < left) left = lk;
+      }
+    }
+    if (left < 0.0) {
+      const int64_t n = ramp;
+      ramp = std::min(cmax, 2 * ramp);
+      return n;
+    }
+    const double want = 0.5 * left - (double)inflight;
+    const int64_t n = want <= (double)cmin ? cmin : (want >= (double)cmax ? cmax : (int64_t)want);
+    ramp = n;
+    return n;
+  }
+};
+
 // Reliable-update Jacobi-PCG (see cg_kernels.hip).  Returns a status; the
 // float64 solution is left in P->xhi.
 //
-// Iterations are launched in chunks of check_every, each followed by a copy
-// of the scalars into one of two pinned slots and an event.  The next chunk
-// is always queued before the host waits on the previous one, so the GPU
-// never idles on a convergence check; launches after a raised flag return at
-// entry.  Launches never exceed the iteration budget.
+// Iterations are launched in chunks of at most check_every (sized by
+// ChunkPlanner), each followed by a copy of the scalars into one of two
+// pinned slots and an event.  The next chunk is always queued before the host
+// waits on the previous one, so the GPU never idles on a convergence check;
+// launches after a raised flag return at entry.  Launches never exceed the
+// iteration budget.
 template <typename VT, typename XT>
 int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_solve_opts& o,
            int64_t* iters, int64_t* updates, bool allow_stall_exit) {
@@ -721,17 +784,17 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   double last_true = -1.0;
   int stalls = 0;
 
-  // Latest snapshot's ||r||^2 and trigger: once the residual is within a
-  // small factor of the trigger, chunks shrink, so that fewer launches are
-  // queued past the iteration that raises the flag (each costs a few us).
-  double seen_rr = -1.0, seen_trig = 0.0;
-  // queue one chunk and its snapshot into slot `slot`; false if none is left
+  ChunkPlanner plan(o.check_every);
+  int64_t slot_len[2] = {0, 0};
+  // queue one chunk and its snapshot into slot `slot` (the other slot's
+  // chunk, if queued, is still unobserved); false if none is left
   auto enqueue = [&](int slot, bool* queued) -> int {
     *queued = false;
-    const bool near = seen_rr >= 0.0 && seen_rr <= 3.0 * seen_trig;
-    const int64_t step = near ? std::min<int64_t>(o.check_every, 8) : o.check_every;
+    const int64_t step = plan.next(slot_len[slot ^ 1]);
     const int64_t chunk = std::min<int64_t>(budget - launched, step);
+    slot_len[slot] = 0;
     if (chunk <= 0) return RBF_OK;
+    slot_len[slot] = chunk;
     for (int64_t it = 0; it < chunk; ++it) {
       const int q = (int)((launched + refreshes) & 1);
       // one launch in kProfPeriod carries start/stop events when timing is on
@@ -771,8 +834,8 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       if (rc) return rc;
       rc = wait_slot(cur, &h);
       if (rc) return rc;
-      seen_rr = h.rr;
-      seen_trig = h.trigger2;
+      slot_len[cur] = 0;
+      plan.seen(h.iter, 1, &h.rr, &h.trigger2, nullptr);
       if (h.done == 0 && next_q) {
         *iters = base_iter + h.iter;
         if (P->prof_on) P->resolve(*iters, false);
@@ -809,7 +872,8 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       ++refreshes;
       *updates += 1;
       fixed = true;
-      seen_rr = -1.0;     // the refresh sets a new trigger
+      plan.restart();     // the refresh sets a new trigger
+      slot_len[0] = slot_len[1] = 0;
       launched = h.iter;  // every queued launch has run; later ones returned at entry
       cur = 0;
       rc = enqueue(cur, &cur_q);
@@ -846,7 +910,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   a.part[0] = P->bpart_it;
   a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
   a.part_ref = P->bpart_ref;
-  rbf::cg_grid(P->nslices, &a.blocks, &a.threads);
+  rbf::cg_grid(P->nslices, &a.blocks, &a.threads, &a.xg);
   const int rch = build_halo(P);
   if (rch) return rch;
   const rbf::CgMatrix A = P->matrix(val, (int)sizeof(XT), nr);
@@ -856,13 +920,16 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   int64_t refreshes = 1, launched = 0;
   const int64_t budget = o.max_iter;
   bool fixed = true;
-  bool near = false;
+  ChunkPlanner plan(o.check_every);
+  int64_t slot_len[2] = {0, 0};
   // queue one chunk and its snapshot into slot `slot`
   auto enqueue = [&](int slot, bool* queued) -> int {
     *queued = false;
-    const int64_t step = near ? std::min<int64_t>(o.check_every, 8) : o.check_every;
+    const int64_t step = plan.next(slot_len[slot ^ 1]);
     const int64_t chunk = std::min<int64_t>(budget - launched, step);
+    slot_len[slot] = 0;
     if (chunk <= 0) return RBF_OK;
+    slot_len[slot] = chunk;
     for (int64_t it = 0; it < chunk; ++it) {
       const int q = (int)((launched + refreshes) & 1);
       const bool timed = P->prof_on && launched % kProfPeriod == kProfPeriod - 1;
@@ -883,12 +950,6 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
     *queued = true;
     return RBF_OK;
   };
-  // chunks shrink once some active right-hand side nears its trigger
-  auto seen = [&](const rbf::CgScalarsN& h) {
-    near = false;
-    for (int k = 0; k < nr; ++k)
-      if (h.active[k] && h.rr[k] <= 3.0 * h.trigger2[k]) near = true;
-  };
   int cur = 0;
   bool cur_q = false;
   int rc = enqueue(cur, &cur_q);
@@ -901,7 +962,8 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
       if (rc) return rc;
       HIPCHK(hipEventSynchronize(P->snap_ev[cur]));
       h = P->host_bsc[cur];
-      seen(h);
+      slot_len[cur] = 0;
+      plan.seen(h.iter, nr, h.rr, h.trigger2, h.active);
       if (h.done == 0 && next_q) {
         *iters = h.iter;
         if (P->prof_on) P->resolve(h.iter, false);
@@ -930,7 +992,8 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
       ++refreshes;
       *updates += 1;
       fixed = true;
-      near = false;
+      plan.restart();
+      slot_len[0] = slot_len[1] = 0;
       launched = h.iter;  // every queued launch has run; later ones returned at entry
       cur = 0;
       rc = enqueue(cur, &cur_q);

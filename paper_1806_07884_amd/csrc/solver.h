@@ -94,6 +94,7 @@ struct CgArgs {
   double* part_ref;    // [kCgParts * blocks] partials of a refresh
   int blocks;          // grid of every slice kernel
   int threads;         // its block size: kCgSmallBlock or kCgLargeBlock
+  int xg;              // XCD chunks of the iteration kernel (see cg_grid)
   // polynomial block (np = 0: none)
   int np;
   const XT* Q;            // [np][m], Q[t * m + row]
@@ -154,8 +155,11 @@ __host__ __device__ inline int64_t sell_pos(const int64_t* sptr, int lanes, int6
 }
 
 int sell_lanes(double mean_row);
-// Grid (blocks, threads per block) of the slice kernels for nslices slices.
-void cg_grid(int64_t nslices, int* blocks, int* threads);
+// Grid (blocks, threads per block) of the slice kernels for nslices slices,
+// and the XCD chunking of the iteration kernels: with xcd_chunks = G > 0 the
+// block count is a multiple of 8 G and each XCD streams G contiguous ranges
+// of slices (0: blocks in dispatch order).
+void cg_grid(int64_t nslices, int* blocks, int* threads, int* xcd_chunks);
 
 // One CG iteration on state buffer q (reads st[q], writes st[q ^ 1]).  fixed:
 // the first iteration after a refresh, which takes its scalars from the
@@ -220,6 +224,7 @@ struct CgArgsN {
   double* part_ref; // [blocks][6 nr] partials of a refresh
   int blocks;
   int threads;
+  int xg;           // XCD chunks of the iteration kernel (see cg_grid)
 };
 template <typename VT, typename XT>
 hipError_t cgn_iterate(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed,
