@@ -23,7 +23,10 @@ workloads; the oracle baseline is taken for terrain2d only.
 points): one plan and assembly, then rbf_set_values and rbf_solve per
 component (or, with ``--batch``, rbf_solve_batch: all components in one CG
 kernel per iteration); throughput counts N points per fit of all p
-components.
+components.  ``--stream K`` assembles from K point chunks (rbf_stream_begin,
+rbf_stream_add per chunk, rbf_stream_finish: B and g as sums over the chunks)
+instead of one resident plan; the timed fits read the chunks from HBM, and
+one more fit from pinned host memory is reported beside (PCIe included).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -117,6 +120,10 @@ def main() -> int:
                     help="vector-valued data: components sharing the points (B assembled once)")
     ap.add_argument("--batch", action="store_true",
                     help="with --components 2..4: solve all components in one batched CG")
+    ap.add_argument("--stream", type=int, default=0, metavar="K",
+                    help="assemble from K point chunks (rbf_stream_*) instead of one resident "
+                         "plan; the chunks sit in HBM for the timed fits, and one more fit takes "
+                         "them from pinned host memory (PCIe-inclusive, reported beside)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -160,9 +167,36 @@ def main() -> int:
         qk = sd.terrain_values(modes, q)
         extra.append((dev(hk), dev(qk)))
     stacked = torch.stack([vals] + [hk for hk, _ in extra]) if args.batch and extra else None
+    # point chunks of the streamed assembly: contiguous (dim, n_c) copies, in
+    # HBM and in pinned host memory
+    chunks_dev, chunks_host = [], []
+    if args.stream:
+        if args.polynomial or args.components > 1:
+            log("--stream takes neither --polynomial nor --components")
+            return 2
+        bounds = np.linspace(0, n_train, args.stream + 1).astype(np.int64)
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            xc = np.ascontiguousarray(prob.points[:, a:b])
+            hc = np.ascontiguousarray(prob.values[a:b])
+            chunks_dev.append((dev(xc), dev(hc)))
+            chunks_host.append((torch.from_numpy(xc).pin_memory(),
+                                torch.from_numpy(hc).pin_memory()))
+        max_chunk = int(np.max(np.diff(bounds)))
+    source = {"chunks": chunks_dev}
     torch.cuda.synchronize()
 
     def fit(prec: str, profile: bool = False):
+        if args.stream:
+            plan = rbf.rbf_stream_begin(ctr, max_chunk, rho=prob.rho, phi=prob.phi, prec=prec,
+                                        lambda_rel=LAMBDA_REL)
+            if profile:
+                rbf.rbf_profile(plan, True)
+            for xc, hc in source["chunks"]:
+                rbf.rbf_stream_add(plan, xc, hc)
+            rbf.rbf_stream_finish(plan)
+            c, info = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
+            _, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+            return plan, info, rmse
         plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL,
                                 polynomial=args.polynomial)
         if profile:
@@ -211,6 +245,14 @@ def main() -> int:
     dt32, per32, stats, n32, avg32, asm32 = timed("fp32", steps, args.warmup)
     dt64, per64, _, n64, avg64, asm64 = timed("fp64", args.fp64_steps or steps, args.warmup)
     value = n_train / dt32
+    pcie = None
+    if args.stream:
+        # the same fit with the chunks coming from pinned host memory
+        source["chunks"] = chunks_host
+        dth, perh, _, _, _, _ = timed("fp32", 1, 0)
+        pcie = {"ms_per_fit": dth * 1e3, "value": n_train / dth,
+                "scoring_rmse": perh[-1][1], "chunks": args.stream}
+        source["chunks"] = chunks_dev
     rmse32, rmse64 = per32[-1][1], per64[-1][1]
     matched = abs(rmse32 - rmse64) <= 1e-3 * rmse64
 
@@ -254,7 +296,8 @@ def main() -> int:
                    "nnz_full": int(nnz), "precision": "fp32 assembly/CG + fp64 reliable updates",
                    "polynomial": "linear" if npoly else "none",
                    "components": max(1, args.components),
-                   "batched_solve": stacked is not None},
+                   "batched_solve": stacked is not None,
+                   "stream_chunks": int(args.stream)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": {"ms_per_fit": dt32 * 1e3, "iterations": per32[-1][0]["iterations"],
@@ -267,6 +310,7 @@ def main() -> int:
                  "assembly_ms": asm64, "cg_iter_kernel_us": kern64 * 1e6,
                  "cg_iter_gbps": b64 / kern64 / 1e9},
         "speedup_mixed_vs_fp64": dt64 / dt32,
+        "stream_from_host": pcie,
         "rmse_matched": bool(matched),
         "scoring": (f"{q.shape[1]} held-out points vs noisy samples" if prob.test_points.shape[1]
                     else f"{q.shape[1]} uniform queries vs the noise-free field"),

@@ -209,10 +209,11 @@ int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, do
  * in the paper's basis (x^T, 1); inactive centres get 0.  The residual
  * ||.|| and ||g|| of the stopping test cover the whole bordered system.  opts NULL: rtol 1e-10,
  * max_iter 100000, check_every 32, reliable_delta 0.1.  Iterations are queued
- * in chunks of check_every (at most 8 once the residual nears the next
- * trigger), each followed by a copy of the residual to host memory; the host
- * waits on a chunk's copy only after the next chunk is queued, so launches
- * queued past convergence return at entry.  Returns OK, WARN_MAXITER
+ * in chunks of at most check_every, shorter as the residual nears the next
+ * reliable-update trigger (sized from its decay), each followed by a copy of
+ * the residual to host memory; the host waits on a chunk's copy only after
+ * the next chunk is queued, so launches queued past a trigger or convergence
+ * return at entry.  Returns OK, WARN_MAXITER
  * (best iterate kept), WARN_FALLBACK (mixed precision stalled and FP64 took
  * over), ERR_BREAKDOWN, ERR_INVALID (not assembled), ERR_HIP.  info may be
  * NULL. */
@@ -245,7 +246,71 @@ int rbf_solve_batch(rbf_plan* plan, int32_t nrhs, const double* values,
 int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
              const double* coeffs, double* out, const double* values, double* rmse_h);
 
-/* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
+/* ---- points streamed through the GPU in chunks -------------------------- *
+ * B = A^T A and g = A^T h are sums over the points: with A_c the rows of A of
+ * the points of chunk c, B = sum_c A_c^T A_c and g = sum_c A_c^T h_c (the
+ * block decomposition of Section 5, eq. 13-16, taken over point blocks rather
+ * than column blocks).  A fit therefore need not hold its points in HBM: a
+ * stream plan is made from the centres alone, chunks of points and values are
+ * added one at a time (from device or host memory), and rbf_stream_finish
+ * forms what rbf_fit_plan and rbf_assemble form for the union of the chunks:
+ * the support counts, the active set and the structural pattern are the same
+ * bit for bit; the values of B and g are summed per chunk in the precision of
+ * the assembly (float32 Kahan sums of float32 phi, or float64) and across
+ * chunks in float64, so they agree with a resident assembly to within the
+ * rounding of the sums.  The finished plan serves rbf_solve, rbf_eval,
+ * rbf_plan_info, rbf_plan_pattern, rbf_system_export, rbf_block_sq_err and
+ * rbf_radius_broadcast; calls that need the points (rbf_assemble,
+ * rbf_set_values, rbf_solve_batch, rbf_density_features) fail with INVALID,
+ * and so do rbf_plan_info and rbf_plan_pattern before the finish.  No
+ * polynomial block. */
+typedef struct {
+  int32_t dim;                  /* 2 or 3 */
+  int64_t n_centers;            /* M */
+  const double* centers;        /* device, SoA [dim][M]; copied */
+  double rho;                   /* support radius (> 0) when rho_per_center is NULL */
+  const double* rho_per_center; /* device [M] radii > 0, or NULL; copied */
+  int32_t min_support;          /* as rbf_plan_desc, applied at the finish (>= 1) */
+  double lambda_rel;            /* as rbf_plan_desc (>= 0) */
+  rbf_phi phi;                  /* basis of the assembly */
+  rbf_precision precision;      /* precision of the assembly and of rbf_solve */
+  int64_t max_chunk;            /* most points one rbf_stream_add takes, [1, 2^31);
+                                   the plan holds one chunk's hash workspace (and,
+                                   for host chunks, two staging slots) of this size */
+  uint32_t flags;               /* RBF_PLAN_* bits, 0 by default */
+} rbf_stream_desc;
+
+/* Make a stream plan: centre hash, the candidate list of every centre (the
+ * centres whose ball can meet its own) and zeroed accumulators over them.
+ * Blocks the host to size the lists.  Errors: INVALID (as rbf_fit_plan, bad
+ * phi/precision/max_chunk, a centre with more than 1024 candidates),
+ * NONFINITE, OOM, HIP.  On error *out is NULL. */
+int rbf_stream_begin(const rbf_stream_desc* desc, const rbf_allocator* allocator, void* stream,
+                     rbf_plan** out);
+
+/* Add a chunk of n points (0 <= n <= max_chunk): coordinates SoA [dim][n]
+ * (component d of point i at points[d * n + i]) and values [n], both on the
+ * device (on_host = 0: read on the plan's stream, stream-ordered) or both in
+ * host memory (on_host != 0: copied into a staging slot on the plan's own copy
+ * stream, so the copy of one chunk overlaps the accumulation of the one
+ * before; pinned memory makes the copy asynchronous).  A host chunk's memory
+ * may be reused once the next rbf_stream_add or rbf_stream_finish has
+ * returned.  Chunks may come in any order and sizes; the sums are added in the
+ * order of the calls, so the same chunks in the same order give the same bits.
+ * Non-finite coordinates or values are reported by rbf_stream_finish.  Errors:
+ * INVALID (not an open stream plan, n out of range, NULL pointers), HIP, OOM. */
+int rbf_stream_add(rbf_plan* plan, int64_t n, const double* points, const double* values,
+                   int32_t on_host);
+
+/* Form the system of all chunks added: active centres (support count >=
+ * min_support), the structural pattern (upper and full CSR, columns ascending),
+ * the solver layout, the values of B and g, the ridge and the Jacobi
+ * preconditioner; the plan then solves as an assembled one.  Blocks the host.
+ * Errors: INVALID (not an open stream plan, pattern over 2^31 entries),
+ * NONFINITE (a chunk held NaN/Inf), OOM, HIP. */
+int rbf_stream_finish(rbf_plan* plan);
+
+/* Kernel timing for measurement./* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
  * starts timing, with HIP events on the plan's stream, the assembly launch
  * (events recorded around it) and one CG iteration launch in sixteen
  * (events stamped at the kernel's own start and end by the extended launch;

@@ -53,6 +53,15 @@ class PlanStats(ctypes.Structure):
                 ("n_poly", ctypes.c_int32), ("solver_staged", ctypes.c_int32)]
 
 
+class StreamDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_centers", ctypes.c_int64),
+                ("centers", ctypes.c_void_p), ("rho", ctypes.c_double),
+                ("rho_per_center", ctypes.c_void_p), ("min_support", ctypes.c_int32),
+                ("lambda_rel", ctypes.c_double), ("phi", ctypes.c_int),
+                ("precision", ctypes.c_int), ("max_chunk", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32),
@@ -95,6 +104,11 @@ SIGNATURES = {
     "rbf_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.POINTER(ctypes.c_double)]),
+    "rbf_stream_begin": (ctypes.c_int, [ctypes.POINTER(StreamDesc), ctypes.POINTER(Allocator),
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "rbf_stream_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int32]),
+    "rbf_stream_finish": (ctypes.c_int, [ctypes.c_void_p]),
     "rbf_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rbf_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int64),

@@ -131,6 +131,74 @@ def rbf_plan_pattern(plan: Plan):
     return rp, col[:info["nnz_upper"]], sup
 
 
+def rbf_stream_begin(centers: torch.Tensor, max_chunk: int, rho: Optional[float] = None,
+                     rho_per_center: Optional[torch.Tensor] = None, phi: str = "w31",
+                     prec: str = "fp64", min_support: int = 1, lambda_rel: float = 0.0,
+                     stream: Optional[torch.cuda.Stream] = None, staging: bool = True) -> Plan:
+    """Stream plan from the centres alone (rbf_stream_begin): points then come
+    in chunks of at most max_chunk (rbf_stream_add) and rbf_stream_finish
+    forms the system, as rbf_fit_plan + rbf_assemble would for all of them."""
+    _need(centers, "centers")
+    if centers.dim() != 2:
+        raise ValueError("centers must be (dim, M)")
+    dim, m = centers.shape
+    if rho_per_center is not None:
+        _need(rho_per_center, "rho_per_center", (m,))
+    elif rho is None:
+        raise ValueError("give rho or rho_per_center")
+    plan = Plan()
+    plan.dim, plan.n, plan.m = int(dim), 0, int(m)
+    plan.device = centers.device
+    plan.stream = stream if stream is not None else torch.cuda.current_stream(centers.device)
+    plan._alloc = _make_allocator(plan.device, plan.stream)
+    desc = L.StreamDesc(int(dim), int(m), centers.data_ptr(),
+                        float(rho) if rho is not None else 0.0,
+                        rho_per_center.data_ptr() if rho_per_center is not None else None,
+                        int(min_support), float(lambda_rel), L.PHI[phi], L.PREC[prec],
+                        int(max_chunk), 0 if staging else L.PLAN_NO_STAGING)
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_stream_begin(ctypes.byref(desc), ctypes.byref(plan._alloc),
+                                      plan._stream_handle(), ctypes.byref(plan.handle))
+    L.check(st, "rbf_stream_begin")
+    return plan
+
+
+def rbf_stream_add(plan: Plan, points: torch.Tensor, values: torch.Tensor) -> None:
+    """Add a chunk (rbf_stream_add): points (dim, n) and values (n,) float64,
+    contiguous, both on the GPU or both in host memory (pinned for an
+    asynchronous copy that overlaps the previous chunk's accumulation)."""
+    on_host = not points.is_cuda
+    for t, name in ((points, "points"), (values, "values")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor")
+        if t.is_cuda == on_host:
+            raise ValueError("points and values must both be on the GPU or both on the host")
+    if points.dim() != 2 or points.shape[0] != plan.dim:
+        raise ValueError(f"points must be ({plan.dim}, n)")
+    n = int(points.shape[1])
+    if tuple(values.shape) != (n,):
+        raise ValueError(f"values has shape {tuple(values.shape)}, expected ({n},)")
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_stream_add(plan.handle, n, points.data_ptr() if n else None,
+                                    values.data_ptr() if n else None, int(on_host))
+    L.check(st, "rbf_stream_add")
+    plan.n += n
+    # inputs the streams may still read: device chunks until the finish, host
+    # chunks until the next call has returned
+    if on_host:
+        plan._keep = [t for t in plan._keep if t.is_cuda] + [points, values]
+    else:
+        plan._keep += [points, values]
+
+
+def rbf_stream_finish(plan: Plan) -> None:
+    """Form the system of all chunks added (rbf_stream_finish); blocks."""
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_stream_finish(plan.handle)
+    L.check(st, "rbf_stream_finish")
+    plan._keep = []
+
+
 def rbf_assemble(plan: Plan, phi: str, prec: str, values: torch.Tensor) -> None:
     """Values of B (+ ridge) and g = A^T h in precision 'fp64' or 'fp32' (rbf_assemble)."""
     _need(values, "values", (plan.n,))

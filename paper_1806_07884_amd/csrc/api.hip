@@ -15,6 +15,7 @@
 #include "plan_kernels.h"
 #include "rbf.h"
 #include "solver.h"
+#include "stream.h"
 
 namespace {
 
@@ -178,6 +179,35 @@ struct rbf_plan {
   rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots (from the pinned pool)
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
 
+  // chunked assembly (rbf_stream_*): 0 = not a stream plan, 1 = taking
+  // chunks, 2 = finished
+  int stream_state = 0;
+  int stream_prec = -1;  // precision of the chunks' sums (rbf_precision)
+  int64_t max_chunk = 0;
+  int64_t* cptr = nullptr;   // candidate lists: [m + 1] offsets, ascending columns
+  int64_t* cup = nullptr;    // [m] start of each list's upper part
+  int32_t* ccol = nullptr;
+  double* sacc = nullptr;    // per upper candidate: float64 sum over the chunks so far
+  uint8_t* smark = nullptr;  // per upper candidate: a point in both supports seen
+  int64_t* scount = nullptr; // per centre: supported points so far
+  int64_t* sinbox = nullptr; // points inside the hash grid so far
+  int32_t* sbad = nullptr;   // a non-finite coordinate or value seen
+  // one chunk's hash (max_chunk points) and the two staging slots of host chunks
+  uint32_t *ckey[2] = {nullptr, nullptr};
+  int32_t* cval[2] = {nullptr, nullptr};
+  void* crtmp = nullptr;
+  double* cps = nullptr;
+  int32_t* cpp = nullptr;
+  int32_t* cpcs = nullptr;
+  double* chs = nullptr;
+  double* stage_x[2] = {nullptr, nullptr};
+  double* stage_h[2] = {nullptr, nullptr};
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t ev_copied[2] = {nullptr, nullptr};
+  hipEvent_t ev_used[2] = {nullptr, nullptr};
+  int stage_next = 0;
+  bool stage_pending[2] = {false, false};
+
   // optional kernel timing: HIP events bracketing sampled launches
   struct Pending {
     int kernel;
@@ -298,6 +328,14 @@ struct rbf_plan {
   }
   ~rbf_plan() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (copy_stream) {
+      (void)hipStreamSynchronize(copy_stream);
+      (void)hipStreamDestroy(copy_stream);
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (ev_copied[k]) (void)hipEventDestroy(ev_copied[k]);
+      if (ev_used[k]) (void)hipEventDestroy(ev_used[k]);
+    }
     while (!bufs.empty()) release(bufs.back().p);
     if (host_sc) pinned_release(host_sc);
     if (host_bsc) (void)hipHostFree(host_bsc);
@@ -404,16 +442,54 @@ int build_halo(rbf_plan* P) {
   return RBF_OK;
 }
 
-int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
-  const int64_t n = P->n, m = P->m;
+// The solver layout over the plan's full CSR (row_ptr, col, ms solver rows,
+// nnz_full entries, col16): sliced ELL with L lanes per row.  Reads its size
+// back, so it synchronises the plan's stream.
+int build_layout(rbf_plan* P) {
+  hipStream_t s = P->stream;
+  const int64_t ms = P->ms;
+  P->lanes = rbf::sell_lanes((double)P->nnz_full / (double)std::max<int64_t>(ms, 1));
+  const int64_t rows_per_slice = 64 / P->lanes;
+  P->nslices = (ms + rows_per_slice - 1) / rows_per_slice;
+  int64_t* ssize;
+  GET(P->slen, P->nslices);
+  GET(P->sptr, P->nslices + 1);
+  GET(ssize, P->nslices + 1);
+  void* stmp2 = P->alloc_bytes(rbf::scan_temp_bytes(P->nslices + 1));
+  if (!stmp2) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, P->srow, ms, P->lanes, P->nslices, P->slen, ssize,
+                                   s));
+  HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(stmp2);
+  P->release(ssize);
+  if (total >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "solver layout exceeds 2^31 entries");
+  P->nsell = total;
+  const size_t cbytes = (size_t)(total + rbf::kSellTail) * (P->col16 ? 2 : 4);
+  P->scol = P->alloc_bytes(cbytes);
+  if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
+  HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
+  HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, P->srow, P->amap, ms, P->sptr, P->lanes,
+                               P->col16, P->scol, s));
+  return RBF_OK;
+}
+
+// Centres, radii, hash grid and centre hash of a plan.  points (device SoA
+// [dim][P->n]) may be NULL (a stream plan); when given, their ranges set the
+// polynomial basis and their finiteness is checked in the same host read.
+int setup_centres(rbf_plan* P, const double* centers, const double* rho_per_center, double rho,
+                  const double* points) {
+  const int64_t n = points ? P->n : 0, m = P->m;
   const int dim = P->dim;
   hipStream_t s = P->stream;
   GET(P->ctr, dim * m);
-  HIPCHK(hipMemcpyAsync(P->ctr, d->centers, sizeof(double) * dim * m, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(P->ctr, centers, sizeof(double) * dim * m, hipMemcpyDeviceToDevice, s));
   GET(P->rho, m);
   GET(P->rho2, m);
   GET(P->irho, m);
-  HIPCHK(rbf::launch_radius_tables(d->rho_per_center, d->rho, m, P->rho, P->rho2, P->irho, s));
+  HIPCHK(rbf::launch_radius_tables(rho_per_center, rho, m, P->rho, P->rho2, P->irho, s));
 
   // ranges and finiteness of centres, points and radii: one host read
   const int nred = 2 * dim + 1;
@@ -424,9 +500,11 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   GET(pmax, nb);
   GET(pbad, nb);
   GET(res, 3 * nred);
+  HIPCHK(hipMemsetAsync(res, 0, sizeof(double) * 3 * nred, s));
   for (int k = 0; k < dim; ++k) {
     HIPCHK(rbf::launch_minmax(P->ctr + k * m, m, pmin, pmax, pbad, nb, res + 3 * k, s));
-    HIPCHK(rbf::launch_minmax(d->points + k * n, n, pmin, pmax, pbad, nb, res + 3 * (dim + k), s));
+    if (points)
+      HIPCHK(rbf::launch_minmax(points + k * n, n, pmin, pmax, pbad, nb, res + 3 * (dim + k), s));
   }
   HIPCHK(rbf::launch_minmax(P->rho, m, pmin, pmax, pbad, nb, res + 3 * (2 * dim), s));
   double host[3 * 7];
@@ -482,20 +560,29 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   if (ncell > kMaxCells) return fail(RBF_ERR_INVALID, "hash grid too large");
   P->grid.ncell = (int32_t)ncell;
 
-  GET(P->ps, dim * n);
-  GET(P->pperm, n);
-  GET(P->pcs, ncell + 2);
-  int rc = hash_into(P, d->points, n, P->ps, P->pperm, P->pcs, true);
-  if (rc) return rc;
   GET(P->ctr_s, dim * m);
   GET(P->cperm, m);
   GET(P->ccs, ncell + 2);
-  rc = hash_into(P, P->ctr, m, P->ctr_s, P->cperm, P->ccs, false);
+  const int rc = hash_into(P, P->ctr, m, P->ctr_s, P->cperm, P->ccs, false);
   if (rc) return rc;
   GET(P->rho2_s, m);
   GET(P->irho_s, m);
   HIPCHK(rbf::launch_gather(P->rho2, P->cperm, m, P->rho2_s, s));
   HIPCHK(rbf::launch_gather(P->irho, P->cperm, m, P->irho_s, s));
+  return RBF_OK;
+}
+
+int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
+  const int64_t n = P->n, m = P->m;
+  const int dim = P->dim;
+  hipStream_t s = P->stream;
+  int rc = setup_centres(P, d->centers, d->rho_per_center, d->rho, d->points);
+  if (rc) return rc;
+  GET(P->ps, dim * n);
+  GET(P->pperm, n);
+  GET(P->pcs, P->grid.ncell + 2);
+  rc = hash_into(P, d->points, n, P->ps, P->pperm, P->pcs, true);
+  if (rc) return rc;
 
   GET(P->support, m);
   GET(P->active, m);
@@ -546,36 +633,203 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   GET(P->col, nnz);
   HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, maxd, marks,
                               s));
-
-  // solver layout: sliced ELL with L lanes per row, over the solver rows
-  P->lanes = rbf::sell_lanes((double)nnz / (double)std::max<int64_t>(ms, 1));
-  const int64_t rows_per_slice = 64 / P->lanes;
-  P->nslices = (ms + rows_per_slice - 1) / rows_per_slice;
-  int64_t* ssize;
-  GET(P->slen, P->nslices);
-  GET(P->sptr, P->nslices + 1);
-  GET(ssize, P->nslices + 1);
-  void* stmp2 = P->alloc_bytes(rbf::scan_temp_bytes(P->nslices + 1));
-  if (!stmp2) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
-  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, P->srow, ms, P->lanes, P->nslices, P->slen, ssize,
-                                   s));
-  HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
-  int64_t total = 0;
-  HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  P->release(stmp2);
-  P->release(ssize);
+  rc = build_layout(P);  // synchronises the stream
   P->release(stmp);
   P->release(err);
   P->release(marks);
-  if (total >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "solver layout exceeds 2^31 entries");
-  P->nsell = total;
-  const size_t cbytes = (size_t)(total + rbf::kSellTail) * (P->col16 ? 2 : 4);
-  P->scol = P->alloc_bytes(cbytes);
-  if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
-  HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
-  HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, P->srow, P->amap, ms, P->sptr, P->lanes,
-                               P->col16, P->scol, s));
+  return rc;
+}
+
+// ---- chunked assembly --------------------------------------------------------
+
+// Candidate lists, accumulators and the chunk workspace of a stream plan.
+int build_stream(rbf_plan* P) {
+  const int64_t m = P->m, mc = P->max_chunk;
+  const int dim = P->dim;
+  hipStream_t s = P->stream;
+  int64_t* cnt;
+  int32_t* err;
+  GET(cnt, m + 1);
+  GET(err, 1);
+  GET(P->cptr, m + 1);
+  GET(P->cup, m);
+  HIPCHK(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
+  const rbf::PlanView v = P->view();
+  HIPCHK(rbf::launch_cand_count(v, cnt, err, s));
+  void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
+  if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::exclusive_scan(cnt, P->cptr, m + 1, stmp, s));
+  int64_t nc = 0;
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&nc, P->cptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&bad, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(stmp);
+  P->release(err);
+  P->release(cnt);
+  if (bad)
+    return fail(RBF_ERR_INVALID,
+                "a centre has more than %d neighbouring centres within two support radii",
+                rbf::kMaxCand);
+  GET(P->ccol, nc);
+  HIPCHK(rbf::launch_cand_fill(v, P->cptr, P->cup, P->ccol, s));
+  // accumulators over the candidates (the upper parts are used) and centres
+  GET(P->sacc, nc);
+  GET(P->smark, nc);
+  GET(P->scount, m);
+  GET(P->sinbox, 1);
+  GET(P->sbad, 1);
+  GET(P->g, m);
+  GET(P->diag, m);
+  GET(P->lam, 1);
+  GET(P->dinv64, m);
+  HIPCHK(hipMemsetAsync(P->sacc, 0, sizeof(double) * nc, s));
+  HIPCHK(hipMemsetAsync(P->smark, 0, (size_t)nc, s));
+  HIPCHK(hipMemsetAsync(P->scount, 0, sizeof(int64_t) * m, s));
+  HIPCHK(hipMemsetAsync(P->sinbox, 0, sizeof(int64_t), s));
+  HIPCHK(hipMemsetAsync(P->sbad, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(P->g, 0, sizeof(double) * m, s));
+  // one chunk's hash
+  for (int k = 0; k < 2; ++k) {
+    GET(P->ckey[k], mc);
+    GET(P->cval[k], mc);
+  }
+  P->crtmp = P->alloc_bytes(rbf::radix_temp_bytes(mc));
+  if (!P->crtmp) return fail(RBF_ERR_OOM, "sort workspace allocation failed");
+  GET(P->cps, dim * mc);
+  GET(P->cpp, mc);
+  GET(P->cpcs, P->grid.ncell + 2);
+  GET(P->chs, mc);
+  return RBF_OK;
+}
+
+// Staging slots and the copy stream of host chunks, made at the first one.
+int ensure_staging(rbf_plan* P) {
+  if (P->copy_stream) return RBF_OK;
+  const int64_t mc = P->max_chunk;
+  for (int k = 0; k < 2; ++k) {
+    GET(P->stage_x[k], P->dim * mc);
+    GET(P->stage_h[k], mc);
+    HIPCHK(hipEventCreateWithFlags(&P->ev_copied[k], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_used[k], hipEventDisableTiming));
+  }
+  HIPCHK(hipStreamCreateWithFlags(&P->copy_stream, hipStreamNonBlocking));
+  return RBF_OK;
+}
+
+// Grid hash of one chunk into the chunk workspace (as hash_into, without the
+// host synchronisation: the workspace lives as long as the plan).
+int hash_chunk(rbf_plan* P, const double* coords, int64_t count) {
+  hipStream_t s = P->stream;
+  int sub = 2 * P->dim;
+  if ((((int64_t)P->grid.ncell + 1) << sub) > (int64_t)UINT32_MAX) sub = 0;
+  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, sub, P->ckey[0], P->cval[0], s));
+  int bits = 1;
+  while ((int64_t(1) << bits) <= ((int64_t)P->grid.ncell << sub) + ((int64_t(1) << sub) - 1)) ++bits;
+  bool in_alt = false;
+  HIPCHK(rbf::radix_sort_pairs(P->ckey[0], P->cval[0], P->ckey[1], P->cval[1], count, bits,
+                               P->crtmp, s, &in_alt));
+  const uint32_t* keys = in_alt ? P->ckey[1] : P->ckey[0];
+  const int32_t* vals = in_alt ? P->cval[1] : P->cval[0];
+  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, sub, P->cpcs, s));
+  HIPCHK(hipMemcpyAsync(P->cpp, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIPCHK(rbf::launch_gather_soa(coords, P->cpp, count, P->dim, P->cps, s));
+  return RBF_OK;
+}
+
+// One chunk (device SoA coordinates x [dim][n], values h [n]) into the
+// accumulators, on the plan's stream.
+int stream_chunk(rbf_plan* P, int64_t n, const double* x, const double* h) {
+  hipStream_t s = P->stream;
+  HIPCHK(rbf::launch_chunk_check(x, h, n, P->dim, P->sbad, s));
+  int rc = hash_chunk(P, x, n);
+  if (rc) return rc;
+  HIPCHK(rbf::launch_stream_inbox(P->cpcs + P->grid.ncell, P->sinbox, s));
+  HIPCHK(rbf::launch_gather(h, P->cpp, n, P->chs, s));
+  rbf::PlanView v = P->view();
+  v.n = n;
+  v.ps = P->cps;
+  v.pcs = P->cpcs;
+  v.pperm = P->cpp;
+  HIPCHK(rbf::launch_stream_accum(v, P->phi, P->stream_prec == RBF_PREC_FP32_REFINE, P->chs, P->cptr,
+                                  P->cup, P->ccol, P->sacc, P->smark, P->scount, P->g, s));
+  return RBF_OK;
+}
+
+// The system of the streamed points: active set, pattern, solver layout,
+// values, ridge and preconditioner (as build_plan and rbf_assemble form them).
+int finish_stream(rbf_plan* P) {
+  const int64_t m = P->m;
+  hipStream_t s = P->stream;
+  GET(P->support, m);
+  GET(P->active, m);
+  HIPCHK(rbf::launch_stream_active(P->scount, m, P->min_support, P->support, P->active, s));
+  int64_t* apos;
+  GET(P->amap, m);
+  GET(P->srow, m);
+  GET(apos, m + 1);
+  void* atmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
+  if (!atmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::launch_solver_rows(P->active, m, apos, atmp, P->amap, P->srow, s));
+  int64_t* cnt;
+  int32_t* maxd;
+  GET(cnt, m + 1);
+  GET(maxd, 1);
+  GET(P->lower_cnt, m);
+  GET(P->row_ptr, m + 1);
+  HIPCHK(hipMemsetAsync(maxd, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
+  HIPCHK(rbf::launch_stream_rows(P->cptr, P->cup, P->ccol, P->smark, P->active, m, cnt,
+                                 P->lower_cnt, maxd, s));
+  void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
+  if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
+  int64_t nnz = 0, ms = 0;
+  int32_t dmax = 0, bad = 0;
+  HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&ms, apos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&dmax, maxd, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&bad, P->sbad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(stmp);
+  P->release(maxd);
+  P->release(cnt);
+  P->release(atmp);
+  P->release(apos);
+  if (bad) return fail(RBF_ERR_NONFINITE, "non-finite point coordinate or value in a chunk");
+  if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
+  P->ms = ms;
+  P->nnz_full = nnz;
+  P->col16 = dmax <= 32767;
+  int64_t* src;
+  GET(P->col, nnz);
+  GET(src, nnz);
+  HIPCHK(rbf::launch_stream_fill(P->cptr, P->cup, P->ccol, P->smark, P->active, m, P->row_ptr,
+                                 P->col, src, s));
+  int rc = build_layout(P);
+  if (rc) return rc;
+  const bool fp32 = P->stream_prec == RBF_PREC_FP32_REFINE;
+  const int64_t nv = P->nsell + rbf::kSellTail;
+  void* val;
+  if (fp32) {
+    GET(P->val32, nv);
+    GET(P->dinv32, m);
+    HIPCHK(hipMemsetAsync(P->val32, 0, sizeof(float) * nv, s));
+    val = P->val32;
+  } else {
+    GET(P->val64, nv);
+    HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * nv, s));
+    val = P->val64;
+  }
+  HIPCHK(rbf::launch_stream_values(P->row_ptr, P->col, src, P->amap, P->active, P->sacc, P->sptr,
+                                   P->lanes, m, fp32, val, P->diag, P->g, s));
+  void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
+  HIPCHK(rbf::launch_finalize(m, P->active, ms, P->srow, P->sptr, P->lanes, P->lower_cnt, P->diag,
+                              P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(src);
+  P->prec = P->stream_prec;
   return RBF_OK;
 }
 
@@ -1115,6 +1369,7 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
 
 int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   if (!P || !o) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (P->stream_state == 1) return fail(RBF_ERR_INVALID, "rbf_stream_finish must come first");
   memset(o, 0, sizeof *o);
   o->dim = P->dim;
   for (int k = 0; k < 3; ++k) o->grid[k] = P->grid.g[k];
@@ -1131,8 +1386,12 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   HIPCHK(hipMemcpyAsync(rp.data(), P->row_ptr, sizeof(int64_t) * (P->m + 1),
                         hipMemcpyDeviceToHost, P->stream));
   HIPCHK(hipMemcpyAsync(act.data(), P->active, P->m, hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipMemcpyAsync(&in_box, P->pcs + P->grid.ncell, sizeof(int32_t), hipMemcpyDeviceToHost,
-                        P->stream));
+  int64_t in_box64 = 0;
+  if (P->pcs)
+    HIPCHK(hipMemcpyAsync(&in_box, P->pcs + P->grid.ncell, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          P->stream));
+  else
+    HIPCHK(hipMemcpyAsync(&in_box64, P->sinbox, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
   int64_t na = 0, tot = 0;
   int32_t smax = 0, rmax = 0;
@@ -1147,7 +1406,7 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->support_max = smax;
   o->row_max = rmax;
   o->nnz_upper = (P->nnz_full + na) / 2;
-  o->n_points_in_box = in_box;
+  o->n_points_in_box = P->pcs ? (int64_t)in_box : in_box64;
   o->density = (double)P->nnz_full / ((double)P->m * (double)P->m);
   o->solver_entries = P->nsell;
   o->solver_col_bytes = P->col16 ? 2 : 4;
@@ -1160,6 +1419,7 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
 int rbf_plan_pattern(const rbf_plan* P, int64_t* row_ptr_h, int32_t* col_h,
                      int32_t* support_count_h) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (P->stream_state == 1) return fail(RBF_ERR_INVALID, "rbf_stream_finish must come first");
   const int64_t m = P->m;
   std::vector<int64_t> rp(m + 1);
   std::vector<int32_t> low(m), colf(P->nnz_full);
@@ -1188,6 +1448,7 @@ int rbf_plan_pattern(const rbf_plan* P, int64_t* row_ptr_h, int32_t* col_h,
 
 int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* values) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!P->ps) return fail(RBF_ERR_INVALID, "a stream plan holds no points to assemble from");
   if ((int)phi < 0 || (int)phi > 3) return fail(RBF_ERR_INVALID, "unknown basis function");
   if ((int)prec < 0 || (int)prec > 1) return fail(RBF_ERR_INVALID, "unknown precision");
   if (!values) return fail(RBF_ERR_INVALID, "values is NULL");
@@ -1208,6 +1469,7 @@ int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* val
 
 int rbf_set_values(rbf_plan* P, const double* values) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!P->ps) return fail(RBF_ERR_INVALID, "a stream plan holds no points");
   if (P->prec < 0) return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_set_values");
   if (!values) return fail(RBF_ERR_INVALID, "values is NULL");
   hipStream_t s = P->stream;
@@ -1319,7 +1581,8 @@ int rbf_poly_export(const rbf_plan* P, double* q_h, double* c_h, double* e_h) {
 int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (!coeffs) return fail(RBF_ERR_INVALID, "coeffs is NULL");
-  if (P->prec < 0) return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_solve");
+  if (P->prec < 0)
+    return fail(RBF_ERR_INVALID, "rbf_assemble (or rbf_stream_finish) must precede rbf_solve");
   rbf_solve_opts o;
   o.rtol = 1e-10;
   o.max_iter = 100000;
@@ -1424,6 +1687,7 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
 int rbf_solve_batch(rbf_plan* P, int32_t nrhs, const double* values,
                     const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!P->ps) return fail(RBF_ERR_INVALID, "a stream plan holds no points");
   if (!values || !coeffs) return fail(RBF_ERR_INVALID, "values/coeffs is NULL");
   if (nrhs < 2 || nrhs > rbf::kMaxRhs)
     return fail(RBF_ERR_INVALID, "nrhs must be in [2, %d]", rbf::kMaxRhs);
@@ -1528,6 +1792,112 @@ int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double
   return RBF_OK;
 }
 
+int rbf_stream_begin(const rbf_stream_desc* d, const rbf_allocator* allocator, void* stream,
+                     rbf_plan** out) {
+  if (!out) return fail(RBF_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(RBF_ERR_INVALID, "desc is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(RBF_ERR_INVALID, "dim must be 2 or 3");
+  if (d->n_centers < 1 || d->n_centers >= (int64_t(1) << 31))
+    return fail(RBF_ERR_INVALID, "n_centers must be in [1, 2^31)");
+  if (!d->centers) return fail(RBF_ERR_INVALID, "centers is NULL");
+  if (!d->rho_per_center && !(d->rho > 0.0 && isfinite(d->rho)))
+    return fail(d->rho > 0.0 ? RBF_ERR_NONFINITE : RBF_ERR_INVALID,
+                "rho must be finite and > 0");
+  if (d->min_support < 1) return fail(RBF_ERR_INVALID, "min_support must be >= 1");
+  if (!(d->lambda_rel >= 0.0 && isfinite(d->lambda_rel)))
+    return fail(RBF_ERR_INVALID, "lambda_rel must be finite and >= 0");
+  if ((int)d->phi < 0 || (int)d->phi > 3) return fail(RBF_ERR_INVALID, "unknown basis function");
+  if ((int)d->precision < 0 || (int)d->precision > 1)
+    return fail(RBF_ERR_INVALID, "unknown precision");
+  if (d->max_chunk < 1 || d->max_chunk >= (int64_t(1) << 31))
+    return fail(RBF_ERR_INVALID, "max_chunk must be in [1, 2^31)");
+  if (d->flags & ~RBF_PLAN_NO_STAGING) return fail(RBF_ERR_INVALID, "unknown plan flags");
+  if (allocator && (!allocator->alloc || !allocator->release))
+    return fail(RBF_ERR_INVALID, "allocator callbacks are NULL");
+  rbf_plan* P = new rbf_plan();
+  if (allocator) {
+    P->alloc = *allocator;
+    P->custom_alloc = true;
+  }
+  P->stream = (hipStream_t)stream;
+  P->dim = d->dim;
+  P->n = 0;
+  P->m = d->n_centers;
+  P->min_support = d->min_support;
+  P->lambda_rel = d->lambda_rel;
+  P->staging = (d->flags & RBF_PLAN_NO_STAGING) == 0;
+  P->max_chunk = d->max_chunk;
+  P->phi = (int)d->phi;
+  P->stream_prec = (int)d->precision;
+  int rc = setup_centres(P, d->centers, d->rho_per_center, d->rho, nullptr);
+  if (!rc) rc = build_stream(P);
+  if (rc != RBF_OK) {
+    delete P;
+    return rc;
+  }
+  P->stream_state = 1;
+  *out = P;
+  return RBF_OK;
+}
+
+int rbf_stream_add(rbf_plan* P, int64_t n, const double* points, const double* values,
+                   int32_t on_host) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (P->stream_state != 1)
+    return fail(RBF_ERR_INVALID, P->stream_state ? "the stream is finished"
+                                                 : "not a stream plan (rbf_stream_begin)");
+  if (n < 0 || n > P->max_chunk)
+    return fail(RBF_ERR_INVALID, "chunk of %lld points (max_chunk %lld)", (long long)n,
+                (long long)P->max_chunk);
+  if (n == 0) return RBF_OK;
+  if (!points || !values) return fail(RBF_ERR_INVALID, "points/values is NULL");
+  const double* x = points;
+  const double* h = values;
+  int slot = -1;
+  if (on_host) {
+    int rc = ensure_staging(P);
+    if (rc) return rc;
+    slot = P->stage_next;
+    P->stage_next ^= 1;
+    // the slot's previous chunk has been consumed by the plan's stream
+    if (P->stage_pending[slot]) HIPCHK(hipStreamWaitEvent(P->copy_stream, P->ev_used[slot], 0));
+    const int dim = P->dim;
+    for (int d = 0; d < dim; ++d)
+      HIPCHK(hipMemcpyAsync(P->stage_x[slot] + d * n, points + d * n, sizeof(double) * n,
+                            hipMemcpyHostToDevice, P->copy_stream));
+    HIPCHK(hipMemcpyAsync(P->stage_h[slot], values, sizeof(double) * n, hipMemcpyHostToDevice,
+                          P->copy_stream));
+    HIPCHK(hipEventRecord(P->ev_copied[slot], P->copy_stream));
+    HIPCHK(hipStreamWaitEvent(P->stream, P->ev_copied[slot], 0));
+    x = P->stage_x[slot];
+    h = P->stage_h[slot];
+  }
+  int rc = stream_chunk(P, n, x, h);
+  if (rc) return rc;
+  if (on_host) {
+    HIPCHK(hipEventRecord(P->ev_used[slot], P->stream));
+    P->stage_pending[slot] = true;
+    // the previous host chunk has been copied: its memory is the caller's again
+    const int prev = slot ^ 1;
+    if (P->stage_pending[prev]) HIPCHK(hipEventSynchronize(P->ev_copied[prev]));
+  }
+  P->n += n;
+  return RBF_OK;
+}
+
+int rbf_stream_finish(rbf_plan* P) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (P->stream_state != 1)
+    return fail(RBF_ERR_INVALID, P->stream_state ? "the stream is finished"
+                                                 : "not a stream plan (rbf_stream_begin)");
+  if (P->copy_stream) HIPCHK(hipStreamSynchronize(P->copy_stream));
+  const int rc = finish_stream(P);
+  if (rc) return rc;
+  P->stream_state = 2;
+  return RBF_OK;
+}
+
 int rbf_profile(rbf_plan* P, int32_t enable) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   HIPCHK(hipStreamSynchronize(P->stream));
@@ -1603,6 +1973,7 @@ extern "C" {
 int rbf_density_features(rbf_plan* P, int32_t n_radii, const double* radii_h,
                          int32_t blocks_per_dim, float* feats) {
   if (!P || !radii_h || !feats) return fail(RBF_ERR_INVALID, "NULL argument");
+  if (!P->ps) return fail(RBF_ERR_INVALID, "a stream plan holds no points");
   if (n_radii < 1 || n_radii > rbf::kMaxRadii)
     return fail(RBF_ERR_INVALID, "n_radii must be in [1, %d]", rbf::kMaxRadii);
   double rmax = 0.0;

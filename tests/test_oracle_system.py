@@ -123,6 +123,36 @@ def test_block_partition_equals_whole():
     assert np.allclose(np.triu(B), np.triu(full), rtol=1e-14, atol=0)
 
 
+def _upper_dense(ne, data):
+    m = ne.m
+    out = np.zeros((m, m))
+    for j in range(m):
+        a, b = ne.row_ptr[j], ne.row_ptr[j + 1]
+        out[j, ne.col[a:b]] = data[a:b]
+    return out
+
+
+def test_point_chunks_sum_to_whole():
+    # the same decomposition over point blocks (the chunked assembly):
+    # B = sum_c A_c^T A_c, g = sum_c A_c^T h_c, n_j = sum_c n_j^c, and the
+    # structural pattern is the union of the chunks' (shared-point counts add)
+    pts, h, ctr, rho = _tiny(7, n=500, m=36, rho=0.28)
+    whole = orc.normal_equations(pts, h, ctr, rho, "w31")
+    m = ctr.shape[1]
+    B, G, N, C = np.zeros((m, m)), np.zeros(m), np.zeros(m, np.int64), np.zeros((m, m))
+    for a, b in [(0, 130), (130, 131), (131, 400), (400, 500)]:
+        ne = orc.normal_equations(pts[:, a:b], h[a:b], ctr, rho, "w31")
+        B += _upper_dense(ne, ne.val)
+        C += _upper_dense(ne, ne.pair_count.astype(float))
+        G += ne.g
+        N += ne.support_count
+    assert np.array_equal(N, whole.support_count)
+    assert np.array_equal(C, _upper_dense(whole, whole.pair_count.astype(float)))
+    assert np.array_equal(np.argwhere(C > 0), np.argwhere(_upper_dense(whole, np.ones(whole.nnz_upper)) > 0))
+    assert np.allclose(B, _upper_dense(whole, whole.val), rtol=1e-13, atol=1e-15)
+    assert np.allclose(G, whole.g, rtol=1e-13, atol=1e-15)
+
+
 # ------------------------------------------------------------------- solve
 @pytest.mark.parametrize("kind", orc.PHI_KINDS)
 def test_solve_equals_dense_qr(kind):
