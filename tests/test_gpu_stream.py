@@ -181,8 +181,11 @@ def test_stream_equals_resident(rbf):
             _, r = rbf.rbf_eval(plan, dev(p.test_points), c, values=dev(p.test_values))
             out[name] = (r, info["iterations"])
         say(prec, out)
-        # FP32: two float32-stored systems that differ by the assembly's rounding
-        rtol = 1e-8 if prec == "fp64" else 1e-4
+        # two solves to a relative residual of 1e-10 of systems equal to within
+        # the summation bound (the resident-vs-oracle bar of the float64 fit is
+        # the same 1e-6); FP32: two float32-stored systems that differ by the
+        # assembly's rounding
+        rtol = 1e-6 if prec == "fp64" else 1e-4
         assert abs(out["stream"][0] - out["resident"][0]) <= rtol * out["resident"][0]
         res.close()
         st.close()
