@@ -183,6 +183,7 @@ struct rbf_plan {
   // chunks, 2 = finished
   int stream_state = 0;
   int stream_prec = -1;  // precision of the chunks' sums (rbf_precision)
+  bool stream_grouped = false;  // upper candidate lists longer than one wave on average
   int64_t max_chunk = 0;
   int64_t* cptr = nullptr;   // candidate lists: [m + 1] offsets, ascending columns
   int64_t* cup = nullptr;    // [m] start of each list's upper part
@@ -674,6 +675,9 @@ int build_stream(rbf_plan* P) {
                 rbf::kMaxCand);
   GET(P->ccol, nc);
   HIPCHK(rbf::launch_cand_fill(v, P->cptr, P->cup, P->ccol, s));
+  // the candidate relation is symmetric and holds every centre's own index:
+  // the upper lists hold (nc + m) / 2 entries in all
+  P->stream_grouped = (double)(nc + m) / (2.0 * (double)std::max<int64_t>(m, 1)) > 64.0;
   // accumulators over the candidates (the upper parts are used) and centres
   GET(P->sacc, nc);
   GET(P->smark, nc);
@@ -752,8 +756,9 @@ int stream_chunk(rbf_plan* P, int64_t n, const double* x, const double* h) {
   v.ps = P->cps;
   v.pcs = P->cpcs;
   v.pperm = P->cpp;
-  HIPCHK(rbf::launch_stream_accum(v, P->phi, P->stream_prec == RBF_PREC_FP32_REFINE, P->chs, P->cptr,
-                                  P->cup, P->ccol, P->sacc, P->smark, P->scount, P->g, s));
+  HIPCHK(rbf::launch_stream_accum(v, P->phi, P->stream_prec == RBF_PREC_FP32_REFINE,
+                                  P->stream_grouped, P->chs, P->cptr, P->cup, P->ccol, P->sacc,
+                                  P->smark, P->scount, P->g, s));
   return RBF_OK;
 }
 

@@ -30,6 +30,7 @@
 // FP64 variant: float64 phi and float64 accumulation.
 // FP32 variant: squared distance and support test in float64 (the pattern is
 // fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
+#include "accum.h"
 #include "plan_kernels.h"
 #include "solver.h"
 
@@ -40,63 +41,7 @@ constexpr int kAsmChunk = 256;
 constexpr int kSlots = 4;  // columns per lane in one pass: 256 per pass
 constexpr int kCols = kWave * kSlots;
 
-template <typename T>
-struct Acc;
-template <>
-struct Acc<double> {
-  double s = 0.0;
-  __device__ __forceinline__ void add(double v) { s += v; }
-  __device__ __forceinline__ double value() const { return s; }
-};
-template <>
-struct Acc<float> {
-  Kahan32 k;
-  __device__ __forceinline__ void add(float v) { k.add(v); }
-  __device__ __forceinline__ float value() const { return k.s; }
-};
-
-template <typename T>
-__device__ __forceinline__ T scaled_r(double s, double irho);
-template <>
-__device__ __forceinline__ double scaled_r<double>(double s, double irho) {
-  return __builtin_sqrt(s) * irho;
-}
-template <>
-__device__ __forceinline__ float scaled_r<float>(double s, double irho) {
-  return __builtin_sqrtf((float)s) * (float)irho;
-}
-
 constexpr int kAsmWaves = 4;
-
-// Plain-data copy of an accumulator (LDS variables take no initialisers).
-template <typename T>
-struct AccPod {
-  T s, c;
-};
-__device__ __forceinline__ Acc<double> from_pod(const AccPod<double>& p) {
-  Acc<double> a;
-  a.s = p.s;
-  return a;
-}
-__device__ __forceinline__ Acc<float> from_pod(const AccPod<float>& p) {
-  Acc<float> a;
-  a.k.s = p.s;
-  a.k.c = p.c;
-  return a;
-}
-__device__ __forceinline__ AccPod<double> to_pod(const Acc<double>& a) { return {a.s, 0.0}; }
-__device__ __forceinline__ AccPod<float> to_pod(const Acc<float>& a) { return {a.k.s, a.k.c}; }
-
-template <typename T>
-__device__ __forceinline__ double partial_value(const Acc<T>& a);
-template <>
-__device__ __forceinline__ double partial_value<double>(const Acc<double>& a) {
-  return a.s;
-}
-template <>
-__device__ __forceinline__ double partial_value<float>(const Acc<float>& a) {
-  return (double)a.k.s - (double)a.k.c;
-}
 
 template <int DIM, int PHI, typename T, bool GROUPED>
 __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(

@@ -19,10 +19,11 @@ hipError_t launch_chunk_check(const double* x, const double* h, int64_t n, int d
 hipError_t launch_stream_inbox(const int32_t* sentinel_start, int64_t* inbox, hipStream_t s);
 // One chunk's terms: P's point hash is the chunk's (n points, values hs in
 // sorted order); acc/mark over the candidates, count and g over the centres.
-hipError_t launch_stream_accum(const PlanView& P, int phi, bool fp32, const double* hs,
-                               const int64_t* cptr, const int64_t* cup, const int32_t* ccol,
-                               double* acc, uint8_t* mark, int64_t* count, double* g,
-                               hipStream_t s);
+// grouped: the grouped path (candidate lists longer than one wave on average).
+hipError_t launch_stream_accum(const PlanView& P, int phi, bool fp32, bool grouped,
+                               const double* hs, const int64_t* cptr, const int64_t* cup,
+                               const int32_t* ccol, double* acc, uint8_t* mark, int64_t* count,
+                               double* g, hipStream_t s);
 // support[j] = min(count[j], INT32_MAX), active[j] = count[j] >= min_support.
 hipError_t launch_stream_active(const int64_t* count, int64_t m, int32_t min_support,
                                 int32_t* support, uint8_t* active, hipStream_t s);

@@ -24,6 +24,7 @@
 // FP64 variant: float64 phi and sums.  FP32 variant: phi in float32 and
 // float32 Kahan sums within a chunk (as the resident assembly), the chunk
 // partials added in float64 and rounded once when the system is formed.
+#include "accum.h"
 #include "plan_kernels.h"
 #include "solver.h"
 #include "stream.h"
@@ -35,32 +36,6 @@ constexpr int kStrWaves = 4;
 constexpr int kStrChunk = 256;
 constexpr int kStrSlots = 4;
 constexpr int kStrCols = kWave * kStrSlots;
-
-template <typename T>
-struct SAcc;
-template <>
-struct SAcc<double> {
-  double s = 0.0;
-  __device__ __forceinline__ void add(double v) { s += v; }
-  __device__ __forceinline__ double value() const { return s; }
-};
-template <>
-struct SAcc<float> {
-  Kahan32 k;
-  __device__ __forceinline__ void add(float v) { k.add(v); }
-  __device__ __forceinline__ double value() const { return (double)k.s - (double)k.c; }
-};
-
-template <typename T>
-__device__ __forceinline__ T str_r(double s, double irho);
-template <>
-__device__ __forceinline__ double str_r<double>(double s, double irho) {
-  return __builtin_sqrt(s) * irho;
-}
-template <>
-__device__ __forceinline__ float str_r<float>(double s, double irho) {
-  return __builtin_sqrtf((float)s) * (float)irho;
-}
 
 // ---- candidate lists ------------------------------------------------------
 
@@ -165,98 +140,196 @@ __global__ void k_chunk_check(const double* __restrict__ x, const double* __rest
 
 // The chunk's terms of row j (one block of kStrWaves waves): its points in
 // the support of j (the view's point hash is the chunk's) are split among the
-// waves; lanes own up to kStrSlots upper candidates per pass.
-template <int DIM, int PHI, typename T>
+// waves.  Ungrouped: lanes own up to kStrSlots upper candidates per pass and
+// visit every staged point.  GROUPED (candidate lists longer than one wave on
+// average): the staged points are taken 64 at a time (consecutive, so
+// spatially close), the candidates whose ball can reach a group's bounding
+// ball are listed, and each lane runs through the group's points for one
+// listed candidate, adding to the wave's LDS accumulator of that candidate.
+// Either way every sum has a fixed order.
+template <int DIM, int PHI, typename T, bool GROUPED>
 __global__ __launch_bounds__(kWave* kStrWaves) void k_stream_accum(
     PlanView P, const double* __restrict__ hs, const int64_t* __restrict__ cptr,
     const int64_t* __restrict__ cup, const int32_t* __restrict__ ccol, double* __restrict__ acc,
     uint8_t* __restrict__ mark, int64_t* __restrict__ count, double* __restrict__ g) {
-  __shared__ double sp[kStrWaves][DIM][kStrChunk];
-  __shared__ int32_t sidx[kStrWaves][kStrChunk];
-  __shared__ T sphi[kStrWaves][kStrChunk];
-  __shared__ double red[kStrWaves][kStrCols];
+  // the grouped path stages half as many points (its LDS holds the pass's
+  // candidates and accumulators too)
+  constexpr int kChunk = GROUPED ? kStrChunk / 2 : kStrChunk;
+  __shared__ double sp[kStrWaves][DIM][kChunk];
+  __shared__ int32_t sidx[kStrWaves][kChunk];
+  __shared__ T sphi[kStrWaves][kChunk];
+  __shared__ double red[GROUPED ? 1 : kStrWaves][GROUPED ? 1 : kStrCols];
   __shared__ uint8_t hit_s[kStrWaves][kStrCols];
   __shared__ double gred[kStrWaves];
   __shared__ int32_t nred[kStrWaves];
+  __shared__ double cxs[GROUPED ? DIM : 1][GROUPED ? kStrCols : 1];
+  __shared__ double crs[GROUPED ? kStrCols : 1], cr2s[GROUPED ? kStrCols : 1],
+      cirs[GROUPED ? kStrCols : 1];
+  __shared__ AccPod<T> cacc[GROUPED ? kStrWaves : 1][GROUPED ? kStrCols : 1];
+  __shared__ int16_t nlist[GROUPED ? kStrWaves : 1][GROUPED ? kStrCols : 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
+  const uint64_t lt = lanemask_lt();
   double xj[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) xj[d] = P.ctr[d * P.m + j];
   const double r2j = P.rho2[j], irj = P.irho[j];
   const int64_t e0 = cup[j], e1 = cptr[j + 1];
-  const int64_t R = e1 - e0;
-  SAcc<T> gacc;
+  const int64_t R = e1 - e0;  // >= 1: j is its own candidate
+  Acc<T> gacc;
   int npts = 0;
   for (int64_t cb = 0; cb < R; cb += kStrCols) {
     const bool first = cb == 0;
-    double xl[kStrSlots][DIM];
-    double r2l[kStrSlots], irl[kStrSlots];
-    bool ok[kStrSlots], hit[kStrSlots];
-    SAcc<T> a[kStrSlots];
+    const int ncol = (int)(R - cb < kStrCols ? R - cb : kStrCols);
+    double xl[GROUPED ? 1 : kStrSlots][DIM];
+    double r2l[GROUPED ? 1 : kStrSlots], irl[GROUPED ? 1 : kStrSlots];
+    bool hit[GROUPED ? 1 : kStrSlots];
+    Acc<T> a[GROUPED ? 1 : kStrSlots];
+    if constexpr (!GROUPED) {
 #pragma unroll
-    for (int t = 0; t < kStrSlots; ++t) {
-      const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
-      ok[t] = e < e1;
-      hit[t] = false;
-      const int32_t l = ok[t] ? ccol[e] : 0;
+      for (int t = 0; t < kStrSlots; ++t) {
+        const int c = lane + kWave * t;
+        const bool ok = c < ncol;
+        hit[t] = false;
+        const int32_t l = ok ? ccol[e0 + cb + c] : 0;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) xl[t][d] = ok[t] ? P.ctr[d * P.m + l] : 0.0;
-      r2l[t] = ok[t] ? P.rho2[l] : 0.0;
-      irl[t] = ok[t] ? P.irho[l] : 0.0;
+        for (int d = 0; d < DIM; ++d) xl[t][d] = ok ? P.ctr[d * P.m + l] : 0.0;
+        r2l[t] = ok ? P.rho2[l] : 0.0;  // 0: no point tests inside
+        irl[t] = ok ? P.irho[l] : 0.0;
+      }
+    } else {
+      for (int t = threadIdx.x; t < ncol; t += kWave * kStrWaves) {
+        const int32_t l = ccol[e0 + cb + t];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) cxs[d][t] = P.ctr[d * P.m + l];
+        crs[t] = P.rho[l];
+        cr2s[t] = P.rho2[l];
+        cirs[t] = P.irho[l];
+      }
+      for (int t = lane; t < ncol; t += kWave) {
+        cacc[w][t] = AccPod<T>{(T)0, (T)0};
+        hit_s[w][t] = 0;
+      }
+      __syncthreads();
     }
     T* wphi = sphi[w];
     const int32_t* widx = sidx[w];
-    double(*wsp)[kStrChunk] = sp[w];
-    stream_support_part<DIM, kStrChunk>(P, xj, r2j, w, kStrWaves, wsp, sidx[w], [&](int np) {
+    double(*wsp)[kChunk] = sp[w];
+    stream_support_part<DIM, kChunk>(P, xj, r2j, w, kStrWaves, wsp, sidx[w], [&](int np) {
       for (int q = lane; q < np; q += kWave) {
         double p[DIM];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
-        const T phij = wendland<PHI, T>(str_r<T>(sqdist<DIM>(p, xj), irj));
+        const T phij = wendland<PHI, T>(scaled_r<T>(sqdist<DIM>(p, xj), irj));
         wphi[q] = phij;
         if (first) gacc.add(phij * (T)hs[widx[q]]);
       }
       if (first) npts += np;
       wave_sync();
-      for (int q = 0; q < np; ++q) {
-        double p[DIM];
+      if constexpr (!GROUPED) {
+        for (int q = 0; q < np; ++q) {
+          double p[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
-        const T phij = wphi[q];
+          for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+          const T phij = wphi[q];
 #pragma unroll
-        for (int t = 0; t < kStrSlots; ++t) {
-          if (ok[t]) {
+          for (int t = 0; t < kStrSlots; ++t) {
             const double s = sqdist<DIM>(p, xl[t]);
             if (s < r2l[t]) {
-              a[t].add(phij * wendland<PHI, T>(str_r<T>(s, irl[t])));
+              a[t].add(phij * wendland<PHI, T>(scaled_r<T>(s, irl[t])));
               hit[t] = true;
             }
           }
         }
+      } else {
+        for (int g0 = 0; g0 < np; g0 += kWave) {
+          const int n = np - g0 < kWave ? np - g0 : kWave;
+          // bounding ball of the group: centre its first point, radius the
+          // farthest of its points (rounded up)
+          double c0[DIM];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) c0[d] = wsp[d][g0];
+          float rg = 0.f;
+          if (lane < n) {
+            double p[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) p[d] = wsp[d][g0 + lane];
+            rg = (float)__builtin_sqrt(sqdist<DIM>(p, c0)) * 1.0001f + 1e-30f;
+          }
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) rg = fmaxf(rg, __shfl_xor(rg, off, kWave));
+          // the candidates whose support can reach the group
+          int nn = 0;
+          for (int t0 = 0; t0 < ncol; t0 += kWave) {
+            const int t = t0 + lane;
+            bool need = false;
+            if (t < ncol) {
+              double xc[DIM];
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) xc[d] = cxs[d][t];
+              const double reach = (crs[t] + (double)rg) * (1.0 + 1e-9);
+              need = sqdist<DIM>(xc, c0) < reach * reach;
+            }
+            const uint64_t msk = __ballot(need);
+            if (need) nlist[w][nn + __popcll(msk & lt)] = (int16_t)t;
+            nn += __popcll(msk);
+          }
+          wave_sync();
+          for (int k0 = 0; k0 < nn; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < nn) {
+              const int t = nlist[w][k];
+              double xc[DIM];
+#pragma unroll
+              for (int d = 0; d < DIM; ++d) xc[d] = cxs[d][t];
+              const double r2t = cr2s[t], irt = cirs[t];
+              Acc<T> at = from_pod(cacc[w][t]);
+              bool h = false;
+              for (int q = g0; q < g0 + n; ++q) {
+                double p[DIM];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
+                const double s = sqdist<DIM>(p, xc);
+                if (s < r2t) {
+                  at.add(wphi[q] * wendland<PHI, T>(scaled_r<T>(s, irt)));
+                  h = true;
+                }
+              }
+              cacc[w][t] = to_pod(at);
+              if (h) hit_s[w][t] = 1;
+            }
+          }
+          wave_sync();
+        }
       }
     });
     // the waves' partial sums, added in wave order
+    if constexpr (!GROUPED) {
 #pragma unroll
-    for (int t = 0; t < kStrSlots; ++t) {
-      red[w][lane + kWave * t] = a[t].value();
-      hit_s[w][lane + kWave * t] = hit[t] ? 1 : 0;
+      for (int t = 0; t < kStrSlots; ++t) {
+        red[w][lane + kWave * t] = partial_value<T>(a[t]);
+        hit_s[w][lane + kWave * t] = hit[t] ? 1 : 0;
+      }
     }
     __syncthreads();
     if (w == 0) {
 #pragma unroll
       for (int t = 0; t < kStrSlots; ++t) {
-        if (!ok[t]) continue;
+        const int c = lane + kWave * t;
+        if (c >= ncol) continue;
         double sum = 0.0;
         int h = 0;
 #pragma unroll
         for (int u = 0; u < kStrWaves; ++u) {
-          sum += red[u][lane + kWave * t];
-          h |= hit_s[u][lane + kWave * t];
+          if constexpr (GROUPED)
+            sum += partial_value<T>(from_pod(cacc[u][c]));
+          else
+            sum += red[u][c];
+          h |= hit_s[u][c];
         }
         if (h) {
-          const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
+          const int64_t e = e0 + cb + c;
           acc[e] += sum;
           mark[e] = 1;
         }
@@ -264,20 +337,7 @@ __global__ __launch_bounds__(kWave* kStrWaves) void k_stream_accum(
     }
     __syncthreads();
   }
-  if (R == 0) {
-    // no upper candidate (cannot happen: j is its own): count and g alone
-    stream_support_part<DIM, kStrChunk>(P, xj, r2j, w, kStrWaves, sp[w], sidx[w], [&](int np) {
-      for (int q = lane; q < np; q += kWave) {
-        double p[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q];
-        const T phij = wendland<PHI, T>(str_r<T>(sqdist<DIM>(p, xj), irj));
-        gacc.add(phij * (T)hs[sidx[w][q]]);
-      }
-      npts += np;
-    });
-  }
-  const double gl = wave_sum(gacc.value());
+  const double gl = wave_sum(partial_value<T>(gacc));
   if (lane == 0) {
     gred[w] = gl;
     nred[w] = npts;
@@ -434,23 +494,28 @@ __global__ void k_stream_values(const int64_t* __restrict__ row_ptr,
 }
 
 template <int DIM, int PHI, typename T>
-hipError_t accum_launch(const PlanView& P, const double* hs, const int64_t* cptr,
+hipError_t accum_launch(bool grouped, const PlanView& P, const double* hs, const int64_t* cptr,
                         const int64_t* cup, const int32_t* ccol, double* acc, uint8_t* mark,
                         int64_t* count, double* g, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream_accum<DIM, PHI, T>), dim3((unsigned)P.m), dim3(kWave * kStrWaves),
-                     0, s, P, hs, cptr, cup, ccol, acc, mark, count, g);
+  const dim3 grid((unsigned)P.m), block(kWave * kStrWaves);
+  if (grouped)
+    hipLaunchKernelGGL((k_stream_accum<DIM, PHI, T, true>), grid, block, 0, s, P, hs, cptr, cup,
+                       ccol, acc, mark, count, g);
+  else
+    hipLaunchKernelGGL((k_stream_accum<DIM, PHI, T, false>), grid, block, 0, s, P, hs, cptr, cup,
+                       ccol, acc, mark, count, g);
   return hipGetLastError();
 }
 
 template <int DIM, typename T>
-hipError_t accum_phi(int phi, const PlanView& P, const double* hs, const int64_t* cptr,
+hipError_t accum_phi(int phi, bool gr, const PlanView& P, const double* hs, const int64_t* cptr,
                      const int64_t* cup, const int32_t* ccol, double* acc, uint8_t* mark,
                      int64_t* count, double* g, hipStream_t s) {
   switch (phi) {
-    case 0: return accum_launch<DIM, 0, T>(P, hs, cptr, cup, ccol, acc, mark, count, g, s);
-    case 1: return accum_launch<DIM, 1, T>(P, hs, cptr, cup, ccol, acc, mark, count, g, s);
-    case 2: return accum_launch<DIM, 2, T>(P, hs, cptr, cup, ccol, acc, mark, count, g, s);
-    default: return accum_launch<DIM, 3, T>(P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+    case 0: return accum_launch<DIM, 0, T>(gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+    case 1: return accum_launch<DIM, 1, T>(gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+    case 2: return accum_launch<DIM, 2, T>(gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+    default: return accum_launch<DIM, 3, T>(gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
   }
 }
 
@@ -491,16 +556,17 @@ hipError_t launch_stream_inbox(const int32_t* sentinel_start, int64_t* inbox, hi
   return hipGetLastError();
 }
 
-hipError_t launch_stream_accum(const PlanView& P, int phi, bool fp32, const double* hs,
-                               const int64_t* cptr, const int64_t* cup, const int32_t* ccol,
-                               double* acc, uint8_t* mark, int64_t* count, double* g,
-                               hipStream_t s) {
+hipError_t launch_stream_accum(const PlanView& P, int phi, bool fp32, bool grouped,
+                               const double* hs, const int64_t* cptr, const int64_t* cup,
+                               const int32_t* ccol, double* acc, uint8_t* mark, int64_t* count,
+                               double* g, hipStream_t s) {
   if (P.m <= 0 || P.n <= 0) return hipSuccess;
+  const bool gr = grouped;
   if (P.dim == 2)
-    return fp32 ? accum_phi<2, float>(phi, P, hs, cptr, cup, ccol, acc, mark, count, g, s)
-                : accum_phi<2, double>(phi, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
-  return fp32 ? accum_phi<3, float>(phi, P, hs, cptr, cup, ccol, acc, mark, count, g, s)
-              : accum_phi<3, double>(phi, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+    return fp32 ? accum_phi<2, float>(phi, gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s)
+                : accum_phi<2, double>(phi, gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
+  return fp32 ? accum_phi<3, float>(phi, gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s)
+              : accum_phi<3, double>(phi, gr, P, hs, cptr, cup, ccol, acc, mark, count, g, s);
 }
 
 hipError_t launch_stream_active(const int64_t* count, int64_t m, int32_t min_support,
