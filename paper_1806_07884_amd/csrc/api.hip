@@ -359,8 +359,32 @@ struct rbf_plan {
 
 namespace {
 
-// Grid hash of `count` points: sorted by cell (with sub_order, by sub-cell
-// within a cell as well), sorted copy, permutation and cell starts.
+// Grid hash of `count` points into caller workspace (keys/values twice
+// `count`, radix temporaries of radix_temp_bytes(count) bytes): sorted by
+// cell (with sub_order, by sub-cell within a cell as well), sorted copy,
+// permutation and cell starts.  Stream-ordered.
+int hash_core(rbf_plan* P, const double* coords, int64_t count, uint32_t* ka, uint32_t* kb,
+              int32_t* va, int32_t* vb, void* tmp, double* sorted, int32_t* perm,
+              int32_t* cell_start, bool sub_order) {
+  hipStream_t s = P->stream;
+  // sub-cell bits below the cell id while the shifted ids still fit 32 bits
+  int sub = sub_order ? 2 * P->dim : 0;
+  if ((((int64_t)P->grid.ncell + 1) << sub) > (int64_t)UINT32_MAX) sub = 0;
+  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, sub, ka, va, s));
+  int bits = 1;
+  while ((int64_t(1) << bits) <= ((int64_t)P->grid.ncell << sub) + ((int64_t(1) << sub) - 1)) ++bits;
+  bool in_alt = false;
+  HIPCHK(rbf::radix_sort_pairs(ka, va, kb, vb, count, bits, tmp, s, &in_alt));
+  const uint32_t* keys = in_alt ? kb : ka;
+  const int32_t* vals = in_alt ? vb : va;
+  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, sub, cell_start, s));
+  HIPCHK(hipMemcpyAsync(perm, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIPCHK(rbf::launch_gather_soa(coords, perm, count, P->dim, sorted, s));
+  return RBF_OK;
+}
+
+// hash_core with temporaries taken from the allocator and given back once
+// the stream has consumed them (synchronises the stream).
 int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, int32_t* perm,
               int32_t* cell_start, bool sub_order) {
   uint32_t *ka, *kb;
@@ -370,21 +394,9 @@ int hash_into(rbf_plan* P, const double* coords, int64_t count, double* sorted, 
   if (!P->get(&ka, count) || !P->get(&kb, count) || !P->get(&va, count) || !P->get(&vb, count) ||
       !(tmp = P->alloc_bytes(tb)))
     return fail(RBF_ERR_OOM, "hash workspace allocation failed");
-  // sub-cell bits below the cell id while the shifted ids still fit 32 bits
-  int sub = sub_order ? 2 * P->dim : 0;
-  if ((((int64_t)P->grid.ncell + 1) << sub) > (int64_t)UINT32_MAX) sub = 0;
-  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, sub, ka, va, P->stream));
-  int bits = 1;
-  while ((int64_t(1) << bits) <= ((int64_t)P->grid.ncell << sub) + ((int64_t(1) << sub) - 1)) ++bits;
-  bool in_alt = false;
-  HIPCHK(rbf::radix_sort_pairs(ka, va, kb, vb, count, bits, tmp, P->stream, &in_alt));
-  const uint32_t* keys = in_alt ? kb : ka;
-  const int32_t* vals = in_alt ? vb : va;
-  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, sub, cell_start, P->stream));
-  HIPCHK(hipMemcpyAsync(perm, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                        P->stream));
-  HIPCHK(rbf::launch_gather_soa(coords, perm, count, P->dim, sorted, P->stream));
-  // the temporaries go back once the stream has consumed them
+  const int rc = hash_core(P, coords, count, ka, kb, va, vb, tmp, sorted, perm, cell_start,
+                           sub_order);
+  if (rc) return rc;
   HIPCHK(hipStreamSynchronize(P->stream));
   P->release(tmp);
   P->release(vb);
@@ -722,32 +734,14 @@ int ensure_staging(rbf_plan* P) {
   return RBF_OK;
 }
 
-// Grid hash of one chunk into the chunk workspace (as hash_into, without the
-// host synchronisation: the workspace lives as long as the plan).
-int hash_chunk(rbf_plan* P, const double* coords, int64_t count) {
-  hipStream_t s = P->stream;
-  int sub = 2 * P->dim;
-  if ((((int64_t)P->grid.ncell + 1) << sub) > (int64_t)UINT32_MAX) sub = 0;
-  HIPCHK(rbf::launch_cell_keys(P->dim, P->grid, coords, count, sub, P->ckey[0], P->cval[0], s));
-  int bits = 1;
-  while ((int64_t(1) << bits) <= ((int64_t)P->grid.ncell << sub) + ((int64_t(1) << sub) - 1)) ++bits;
-  bool in_alt = false;
-  HIPCHK(rbf::radix_sort_pairs(P->ckey[0], P->cval[0], P->ckey[1], P->cval[1], count, bits,
-                               P->crtmp, s, &in_alt));
-  const uint32_t* keys = in_alt ? P->ckey[1] : P->ckey[0];
-  const int32_t* vals = in_alt ? P->cval[1] : P->cval[0];
-  HIPCHK(rbf::cell_starts(keys, count, P->grid.ncell, sub, P->cpcs, s));
-  HIPCHK(hipMemcpyAsync(P->cpp, vals, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  HIPCHK(rbf::launch_gather_soa(coords, P->cpp, count, P->dim, P->cps, s));
-  return RBF_OK;
-}
-
 // One chunk (device SoA coordinates x [dim][n], values h [n]) into the
 // accumulators, on the plan's stream.
 int stream_chunk(rbf_plan* P, int64_t n, const double* x, const double* h) {
   hipStream_t s = P->stream;
   HIPCHK(rbf::launch_chunk_check(x, h, n, P->dim, P->sbad, s));
-  int rc = hash_chunk(P, x, n);
+  // the chunk's hash, into the plan's chunk workspace (no synchronisation)
+  int rc = hash_core(P, x, n, P->ckey[0], P->ckey[1], P->cval[0], P->cval[1], P->crtmp, P->cps,
+                     P->cpp, P->cpcs, true);
   if (rc) return rc;
   HIPCHK(rbf::launch_stream_inbox(P->cpcs + P->grid.ncell, P->sinbox, s));
   HIPCHK(rbf::launch_gather(h, P->cpp, n, P->chs, s));
