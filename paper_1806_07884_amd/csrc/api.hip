@@ -14,6 +14,7 @@
 #include "mlp_kernels.h"
 #include "plan_kernels.h"
 #include "rbf.h"
+#include "chunk_planner.h"
 #include "solver.h"
 #include "stream.h"
 
@@ -44,6 +45,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int64_t kMaxCells = int64_t(1) << 26;
+static_assert(rbf::kPlanMaxRhs == rbf::kMaxRhs, "the chunk planner tracks every right-hand side");
 
 }  // namespace
 
@@ -949,72 +951,11 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   return RBF_OK;
 }
 
-// Sizes of the chunks of CG launches queued between host checks.  A launch
-// queued past a raised flag (reliable update, convergence) returns at entry
-// but still costs a few us, and the chunk after the one that raises the flag
-// is always queued too.  So chunks shrink as the flag nears: the decay of
-// ||r||^2 between the last two snapshots gives the iterations left to the
-// trigger (the soonest over the right-hand sides still iterating), and a
-// chunk takes half of what remains past the chunk still in flight, between
-// 4 launches and check_every.  Without a decay to go by (after a refresh,
-// which may have converged, or when ||r|| grew) chunks start small and double.
-struct ChunkPlanner {
-  int64_t cmin, cmax, ramp;
-  int nr = 0;
-  double rr0[rbf::kMaxRhs], rr1[rbf::kMaxRhs], trig[rbf::kMaxRhs];
-  bool on[rbf::kMaxRhs];
-  int64_t it0 = -1, it1 = -1;
-
-  explicit ChunkPlanner(int64_t check_every)
-      : cmin(std::min<int64_t>(4, check_every)), cmax(check_every), ramp(cmin) {}
-  void restart() {
-    it0 = it1 = -1;
-    ramp = cmin;
-  }
-  // a snapshot after `iter` iterations: ||r||^2, trigger and activity per
-  // right-hand side
-  void seen(int64_t iter, int n, const double* rr, const double* trigger2, const int32_t* active) {
-    nr = n;
-    it0 = it1;
-    it1 = iter;
-    for (int k = 0; k < n; ++k) {
-      rr0[k] = rr1[k];
-      rr1[k] = rr[k];
-      trig[k] = trigger2[k];
-      on[k] = active == nullptr || active[k] != 0;
-    }
-  }
-  int64_t next(int64_t inflight) {
-    double left = -1.0;
-    if (it0 >= 0 && it1 > it0) {
-      for (int k = 0; k < nr; ++k) {
-        if (!on[k]) continue;
-        if (!(rr0[k] > 0.0 && rr1[k] > 0.0 && rr1[k] < rr0[k] && trig[k] > 0.0)) {
-          left = -1.0;  // a right-hand side without a decay: no estimate
-          break;
-        }
-        const double rate = std::log(rr1[k] / rr0[k]) / (double)(it1 - it0);
-        const double lk = rr1[k] > trig[k] ? std::log(trig[k] / rr1[k]) / rate : 0.0;
-        if (left < 0.0 || lk < left) left = lk;
-      }
-    }
-    if (left < 0.0) {
-      const int64_t n = ramp;
-      ramp = std::min(cmax, 2 * ramp);
-      return n;
-    }
-    const double want = 0.5 * left - (double)inflight;
-    const int64_t n = want <= (double)cmin ? cmin : (want >= (double)cmax ? cmax : (int64_t)want);
-    ramp = n;
-    return n;
-  }
-};
-
 // Reliable-update Jacobi-PCG (see cg_kernels.hip).  Returns a status; the
 // float64 solution is left in P->xhi.
 //
 // Iterations are launched in chunks of at most check_every (sized by
-// ChunkPlanner), each followed by a copy of the scalars into one of two
+// rbf::ChunkPlanner), each followed by a copy of the scalars into one of two
 // pinned slots and an event.  The next chunk is always queued before the host
 // waits on the previous one, so the GPU never idles on a convergence check;
 // launches after a raised flag return at entry.  Launches never exceed the
@@ -1037,7 +978,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   double last_true = -1.0;
   int stalls = 0;
 
-  ChunkPlanner plan(o.check_every);
+  rbf::ChunkPlanner plan(o.check_every);
   int64_t slot_len[2] = {0, 0};
   // queue one chunk and its snapshot into slot `slot` (the other slot's
   // chunk, if queued, is still unobserved); false if none is left
@@ -1173,7 +1114,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   int64_t refreshes = 1, launched = 0;
   const int64_t budget = o.max_iter;
   bool fixed = true;
-  ChunkPlanner plan(o.check_every);
+  rbf::ChunkPlanner plan(o.check_every);
   int64_t slot_len[2] = {0, 0};
   // queue one chunk and its snapshot into slot `slot`
   auto enqueue = [&](int slot, bool* queued) -> int {
