@@ -23,9 +23,9 @@ namespace {
 thread_local std::string g_last_error;
 
 // With timing on, one CG iteration launch in kProfPeriod carries start/stop
-// events.  Each stamped launch costs a few microseconds of extra gap on the
-// stream, so the sample is kept sparse (a terrain2d fit still times ~300).
-constexpr int64_t kProfPeriod = 16;
+// events.  Each stamped launch costs about 6 us of extra gap on the stream,
+// so the sample is kept sparse (a terrain2d fit still times ~160).
+constexpr int64_t kProfPeriod = 32;
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
