@@ -170,3 +170,43 @@ def test_big_matched_rmse(case):
     if len(case.rmse) < 2:
         pytest.skip("needs both precisions")
     assert abs(case.rmse["fp32"] - case.rmse["fp64"]) <= 1e-3 * case.rmse["fp64"]
+
+
+@pytest.mark.timeout(900)
+def test_big_stream_equals_resident(case, rbf):
+    # the same points streamed in 8 chunks (rbf_stream_*, float32): pattern
+    # and support counts equal to the resident plan's, sampled values and g_j
+    # within the float32 bars of the oracle's rows, the same RMSE
+    p = case.prob
+    n = p.points.shape[1]
+    bounds = np.linspace(0, n, 9).astype(np.int64)
+    say(case.name, "stream in 8 chunks")
+    st = rbf.rbf_stream_begin(case.dc, int(np.max(np.diff(bounds))), rho=p.rho, phi=p.phi,
+                              prec="fp32", lambda_rel=LAM)
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        rbf.rbf_stream_add(st, dev(p.points[:, a:b]), dev(p.values[a:b]))
+    rbf.rbf_stream_finish(st)
+    rp, col, sup = rbf.rbf_plan_pattern(st)
+    rp0, col0, sup0 = rbf.rbf_plan_pattern(case.plan)
+    assert np.array_equal(rp, rp0) and np.array_equal(col, col0) and np.array_equal(sup, sup0)
+    val, g, lam = rbf.rbf_system_export(st)
+    phi0sq = float(orc.wendland(p.phi, np.array([0.0]))[0]) ** 2
+    a_tol, n_tol = 1e-5, 3e-6
+    for j in case.rows(4, 2):
+        row = orc.sample_row(p.points, p.values, p.centers, p.rho, p.phi, j)
+        if row.support.size == 0:
+            continue
+        got = val[rp[j]:rp[j + 1]]
+        ref = row.vals.copy()
+        ref[0] += lam
+        tol = a_tol * ref + n_tol * phi0sq * row.pair_count + 1e-12 * lam
+        assert np.all(np.abs(got - ref) <= tol), (j, float(np.max(np.abs(got - ref) / tol)))
+        hsum = np.sum(np.abs(p.values[row.support]))
+        assert abs(g[j] - row.g) <= (a_tol + n_tol) * np.sqrt(phi0sq) * hsum
+    c, info = rbf.rbf_solve(st, rtol=RTOL, max_iter=200000)
+    assert info["status"] == 0
+    _, rmse = rbf.rbf_eval(st, dev(case.q), c, values=dev(case.qh))
+    say(case.name, "streamed rmse", rmse, "resident", case.rmse.get("fp32"))
+    if "fp32" in case.rmse:
+        assert abs(rmse - case.rmse["fp32"]) <= 1e-3 * case.rmse["fp32"]
+    st.close()
