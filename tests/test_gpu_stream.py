@@ -203,6 +203,15 @@ def test_stream_deterministic_and_order(rbf):
     va, ga, la = rbf.rbf_system_export(a)
     vb, gb, lb = rbf.rbf_system_export(b)
     assert np.array_equal(va, vb) and np.array_equal(ga, gb) and la == lb
+    # host chunks in pageable memory (a synchronous copy): the same bits
+    c = rbf.rbf_stream_begin(dev(ctr), max(b1 - a1 for a1, b1 in parts), rho=rho, phi="w31",
+                             prec="fp32", lambda_rel=1e-5)
+    for a1, b1 in parts:
+        rbf.rbf_stream_add(c, torch.from_numpy(np.ascontiguousarray(pts[:, a1:b1])),
+                           torch.from_numpy(np.ascontiguousarray(h[a1:b1])))
+    rbf.rbf_stream_finish(c)
+    vc, gc, lc = rbf.rbf_system_export(c)
+    assert np.array_equal(va, vc) and np.array_equal(ga, gc) and la == lc
     rev = stream(rbf, pts, h, ctr, rho, "w31", "fp64", parts[::-1], on_host=False)
     fwd = stream(rbf, pts, h, ctr, rho, "w31", "fp64", parts, on_host=False)
     assert np.array_equal(rbf.rbf_plan_pattern(rev)[1], rbf.rbf_plan_pattern(fwd)[1])
