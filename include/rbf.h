@@ -210,10 +210,10 @@ int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, do
  * ||.|| and ||g|| of the stopping test cover the whole bordered system.  opts NULL: rtol 1e-10,
  * max_iter 100000, check_every 32, reliable_delta 0.1.  Iterations are queued
  * in chunks of at most check_every, shorter as the residual nears the next
- * reliable-update trigger (sized from its decay), each followed by a copy of
- * the residual to host memory; the host waits on a chunk's copy only after
- * the next chunk is queued, so launches queued past a trigger or convergence
- * return at entry.  Returns OK, WARN_MAXITER
+ * reliable-update trigger (sized from its decay); the last launch of a chunk
+ * writes the residual and flags into pinned host memory, and the host waits
+ * on a chunk only after the next chunk is queued, so launches queued past a
+ * trigger or convergence return at entry.  Returns OK, WARN_MAXITER
  * (best iterate kept), WARN_FALLBACK (mixed precision stalled and FP64 took
  * over), ERR_BREAKDOWN, ERR_INVALID (not assembled), ERR_HIP.  info may be
  * NULL. */

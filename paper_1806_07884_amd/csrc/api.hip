@@ -65,7 +65,9 @@ rbf::CgScalars* pinned_acquire() {
     }
   }
   void* p = nullptr;
-  if (hipHostMalloc(&p, 2 * sizeof(rbf::CgScalars), hipHostMallocDefault) != hipSuccess) {
+  // mapped and coherent: the CG kernel that ends a chunk writes its slot
+  if (hipHostMalloc(&p, 2 * sizeof(rbf::CgScalars), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
@@ -179,6 +181,7 @@ struct rbf_plan {
   double* cs_sorted = nullptr;
   double* eval_part = nullptr;
   rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots (from the pinned pool)
+  rbf::CgScalars* host_sc_dev = nullptr;  // their device address
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
 
   // chunked assembly (rbf_stream_*): 0 = not a stream plan, 1 = taking
@@ -846,6 +849,7 @@ rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   a.xhi = P->xhi;
   a.r64 = P->r64;
   a.sc = P->sc;
+  a.snap = nullptr;
   a.part[0] = P->part_it;
   a.part[1] = P->part_it + rbf::kCgParts * rbf::kCgMaxBlocks;
   a.part_ref = P->part_ref;
@@ -882,6 +886,7 @@ int ensure_solver(rbf_plan* P, bool fp32) {
   if (!P->host_sc) {
     P->host_sc = pinned_acquire();
     if (!P->host_sc) return fail(RBF_ERR_OOM, "pinned host allocation failed");
+    HIPCHK(hipHostGetDevicePointer((void**)&P->host_sc_dev, P->host_sc, 0));
   }
   for (hipEvent_t& e : P->snap_ev)
     if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -955,8 +960,8 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
 // float64 solution is left in P->xhi.
 //
 // Iterations are launched in chunks of at most check_every (sized by
-// rbf::ChunkPlanner), each followed by a copy of the scalars into one of two
-// pinned slots and an event.  The next chunk is always queued before the host
+// rbf::ChunkPlanner); the last launch of a chunk writes the scalars into one
+// of two pinned host slots, and an event follows it.  The next chunk is always queued before the host
 // waits on the previous one, so the GPU never idles on a convergence check;
 // launches after a raised flag return at entry.  Launches never exceed the
 // iteration budget.
@@ -999,13 +1004,14 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
         e1 = P->event();
         if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
       }
+      // the chunk's last launch writes the scalars into the host slot
+      a.snap = it == chunk - 1 ? P->host_sc_dev + slot : nullptr;
       HIPCHK(rbf::cg_iterate<VT, XT>(a, A, q, fixed ? 1 : 0, e0, e1, s));
       if (timed) P->pending.push_back({0, base_iter + launched, e0, e1});
       fixed = false;
       ++launched;
     }
-    HIPCHK(hipMemcpyAsync(P->host_sc + slot, P->sc, sizeof(rbf::CgScalars),
-                          hipMemcpyDeviceToHost, s));
+    a.snap = nullptr;
     HIPCHK(hipEventRecord(P->snap_ev[slot], s));
     *queued = true;
     return RBF_OK;

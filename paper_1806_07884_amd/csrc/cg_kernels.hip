@@ -67,6 +67,14 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int xg) {
   return (g * kXcds + x) * C + j;
 }
 
+// The scalars as this launch leaves them, copied into the host's snapshot
+// slot when the launch ends a chunk (block 0, thread 0, after its own
+// updates; the slot is pinned coherent host memory, read by the host once the
+// chunk's event has completed).
+__device__ __forceinline__ void snapshot(const CgScalars* sc, CgScalars* snap) {
+  if (snap) *snap = *sc;
+}
+
 // s_i = w_i + beta s_{i-1} and r_{i+1} = r_i - alpha s_i, rounded step by step
 // so that a row's own update and every neighbour's on-the-fly copy of it are
 // the same numbers.
@@ -315,7 +323,7 @@ __device__ __forceinline__ void poly_store(const PolySys& S, int np, const doubl
 template <typename VT, typename XT, typename CT, int L, int BS, bool POLY, bool HALO = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1))) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
-    XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc,
+    XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc, CgScalars* snap,
     const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int xg, int q,
     int fixed, int np, const XT* __restrict__ Q, const PolySys* __restrict__ psys,
     const PolyState* __restrict__ pin, PolyState* __restrict__ pout) {
@@ -411,7 +419,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   }
   if (threadIdx.x == 0) s_flag = sc->done;
   __syncthreads();
-  if (s_flag) return;
+  if (s_flag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) snapshot(sc, snap);
+    return;
+  }
   for (int t = 0; t < NP; ++t) {
     double v = 0.0;
 #pragma unroll 4
@@ -453,18 +464,25 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
     alpha_d = gamma / (red[1] + beta_d * (red[3] + red[4]) + beta_d * beta_d * red[5]);
   }
   if (!__builtin_isfinite(rr) || !__builtin_isfinite(gamma)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 2;
+      snapshot(sc, snap);
+    }
     return;
   }
   if (rr <= trigger2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->rr = rr;
       sc->done = 1;
+      snapshot(sc, snap);
     }
     return;
   }
   if (!(alpha_d > 0.0) || !__builtin_isfinite(alpha_d) || !__builtin_isfinite(beta_d)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 2;
+      snapshot(sc, snap);
+    }
     return;
   }
   const XT alpha = (XT)alpha_d, beta = (XT)beta_d;
@@ -604,6 +622,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
       sc->alp[q] = alpha_d;
       sc->rr = rr;
       sc->iter += 1;
+      snapshot(sc, snap);
     }
   }
 }
@@ -916,12 +935,12 @@ void launch_iter_p(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hip
     // the extended launch stamps the events at the kernel's own start and end
     hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
                           dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p,
-                          a.xlo, a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
+                          a.xlo, a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
                           q, fixed, a.np, a.Q, a.psys, pin, pout);
   } else {
     hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
                        dim3(BS), 0, s, a.m,
-                       A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed, a.np,
                        a.Q, a.psys, pin, pout);
   }
@@ -984,12 +1003,12 @@ void launch_iter_halo(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, 
   if (e0) {
     hipExtLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks),
                           dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q],
-                          a.st[q ^ 1], a.p, a.xlo, a.sc, (const double*)a.part[q ^ 1], a.part[q],
+                          a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q],
                           a.blocks, a.xg, q, fixed, 0, (const XT*)nullptr,
                           (const PolySys*)nullptr, (const PolyState*)nullptr, (PolyState*)nullptr);
   } else {
     hipLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks), dim3(BS),
-                       0, s, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       0, s, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed, 0,
                        (const XT*)nullptr, (const PolySys*)nullptr, (const PolyState*)nullptr,
                        (PolyState*)nullptr);

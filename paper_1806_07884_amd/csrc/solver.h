@@ -90,6 +90,9 @@ struct CgArgs {
   double* xhi;         // float64 solution
   double* r64;         // float64 true residual
   CgScalars* sc;
+  // host snapshot slot (device address of pinned, coherent host memory) that
+  // the launch copies the scalars into when it ends a chunk; NULL otherwise
+  CgScalars* snap;
   double* part[2];     // [kCgParts * blocks] partials of an iteration, by state buffer
   double* part_ref;    // [kCgParts * blocks] partials of a refresh
   int blocks;          // grid of every slice kernel
