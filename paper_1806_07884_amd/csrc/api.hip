@@ -176,6 +176,7 @@ struct rbf_plan {
   double* bpart_ref = nullptr;
   rbf::CgScalarsN* bsc = nullptr;
   rbf::CgScalarsN* host_bsc = nullptr;  // pinned, two snapshot slots
+  rbf::CgScalarsN* host_bsc_dev = nullptr;  // their device address
   void* vec64[4] = {};         // state buffers 0 and 1 (4 per row), p, x_lo
   void* vec32[4] = {};
   double* cs_sorted = nullptr;
@@ -1107,6 +1108,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   a.xhi = P->bxhi;
   a.r64 = P->br64;
   a.sc = P->bsc;
+  a.snap = nullptr;
   a.part[0] = P->bpart_it;
   a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
   a.part_ref = P->bpart_ref;
@@ -1139,13 +1141,14 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
         e1 = P->event();
         if (!e0 || !e1) return fail(RBF_ERR_HIP, "hipEventCreate failed");
       }
+      // the chunk's last launch writes the scalars into the host slot
+      a.snap = it == chunk - 1 ? P->host_bsc_dev + slot : nullptr;
       HIPCHK(rbf::cgn_iterate<VT, XT>(a, A, q, fixed ? 1 : 0, e0, e1, s));
       if (timed) P->pending.push_back({1, launched, e0, e1});
       fixed = false;
       ++launched;
     }
-    HIPCHK(hipMemcpyAsync(P->host_bsc + slot, P->bsc, sizeof(rbf::CgScalarsN),
-                          hipMemcpyDeviceToHost, s));
+    a.snap = nullptr;
     HIPCHK(hipEventRecord(P->snap_ev[slot], s));
     *queued = true;
     return RBF_OK;
@@ -1237,11 +1240,14 @@ int ensure_batch(rbf_plan* P, bool fp32) {
   }
   if (!P->host_bsc) {
     void* h = nullptr;
-    if (hipHostMalloc(&h, 2 * sizeof(rbf::CgScalarsN), hipHostMallocDefault) != hipSuccess) {
+    // mapped and coherent: the CG kernel that ends a chunk writes its slot
+    if (hipHostMalloc(&h, 2 * sizeof(rbf::CgScalarsN),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
       (void)hipGetLastError();
       return fail(RBF_ERR_OOM, "pinned host allocation failed");
     }
     P->host_bsc = static_cast<rbf::CgScalarsN*>(h);
+    HIPCHK(hipHostGetDevicePointer((void**)&P->host_bsc_dev, P->host_bsc, 0));
   }
   for (hipEvent_t& e : P->snap_ev)
     if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));

@@ -1266,7 +1266,7 @@ template <typename VT, typename XT, typename CT, int L, int BS, int NR, bool HAL
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_cgn_iter(
     int64_t m, CgMatrix A, const CgStateN<XT, NR>* __restrict__ sin,
     CgStateN<XT, NR>* __restrict__ sout, XT* __restrict__ p, XT* __restrict__ xlo,
-    CgScalarsN* __restrict__ sc, const double* __restrict__ part_in,
+    CgScalarsN* __restrict__ sc, CgScalarsN* snap, const double* __restrict__ part_in,
     double* __restrict__ part_out, int n_in, int xg, int q, int fixed) {
   constexpr int W = BS / kWave;
   constexpr int NPT = 6 * NR;
@@ -1303,7 +1303,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   if (threadIdx.x == 0) s_flag = sc->done;
   __syncthreads();
-  if (s_flag) return;
+  if (s_flag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && snap) *snap = *sc;
+    return;
+  }
   XT alpha[NR], beta[NR];
   double alpha_d[NR], gamma_d[NR], rr_d[NR];
   bool act[NR];
@@ -1352,6 +1355,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       for (int k = 0; k < NR; ++k) sc->rr[k] = rr_d[k];
       sc->done = flag;
+      if (snap) *snap = *sc;
     }
     return;
   }
@@ -1435,6 +1439,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
         sc->rr[k] = rr_d[k];
       }
       sc->iter += 1;
+      if (snap) *snap = *sc;  // the chunk's last launch: the host's slot
     }
   }
   (void)alpha_d;
@@ -1667,11 +1672,11 @@ void cgn_iter_launch_h(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed
   if (e0) {
     hipExtLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0,
                           s, e0, e1, 0, a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo,
-                          a.sc, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q,
-                          fixed);
+                          a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
+                          q, fixed);
   } else {
     hipLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0, s,
-                       a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc,
+                       a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed);
   }
 }

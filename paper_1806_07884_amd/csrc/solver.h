@@ -223,6 +223,7 @@ struct CgArgsN {
   double* xhi;      // [nr][m]
   double* r64;      // [nr][m]
   CgScalarsN* sc;
+  CgScalarsN* snap;  // host snapshot slot written by a chunk's last launch, or NULL
   double* part[2];  // [blocks][6 nr] partials of an iteration, by state buffer
   double* part_ref; // [blocks][6 nr] partials of a refresh
   int blocks;
