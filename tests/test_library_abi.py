@@ -56,3 +56,30 @@ def test_status_strings_without_gpu():
     d = _lib.PlanDesc(2, 10, 10, 1, 1, float("inf"), None, 1, 0.0)
     assert L.rbf_fit_plan(ctypes.byref(d), None, None, ctypes.byref(out)) == _lib.RBF_ERR_NONFINITE
     assert out.value is None
+
+
+def test_stream_argument_validation_without_gpu():
+    # rbf_stream_begin / rbf_stream_add / rbf_stream_finish reject bad
+    # arguments before any device call
+    from paper_1806_07884_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("librbf.so not built")
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+    assert L.rbf_stream_begin(None, None, None, ctypes.byref(out)) == _lib.RBF_ERR_INVALID
+    assert b"desc" in L.rbf_last_error()
+    good = dict(dim=2, n_centers=10, centers=1, rho=0.1, rho_per_center=None, min_support=1,
+                lambda_rel=0.0, phi=1, precision=1, max_chunk=100, flags=0)
+    bad = [dict(dim=4), dict(n_centers=0), dict(centers=None), dict(rho=-1.0),
+           dict(min_support=0), dict(lambda_rel=-1.0), dict(phi=7), dict(precision=3),
+           dict(max_chunk=0), dict(max_chunk=1 << 31), dict(flags=8)]
+    for change in bad:
+        d = _lib.StreamDesc(**{**good, **change})
+        assert L.rbf_stream_begin(ctypes.byref(d), None, None, ctypes.byref(out)) \
+            == _lib.RBF_ERR_INVALID, change
+        assert out.value is None
+    d = _lib.StreamDesc(**{**good, "rho": float("nan")})
+    assert L.rbf_stream_begin(ctypes.byref(d), None, None, ctypes.byref(out)) \
+        in (_lib.RBF_ERR_INVALID, _lib.RBF_ERR_NONFINITE)
+    assert L.rbf_stream_add(None, 1, None, None, 0) == _lib.RBF_ERR_INVALID
+    assert L.rbf_stream_finish(None) == _lib.RBF_ERR_INVALID
