@@ -694,12 +694,8 @@ int build_stream(rbf_plan* P) {
   GET(P->ccol, nc);
   HIPCHK(rbf::launch_cand_fill(v, P->cptr, P->cup, P->ccol, s));
   // the candidate relation is symmetric and holds every centre's own index:
-  // the upper lists hold (nc + m) / 2 entries in all.  Long lists take the
-  // grouped path, except for float64 sums in 2D, where the plain scan
-  // measured faster (terrain2d chunks: 1.46 against 1.63 ms; float32 1.37
-  // against 1.27 ms, and the 3D field gains in both precisions)
-  const bool long_lists = (double)(nc + m) / (2.0 * (double)std::max<int64_t>(m, 1)) > 64.0;
-  P->stream_grouped = long_lists && (P->dim == 3 || P->stream_prec == RBF_PREC_FP32_REFINE);
+  // the upper lists hold (nc + m) / 2 entries in all
+  P->stream_grouped = (double)(nc + m) / (2.0 * (double)std::max<int64_t>(m, 1)) > 64.0;
   // accumulators over the candidates (the upper parts are used) and centres
   GET(P->sacc, nc);
   GET(P->smark, nc);
