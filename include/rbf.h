@@ -134,6 +134,9 @@ typedef struct {
   int32_t check_every;  /* iterations between host reads of the residual (>= 1) */
   double reliable_delta;/* FP32_REFINE: float64 residual recomputation when the
                            iterated residual fell by this factor (0 < d < 1) */
+  int32_t stall_limit;  /* FP32_REFINE: consecutive reliable updates whose float64
+                           residual fell by less than 2x before the solve gives up
+                           on float32 (>= 0; 0 = the default, 8) */
 } rbf_solve_opts;
 
 typedef struct {
@@ -213,10 +216,19 @@ int rbf_system_export(const rbf_plan* plan, double* val_upper_h, double* g_h, do
  * reliable-update trigger (sized from its decay); the last launch of a chunk
  * writes the residual and flags into pinned host memory, and the host waits
  * on a chunk only after the next chunk is queued, so launches queued past a
- * trigger or convergence return at entry.  Returns OK, WARN_MAXITER
- * (best iterate kept), WARN_FALLBACK (mixed precision stalled and FP64 took
- * over), ERR_BREAKDOWN, ERR_INVALID (not assembled), ERR_HIP.  info may be
- * NULL. */
+ * trigger or convergence return at entry.  A float32 (FP32_REFINE) solve
+ * that stalls (opts->stall_limit) or breaks down while iterations remain goes
+ * on in float64 from its current solution, within the same max_iter: a plan
+ * holding its points assembles B, g, lambda and the preconditioner again in
+ * float64; a chunked plan (rbf_stream_*) takes its float64 accumulators (the
+ * sums as added, from float32 basis values) as the float64 matrix.  Either way
+ * the plan is a float64 plan afterwards (later solves, rbf_set_values and
+ * rbf_system_export use the float64 system).  A float32 solve that reaches
+ * max_iter, or stalls with no iteration left, returns WARN_MAXITER with the
+ * float32 system untouched.  Returns OK, WARN_MAXITER (best iterate kept),
+ * WARN_FALLBACK (mixed precision stalled or broke down and float64 finished
+ * the solve), ERR_BREAKDOWN, ERR_INVALID (not assembled, bad options),
+ * ERR_HIP, ERR_OOM.  info may be NULL. */
 int rbf_solve(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info);
 
 /* Solve for nrhs right-hand sides at once (vector-valued data, h_i in E^p,
@@ -310,7 +322,7 @@ int rbf_stream_add(rbf_plan* plan, int64_t n, const double* points, const double
  * NONFINITE (a chunk held NaN/Inf), OOM, HIP. */
 int rbf_stream_finish(rbf_plan* plan);
 
-/* Kernel timing for measurement./* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
+/* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
  * starts timing, with HIP events on the plan's stream, the assembly launch
  * (events recorded around it) and one CG iteration launch in 32
  * (events stamped at the kernel's own start and end by the extended launch;
@@ -386,6 +398,26 @@ int rbf_mlp_train(rbf_mlp* mlp, const float* x, const float* y, int64_t n_rows,
  * activations rounded to bfloat16 (nearest even) and float32 accumulation.
  * Stream-ordered. */
 int rbf_mlp_infer_bf16(const rbf_mlp* mlp, const float* x, int64_t n, float* out);
+
+/* Input standardisation used by rbf_mlp_grad, rbf_mlp_train and
+ * rbf_mlp_infer_bf16: every input x_i is replaced by (x_i - mean_h[i]) /
+ * std_h[i] (float32) as the kernels load it; host [16] each, std > 0.  A new
+ * MLP has mean 0 and std 1 (inputs as given).  Blocks the host.  Errors:
+ * INVALID (NULL, non-finite, std <= 0). */
+int rbf_mlp_set_input_scaling(rbf_mlp* mlp, const float* mean_h, const float* std_h);
+
+/* Checkpoint of everything training continues from: parameters (host
+ * [RBF_MLP_PARAMS]), Adam first and second moments (host [RBF_MLP_PARAMS]
+ * each), Adam steps taken (host scalar) and the input standardisation (host
+ * [16] each).  Any pointer may be NULL.  Training resumed from a checkpoint
+ * (rbf_mlp_load_state into any MLP, then rbf_mlp_train on the remaining
+ * batches) gives the same bits as training without the interruption.  Both
+ * block the host.  Errors: INVALID (NULL MLP; for the load, any NULL array, a
+ * step count outside [0, 2^30], bad scaling). */
+int rbf_mlp_state(const rbf_mlp* mlp, float* params_h, float* m1_h, float* m2_h,
+                  int64_t* step_h, float* mean_h, float* std_h);
+int rbf_mlp_load_state(rbf_mlp* mlp, const float* params_h, const float* m1_h,
+                       const float* m2_h, int64_t step, const float* mean_h, const float* std_h);
 void rbf_mlp_destroy(rbf_mlp* mlp);
 
 /* Release every buffer of the plan (after the plan's stream work finished). */

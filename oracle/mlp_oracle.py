@@ -18,9 +18,15 @@ radius that minimises held-out error from the local density of the data:
 Parameter layout (5313 floats): W1[16][64] (input-major), b1[64],
 W2[64][64], b2[64], W3[64], b3.
 
+bfloat16 inference reference: weights, inputs and hidden activations
+rounded to bfloat16 (nearest even), sums in float64.
+
 Parity: pinned.  Gradients against central finite differences, the first Adam
 step against its closed form, features against brute-force support counts,
-block assignment against integer grid arithmetic (tests/test_oracle_mlp.py).
+block assignment against integer grid arithmetic, per-block squared errors
+against a per-query search over the blocks' boxes, the bfloat16 rounding
+against torch's bfloat16 conversion and the bfloat16 network against a
+single-path network written out with that conversion (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
 
@@ -118,22 +124,29 @@ def train(theta, X, y, order, batch, lr):
 
 
 # ---------------------------------------------------------------- blocks
-def block_of(centers: np.ndarray, blocks_per_dim: int) -> np.ndarray:
-    """Block index of every centre: a uniform nb^dim partition of the centres'
-    bounding box, t = (xi - min) / (max - min), b = min(nb - 1, floor(t nb)),
-    first coordinate fastest."""
-    dim, m = centers.shape
+def block_index(coords: np.ndarray, centers: np.ndarray, blocks_per_dim: int) -> np.ndarray:
+    """Block index of every column of coords (SoA [dim][n]) in a uniform
+    nb^dim partition of the centres' bounding box: per dimension
+    t = (x - min) / (max - min) and b = floor(t nb) clipped to [0, nb - 1]
+    (coordinates outside the box go to the nearest block), first coordinate
+    fastest."""
+    dim, n = coords.shape
     nb = blocks_per_dim
-    idx = np.zeros(m, dtype=np.int64)
+    idx = np.zeros(n, dtype=np.int64)
     mul = 1
     for d in range(dim):
         lo, hi = centers[d].min(), centers[d].max()
         ext = hi - lo
-        t = (centers[d] - lo) / ext if ext > 0 else np.zeros(m)
-        b = np.minimum(nb - 1, np.floor(t * nb).astype(np.int64))
+        t = (coords[d] - lo) / ext if ext > 0 else np.zeros(n)
+        b = np.clip(np.floor(t * nb), 0, nb - 1).astype(np.int64)
         idx += b * mul
         mul *= nb
     return idx
+
+
+def block_of(centers: np.ndarray, blocks_per_dim: int) -> np.ndarray:
+    """Block index of every centre (t lies in [0, 1], so only t = 1 clips)."""
+    return block_index(centers, centers, blocks_per_dim)
 
 
 def density_features(points, centers, radii, blocks_per_dim):
@@ -164,18 +177,33 @@ def broadcast_radius(pred_log, centers, blocks_per_dim, spacing, rho_min, rho_ma
 
 
 def block_sq_err(queries, f, h, centers, blocks_per_dim):
-    """Per block of the centres' box: sum of (f - h)^2 and count of queries."""
-    dim = centers.shape[0]
-    nb = blocks_per_dim
-    idx = np.zeros(queries.shape[1], dtype=np.int64)
-    mul = 1
-    for d in range(dim):
-        lo, hi = centers[d].min(), centers[d].max()
-        ext = hi - lo
-        t = (queries[d] - lo) / ext if ext > 0 else np.zeros(queries.shape[1])
-        b = np.clip(np.floor(t * nb), 0, nb - 1).astype(np.int64)
-        idx += b * mul
-        mul *= nb
-    nblk = nb ** dim
-    e = (np.asarray(f) - np.asarray(h)) ** 2
+    """Per block of the centres' box (block_index): sum of (f - h)^2 over the
+    queries in the block and their count."""
+    idx = block_index(np.asarray(queries, dtype=np.float64), centers, blocks_per_dim)
+    nblk = blocks_per_dim ** centers.shape[0]
+    e = (np.asarray(f, dtype=np.float64) - np.asarray(h, dtype=np.float64)) ** 2
     return np.bincount(idx, weights=e, minlength=nblk), np.bincount(idx, minlength=nblk)
+
+
+# ---------------------------------------------------------------- bfloat16
+def bf16_round(a) -> np.ndarray:
+    """Values rounded to bfloat16 and returned as float64: first to float32
+    (nearest even), then the 32-bit pattern to its upper 16 bits, nearest with
+    ties to even (add 0x7FFF plus the lowest kept bit, drop the low half)."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    keep_lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + keep_lsb) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_forward(theta, X) -> np.ndarray:
+    """The network with bfloat16 weights, inputs and hidden activations:
+    every parameter and input rounded to bfloat16, each layer's affine map
+    summed in float64, tanh in float64 and its output rounded to bfloat16; the
+    output layer's sum is not rounded."""
+    W1, b1, W2, b2, W3, b3 = unpack(bf16_round(np.asarray(theta, np.float64)))
+    x = bf16_round(X)
+    h1 = bf16_round(np.tanh(x @ W1 + b1))
+    h2 = bf16_round(np.tanh(h1 @ W2 + b2))
+    return h2 @ W3 + b3

@@ -43,8 +43,9 @@ design notes of the repository):
 
 Parity: pinned.  Basis closed forms, brute-force supports, dense least
 squares (QR), symmetry / positive definiteness, the normal-equation invariant,
-the interpolation special case and the worked COO example of Section 4 pin
-every function here; the polynomial part is pinned by exact reproduction of
+the interpolation special case, the worked COO example of Section 4 and, for
+the RMSE, closed forms and the noise level of the Franke fit (a least-squares
+fit leaves sigma sqrt(1 - M/N) of N(0, sigma^2) noise) pin every function here; the polynomial part is pinned by exact reproduction of
 linear data, the QR solution of eq. 9 and the Table 4 density with a
 polynomial (see tests/test_oracle_*.py).
 """
@@ -408,14 +409,6 @@ def evaluate_one(query, centers, rho, phi: str, coeffs) -> float:
 def rmse(f, h) -> float:
     d = np.asarray(f, dtype=np.float64) - np.asarray(h, dtype=np.float64)
     return float(np.sqrt(np.mean(d * d))) if d.size else 0.0
-
-
-def normal_residual(ne: NormalEquations, c) -> float:
-    """||A^T (h - A c) - lambda c|| / ||A^T h|| on the active set."""
-    act = ne.active
-    r = ne.g - ne.full_matrix(with_ridge=True) @ np.asarray(c)
-    gn = np.linalg.norm(ne.g[act])
-    return float(np.linalg.norm(r[act]) / gn) if gn > 0 else 0.0
 
 
 # ---------------------------------------------------------------------------

@@ -65,7 +65,7 @@ class StreamDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("reliable_delta", ctypes.c_double)]
+                ("reliable_delta", ctypes.c_double), ("stall_limit", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -131,6 +131,14 @@ SIGNATURES = {
                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_float, ctypes.c_void_p]),
     "rbf_mlp_infer_bf16": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "rbf_mlp_set_input_scaling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
+    "rbf_mlp_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "rbf_mlp_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "rbf_mlp_destroy": (None, [ctypes.c_void_p]),
     "rbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -244,14 +244,14 @@ def rbf_poly_export(plan: Plan):
 
 def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1e-10,
               max_iter: int = 100000, warm_start: bool = False, check_every: int = 32,
-              reliable_delta: float = 0.1):
+              reliable_delta: float = 0.1, stall_limit: int = 0):
     """Jacobi-PCG solve of (B + lambda I) c = g, or of the bordered system of eq. 10
     with a polynomial (rbf_solve).  Returns (coeffs [M + n_poly], info)."""
     if coeffs is None:
         coeffs = torch.zeros(plan.m + plan.n_poly, dtype=torch.float64, device=plan.device)
     _need(coeffs, "coeffs", (plan.m + plan.n_poly,))
     opts = L.SolveOpts(float(rtol), int(max_iter), int(bool(warm_start)), int(check_every),
-                       float(reliable_delta))
+                       float(reliable_delta), int(stall_limit))
     info = L.SolveInfo()
     with torch.cuda.device(plan.device):
         st = L.lib().rbf_solve(plan.handle, ctypes.byref(opts), coeffs.data_ptr(),
@@ -434,6 +434,40 @@ class Mlp:
             L.check(L.lib().rbf_mlp_infer_bf16(self.handle, x.data_ptr(), n, out.data_ptr()),
                     "rbf_mlp_infer_bf16")
         return out
+
+    def set_input_scaling(self, mean, std) -> None:
+        """Inputs are standardised as (x - mean) / std (float32, per input) by
+        the training, gradient and inference kernels."""
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float32).reshape(L.MLP_INPUTS))
+        s = np.ascontiguousarray(np.asarray(std, dtype=np.float32).reshape(L.MLP_INPUTS))
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_set_input_scaling(self.handle, m.ctypes.data, s.ctypes.data),
+                    "rbf_mlp_set_input_scaling")
+
+    def state(self) -> dict:
+        """Everything training continues from: parameters, Adam moments and
+        step count, input scaling (rbf_mlp_state)."""
+        out = {k: np.zeros(L.MLP_PARAMS, np.float32) for k in ("params", "m1", "m2")}
+        out["mean"] = np.zeros(L.MLP_INPUTS, np.float32)
+        out["std"] = np.zeros(L.MLP_INPUTS, np.float32)
+        step = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_state(self.handle, out["params"].ctypes.data,
+                                          out["m1"].ctypes.data, out["m2"].ctypes.data,
+                                          ctypes.byref(step), out["mean"].ctypes.data,
+                                          out["std"].ctypes.data), "rbf_mlp_state")
+        out["step"] = int(step.value)
+        return out
+
+    def load_state(self, st: dict) -> None:
+        """Resume from a state() dictionary (rbf_mlp_load_state)."""
+        arr = {k: np.ascontiguousarray(np.asarray(st[k], dtype=np.float32))
+               for k in ("params", "m1", "m2", "mean", "std")}
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rbf_mlp_load_state(self.handle, arr["params"].ctypes.data,
+                                               arr["m1"].ctypes.data, arr["m2"].ctypes.data,
+                                               int(st["step"]), arr["mean"].ctypes.data,
+                                               arr["std"].ctypes.data), "rbf_mlp_load_state")
 
     def close(self):
         if self.handle and self.handle.value:

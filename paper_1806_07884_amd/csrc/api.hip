@@ -15,6 +15,7 @@
 #include "plan_kernels.h"
 #include "rbf.h"
 #include "chunk_planner.h"
+#include "solve_policy.h"
 #include "solver.h"
 #include "stream.h"
 
@@ -622,9 +623,11 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   GET(cnt, m + 1);
   GET(P->lower_cnt, m);
   GET(P->row_ptr, m + 1);
-  GET(err, 2);
+  GET(err, 3);
   maxd = err + 1;
-  HIPCHK(hipMemsetAsync(err, 0, 2 * sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(err, 0, 3 * sizeof(int32_t), s));
+  // without a ridge, identical columns of A make B singular
+  if (P->lambda_rel == 0.0) HIPCHK(rbf::launch_duplicate_centres(v, err + 2, s));
   HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
   uint32_t* marks;
   GET(marks, (int64_t)rbf::symbolic_marks_words(m));
@@ -633,10 +636,10 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
   HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
   int64_t nnz = 0, ms = 0;
-  int32_t flags[2] = {0, 0};
+  int32_t flags[3] = {0, 0, 0};
   HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&ms, apos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(flags, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(flags, err, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(cnt);
   P->release(apos);
@@ -646,6 +649,10 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
     return fail(RBF_ERR_INVALID,
                 "a centre has more than %d neighbouring centres within two support radii",
                 rbf::kMaxCand);
+  if (flags[2])
+    return fail(RBF_ERR_SINGULAR,
+                "two active centres have the same coordinates and radius and lambda_rel is 0: "
+                "B is singular");
   if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
   P->nnz_full = nnz;
   P->col16 = flags[1] <= 32767;
@@ -780,10 +787,12 @@ int finish_stream(rbf_plan* P) {
   int64_t* cnt;
   int32_t* maxd;
   GET(cnt, m + 1);
-  GET(maxd, 1);
+  GET(maxd, 2);
   GET(P->lower_cnt, m);
   GET(P->row_ptr, m + 1);
-  HIPCHK(hipMemsetAsync(maxd, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(maxd, 0, 2 * sizeof(int32_t), s));
+  // without a ridge, identical columns of A make B singular
+  if (P->lambda_rel == 0.0) HIPCHK(rbf::launch_duplicate_centres(P->view(), maxd + 1, s));
   HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
   HIPCHK(rbf::launch_stream_rows(P->cptr, P->cup, P->ccol, P->smark, P->active, m, cnt,
                                  P->lower_cnt, maxd, s));
@@ -791,10 +800,10 @@ int finish_stream(rbf_plan* P) {
   if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
   HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
   int64_t nnz = 0, ms = 0;
-  int32_t dmax = 0, bad = 0;
+  int32_t dm[2] = {0, 0}, bad = 0;
   HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&ms, apos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&dmax, maxd, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(dm, maxd, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&bad, P->sbad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(stmp);
@@ -804,9 +813,13 @@ int finish_stream(rbf_plan* P) {
   P->release(apos);
   if (bad) return fail(RBF_ERR_NONFINITE, "non-finite point coordinate or value in a chunk");
   if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
+  if (dm[1])
+    return fail(RBF_ERR_SINGULAR,
+                "two active centres have the same coordinates and radius and lambda_rel is 0: "
+                "B is singular");
   P->ms = ms;
   P->nnz_full = nnz;
-  P->col16 = dmax <= 32767;
+  P->col16 = dm[0] <= 32767;
   int64_t* src;
   GET(P->col, nnz);
   GET(src, nnz);
@@ -835,6 +848,32 @@ int finish_stream(rbf_plan* P) {
   HIPCHK(hipStreamSynchronize(s));
   P->release(src);
   P->prec = P->stream_prec;
+  return RBF_OK;
+}
+
+// The float64 system of a finished chunked plan from its float64 accumulators
+// (the float64 fallback of a float32 solve: the points are gone).  The
+// accumulators' index of every stored entry is rebuilt by the fill pass that
+// finish_stream ran (it rewrites the same columns).
+int stream_values64(rbf_plan* P) {
+  const int64_t m = P->m, nnz = P->nnz_full;
+  hipStream_t s = P->stream;
+  const int64_t nv = P->nsell + rbf::kSellTail;
+  if (!P->val64) {
+    GET(P->val64, nv);
+    HIPCHK(hipMemsetAsync(P->val64, 0, sizeof(double) * nv, s));
+  }
+  int64_t* src;
+  GET(src, std::max<int64_t>(nnz, 1));
+  HIPCHK(rbf::launch_stream_fill(P->cptr, P->cup, P->ccol, P->smark, P->active, m, P->row_ptr,
+                                 P->col, src, s));
+  HIPCHK(rbf::launch_stream_values(P->row_ptr, P->col, src, P->amap, P->active, P->sacc, P->sptr,
+                                   P->lanes, m, false, P->val64, P->diag, P->g, s));
+  HIPCHK(rbf::launch_finalize(m, P->active, P->ms, P->srow, P->sptr, P->lanes, P->lower_cnt,
+                              P->diag, P->lambda_rel, P->lam, false, P->val64, P->dinv64,
+                              P->dinv64, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(src);
   return RBF_OK;
 }
 
@@ -968,7 +1007,7 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
 // iteration budget.
 template <typename VT, typename XT>
 int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_solve_opts& o,
-           int64_t* iters, int64_t* updates, bool allow_stall_exit) {
+           int64_t* iters, int64_t* updates, int stall_limit) {
   hipStream_t s = P->stream;
   rbf::CgArgs<XT> a = make_args<XT>(P, vec, dinv);
   const rbf::CgMatrix A = P->matrix(val, (int)sizeof(XT));
@@ -981,8 +1020,8 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
   const int64_t budget = std::max<int64_t>(o.max_iter - base_iter, 0);
   int64_t launched = 0;  // iterations launched since the start (>= executed)
   bool fixed = true;     // the next launch takes its scalars from the refresh
-  double last_true = -1.0;
-  int stalls = 0;
+  // stall_limit 0: never give up on a stall (the float64 iteration)
+  rbf::StallWatch stall(stall_limit);
 
   rbf::ChunkPlanner plan(o.check_every);
   int64_t slot_len[2] = {0, 0};
@@ -1063,12 +1102,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
     if (h.done == 2) return fail(RBF_ERR_BREAKDOWN, "CG breakdown after %lld iterations",
                                  (long long)h.iter);
     if (h.done == 1) {
-      if (last_true >= 0.0 && h.rr_true > 0.25 * last_true) {
-        if (++stalls >= 8 && allow_stall_exit) return RBF_WARN_FALLBACK;
-      } else {
-        stalls = 0;
-      }
-      last_true = h.rr_true;
+      if (stall.update(h.rr_true) && stall_limit > 0) return RBF_WARN_FALLBACK;
       HIPCHK(rbf::cg_refresh<VT, XT>(a, A, P->g_s, q, q ^ 1, 0, s));
       ++refreshes;
       *updates += 1;
@@ -1541,9 +1575,10 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   o.warm_start = 0;
   o.check_every = 32;
   o.reliable_delta = 0.1;
+  o.stall_limit = 0;
   if (opts) o = *opts;
   if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 ||
-      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0))
+      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0) || o.stall_limit < 0)
     return fail(RBF_ERR_INVALID, "bad solve options");
   const bool fp32 = P->prec == RBF_PREC_FP32_REFINE;
   int rc = ensure_solver(P, fp32);
@@ -1591,29 +1626,33 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   int64_t iters = 0, updates = 0;
   int used = P->prec;
   if (fp32) {
-    rc = run_cg<float, float>(P, P->val32, P->dinv32, P->vec32, o, &iters, &updates, true);
-    if (rc == RBF_WARN_FALLBACK || rc == RBF_ERR_BREAKDOWN || rc == RBF_WARN_MAXITER) {
-      // finish in float64 from the current float64 solution
-      const int rc2 = ensure_solver(P, false);
+    const int limit = o.stall_limit > 0 ? o.stall_limit : rbf::kDefaultStallLimit;
+    rc = run_cg<float, float>(P, P->val32, P->dinv32, P->vec32, o, &iters, &updates, limit);
+    // decided on the host before any launch (solve_policy.h)
+    const rbf::Fallback act = rbf::fallback_action(rc, RBF_WARN_FALLBACK, RBF_ERR_BREAKDOWN, true,
+                                                   P->ps != nullptr, o.max_iter - iters);
+    if (act == rbf::Fallback::kNone && rc == RBF_WARN_FALLBACK) rc = RBF_WARN_MAXITER;
+    if (act != rbf::Fallback::kNone) {
+      // the float64 system, then the float64 iteration from the current
+      // float64 solution; the plan is a float64 plan from here on
+      int rc2 = ensure_solver(P, false);
       if (rc2) return rc2;
-      const int rch = build_halo(P);
-      if (rch) return rch;
-      const int rc3 = assemble_into(P, P->phi, false);
-      if (rc3) return rc3;
-      const int64_t left = o.max_iter - iters;
-      if (left > 0) {
-        rbf_solve_opts o2 = o;
-        o2.max_iter = iters + left;
-        const int rc4 = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o2, &iters,
-                                               &updates, false);
-        rc = rc4 == RBF_OK ? RBF_WARN_FALLBACK : rc4;
-        used = RBF_PREC_FP64;
-      }
+      rc2 = act == rbf::Fallback::kReassemble ? assemble_into(P, P->phi, false)
+                                              : stream_values64(P);
+      if (rc2) return rc2;
+      P->prec = RBF_PREC_FP64;
+      HIPCHK(rbf::launch_gather(P->g, P->srow, P->ms, P->g_s, s));
+      rc2 = build_halo(P);
+      if (rc2) return rc2;
+      const int rc4 = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters,
+                                             &updates, 0);
+      rc = rc4 == RBF_OK ? RBF_WARN_FALLBACK : rc4;
+      used = RBF_PREC_FP64;
     }
   } else {
     rc = build_halo(P);
     if (rc) return rc;
-    rc = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters, &updates, false);
+    rc = run_cg<double, double>(P, P->val64, P->dinv64, P->vec64, o, &iters, &updates, 0);
   }
   if (rc < 0 && rc != RBF_ERR_BREAKDOWN) return rc;
   HIPCHK(rbf::launch_scatter_rows(P->xhi, P->amap, P->m, coeffs, s));
@@ -1654,9 +1693,10 @@ int rbf_solve_batch(rbf_plan* P, int32_t nrhs, const double* values,
   o.warm_start = 0;
   o.check_every = 32;
   o.reliable_delta = 0.1;
+  o.stall_limit = 0;
   if (opts) o = *opts;
   if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 ||
-      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0))
+      !(o.reliable_delta > 0.0 && o.reliable_delta < 1.0) || o.stall_limit < 0)
     return fail(RBF_ERR_INVALID, "bad solve options");
   const bool fp32 = P->prec == RBF_PREC_FP32_REFINE;
   int rc = ensure_solver(P, fp32);
@@ -1881,12 +1921,14 @@ struct rbf_mlp {
   float* params = nullptr;
   float* m1 = nullptr;
   float* m2 = nullptr;
+  float* scale = nullptr;  // input standardisation {mean[16], std[16]}
   int64_t t = 0;  // Adam steps taken
   ~rbf_mlp() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (params) (void)hipFree(params);
     if (m1) (void)hipFree(m1);
     if (m2) (void)hipFree(m2);
+    if (scale) (void)hipFree(scale);
   }
 };
 
@@ -2005,14 +2047,22 @@ int rbf_mlp_create(const float* params_h, void* stream, rbf_mlp** out) {
   M->stream = (hipStream_t)stream;
   const size_t bytes = sizeof(float) * rbf::kMlpParams;
   if (hipMalloc(&M->params, bytes) != hipSuccess || hipMalloc(&M->m1, bytes) != hipSuccess ||
-      hipMalloc(&M->m2, bytes) != hipSuccess) {
+      hipMalloc(&M->m2, bytes) != hipSuccess ||
+      hipMalloc(&M->scale, sizeof(float) * 2 * rbf::kMlpInputs) != hipSuccess) {
     (void)hipGetLastError();
     delete M;
     return fail(RBF_ERR_OOM, "MLP allocation failed");
   }
+  float unit[2 * rbf::kMlpInputs];
+  for (int i = 0; i < rbf::kMlpInputs; ++i) {
+    unit[i] = 0.0f;
+    unit[rbf::kMlpInputs + i] = 1.0f;
+  }
   hipError_t e = hipMemcpyAsync(M->params, params_h, bytes, hipMemcpyHostToDevice, M->stream);
   if (e == hipSuccess) e = hipMemsetAsync(M->m1, 0, bytes, M->stream);
   if (e == hipSuccess) e = hipMemsetAsync(M->m2, 0, bytes, M->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(M->scale, unit, sizeof(unit), hipMemcpyHostToDevice, M->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
   if (e != hipSuccess) {
     delete M;
@@ -2036,7 +2086,8 @@ int rbf_mlp_grad(rbf_mlp* M, const float* x, const float* y, int64_t n, float* g
   if (n < 1) return fail(RBF_ERR_INVALID, "n must be >= 1");
   DevTmp<float> g;
   HIPCHK(g.alloc(rbf::kMlpParams + 1));
-  HIPCHK(rbf::launch_mlp_grad(M->params, x, y, n, g.p, g.p + rbf::kMlpParams, M->stream));
+  HIPCHK(rbf::launch_mlp_grad(M->params, M->scale, x, y, n, g.p, g.p + rbf::kMlpParams,
+                              M->stream));
   HIPCHK(hipMemcpyAsync(grad_h, g.p, sizeof(float) * rbf::kMlpParams, hipMemcpyDeviceToHost,
                         M->stream));
   HIPCHK(hipMemcpyAsync(loss_h, g.p + rbf::kMlpParams, sizeof(float), hipMemcpyDeviceToHost,
@@ -2061,7 +2112,7 @@ int rbf_mlp_train(rbf_mlp* M, const float* x, const float* y, int64_t n_rows,
     if (ord[k] < 0 || ord[k] >= n_rows) return fail(RBF_ERR_INVALID, "order index out of range");
   DevTmp<float> losses;
   HIPCHK(losses.alloc(steps));
-  HIPCHK(rbf::launch_mlp_train(M->params, M->m1, M->m2, x, y, order, steps, batch, lr,
+  HIPCHK(rbf::launch_mlp_train(M->params, M->m1, M->m2, M->scale, x, y, order, steps, batch, lr,
                                (int)M->t, losses.p, M->stream));
   M->t += steps;
   if (losses_h)
@@ -2074,7 +2125,55 @@ int rbf_mlp_train(rbf_mlp* M, const float* x, const float* y, int64_t n_rows,
 int rbf_mlp_infer_bf16(const rbf_mlp* M, const float* x, int64_t n, float* out) {
   if (!M || (n > 0 && (!x || !out))) return fail(RBF_ERR_INVALID, "NULL argument");
   if (n < 0) return fail(RBF_ERR_INVALID, "n < 0");
-  HIPCHK(rbf::launch_mlp_infer_bf16(M->params, x, n, out, M->stream));
+  HIPCHK(rbf::launch_mlp_infer_bf16(M->params, M->scale, x, n, out, M->stream));
+  return RBF_OK;
+}
+
+int rbf_mlp_set_input_scaling(rbf_mlp* M, const float* mean_h, const float* std_h) {
+  if (!M || !mean_h || !std_h) return fail(RBF_ERR_INVALID, "NULL argument");
+  float sc[2 * rbf::kMlpInputs];
+  for (int i = 0; i < rbf::kMlpInputs; ++i) {
+    if (!std::isfinite(mean_h[i]) || !std::isfinite(std_h[i]) || !(std_h[i] > 0.0f))
+      return fail(RBF_ERR_INVALID, "input scaling: mean must be finite and std finite and > 0");
+    sc[i] = mean_h[i];
+    sc[rbf::kMlpInputs + i] = std_h[i];
+  }
+  HIPCHK(hipMemcpyAsync(M->scale, sc, sizeof(sc), hipMemcpyHostToDevice, M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  return RBF_OK;
+}
+
+int rbf_mlp_state(const rbf_mlp* M, float* params_h, float* m1_h, float* m2_h, int64_t* step_h,
+                  float* mean_h, float* std_h) {
+  if (!M) return fail(RBF_ERR_INVALID, "NULL argument");
+  const size_t bytes = sizeof(float) * rbf::kMlpParams;
+  const size_t half = sizeof(float) * rbf::kMlpInputs;
+  if (params_h)
+    HIPCHK(hipMemcpyAsync(params_h, M->params, bytes, hipMemcpyDeviceToHost, M->stream));
+  if (m1_h) HIPCHK(hipMemcpyAsync(m1_h, M->m1, bytes, hipMemcpyDeviceToHost, M->stream));
+  if (m2_h) HIPCHK(hipMemcpyAsync(m2_h, M->m2, bytes, hipMemcpyDeviceToHost, M->stream));
+  if (mean_h) HIPCHK(hipMemcpyAsync(mean_h, M->scale, half, hipMemcpyDeviceToHost, M->stream));
+  if (std_h)
+    HIPCHK(hipMemcpyAsync(std_h, M->scale + rbf::kMlpInputs, half, hipMemcpyDeviceToHost,
+                          M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  if (step_h) *step_h = M->t;
+  return RBF_OK;
+}
+
+int rbf_mlp_load_state(rbf_mlp* M, const float* params_h, const float* m1_h, const float* m2_h,
+                       int64_t step, const float* mean_h, const float* std_h) {
+  if (!M || !params_h || !m1_h || !m2_h || !mean_h || !std_h)
+    return fail(RBF_ERR_INVALID, "NULL argument");
+  if (step < 0 || step > (int64_t)1 << 30) return fail(RBF_ERR_INVALID, "bad Adam step count");
+  const int rc = rbf_mlp_set_input_scaling(M, mean_h, std_h);
+  if (rc) return rc;
+  const size_t bytes = sizeof(float) * rbf::kMlpParams;
+  HIPCHK(hipMemcpyAsync(M->params, params_h, bytes, hipMemcpyHostToDevice, M->stream));
+  HIPCHK(hipMemcpyAsync(M->m1, m1_h, bytes, hipMemcpyHostToDevice, M->stream));
+  HIPCHK(hipMemcpyAsync(M->m2, m2_h, bytes, hipMemcpyHostToDevice, M->stream));
+  HIPCHK(hipStreamSynchronize(M->stream));
+  M->t = step;
   return RBF_OK;
 }
 

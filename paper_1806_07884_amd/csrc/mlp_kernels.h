@@ -26,12 +26,14 @@ hipError_t launch_block_sq_err(const double* y, int64_t nq, int dim, const doubl
 hipError_t launch_radius_broadcast(const float* pred, const int32_t* blk, int64_t m,
                                    double spacing, double rho_min, double rho_max,
                                    double rho_fallback, double* rho, hipStream_t s);
-hipError_t launch_mlp_grad(const float* params, const float* x, const float* y, int64_t n,
-                           float* grad, float* loss, hipStream_t s);
-hipError_t launch_mlp_train(float* params, float* m1, float* m2, const float* x, const float* y,
-                            const int32_t* order, int steps, int batch, float lr, int t0,
-                            float* losses, hipStream_t s);
-hipError_t launch_mlp_infer_bf16(const float* params, const float* x, int64_t n, float* out,
-                                 hipStream_t s);
+// scale: device {mean[16], std[16]}; every input is standardised as
+// (x_i - mean_i) / std_i in float32 when loaded.
+hipError_t launch_mlp_grad(const float* params, const float* scale, const float* x,
+                           const float* y, int64_t n, float* grad, float* loss, hipStream_t s);
+hipError_t launch_mlp_train(float* params, float* m1, float* m2, const float* scale,
+                            const float* x, const float* y, const int32_t* order, int steps,
+                            int batch, float lr, int t0, float* losses, hipStream_t s);
+hipError_t launch_mlp_infer_bf16(const float* params, const float* scale, const float* x,
+                                 int64_t n, float* out, hipStream_t s);
 
 }  // namespace rbf

@@ -290,12 +290,15 @@ __device__ void mlp_chunk(MlpLds& L, int nb, float scale, float* g) {
   __syncthreads();
 }
 
+// Rows of the chunk into LDS, each input standardised: (x_i - mean_i) / std_i
+// in float32 (scale = {mean[16], std[16]}).
 __device__ void load_chunk(MlpLds& L, const float* __restrict__ x, const float* __restrict__ y,
-                           const int32_t* __restrict__ idx, int64_t first, int nb) {
+                           const float* __restrict__ scale, const int32_t* __restrict__ idx,
+                           int64_t first, int nb) {
   for (int t = threadIdx.x; t < nb * kIn; t += kT) {
     const int s = t / kIn, i = t % kIn;
     const int64_t row = idx ? (int64_t)idx[first + s] : first + s;
-    L.X[s][i] = x[row * kIn + i];
+    L.X[s][i] = (x[row * kIn + i] - scale[i]) / scale[kIn + i];
   }
   for (int s = threadIdx.x; s < nb; s += kT) {
     const int64_t row = idx ? (int64_t)idx[first + s] : first + s;
@@ -307,6 +310,7 @@ __device__ void load_chunk(MlpLds& L, const float* __restrict__ x, const float* 
 // Full-batch gradient of the mean squared error over n samples (chunks of kB
 // in order), and the loss.
 __global__ __launch_bounds__(kT) void k_mlp_grad(const float* __restrict__ params,
+                                                 const float* __restrict__ scale,
                                                  const float* __restrict__ x,
                                                  const float* __restrict__ y, int64_t n,
                                                  float* __restrict__ grad,
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(kT) void k_mlp_grad(const float* __restrict__ param
   float lsum = 0.0f;
   for (int64_t first = 0; first < n; first += kB) {
     const int nb = (int)(n - first < kB ? n - first : kB);
-    load_chunk(L, x, y, nullptr, first, nb);
+    load_chunk(L, x, y, scale, nullptr, first, nb);
     mlp_chunk(L, nb, (float)n, g);
     lsum += L.lossv[0];
     __syncthreads();
@@ -339,6 +343,7 @@ __global__ __launch_bounds__(kT) void k_mlp_grad(const float* __restrict__ param
 __global__ __launch_bounds__(kT) void k_mlp_train(float* __restrict__ params,
                                                   float* __restrict__ mom1,
                                                   float* __restrict__ mom2,
+                                                  const float* __restrict__ scale,
                                                   const float* __restrict__ x,
                                                   const float* __restrict__ y,
                                                   const int32_t* __restrict__ order, int steps,
@@ -362,7 +367,7 @@ __global__ __launch_bounds__(kT) void k_mlp_train(float* __restrict__ params,
     float lsum = 0.0f;
     for (int first = 0; first < batch; first += kB) {
       const int nb = batch - first < kB ? batch - first : kB;
-      load_chunk(L, x, y, order, (int64_t)st * batch + first, nb);
+      load_chunk(L, x, y, scale, order, (int64_t)st * batch + first, nb);
       mlp_chunk(L, nb, (float)batch, g);
       lsum += L.lossv[0];
       __syncthreads();
@@ -395,6 +400,7 @@ __global__ __launch_bounds__(kT) void k_mlp_train(float* __restrict__ params,
 // BF16 inference: weights, inputs and hidden activations rounded to bfloat16
 // (nearest even), products accumulated in float32; one thread per sample.
 __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const float* __restrict__ params,
+                                                        const float* __restrict__ scale,
                                                         const float* __restrict__ x, int64_t n,
                                                         float* __restrict__ out) {
   __shared__ __hip_bfloat16 W[kMlpParams];
@@ -404,7 +410,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const float* __restrict_
   if (s >= n) return;
   float xin[kIn];
 #pragma unroll
-  for (int i = 0; i < kIn; ++i) xin[i] = __bfloat162float(__float2bfloat16(x[s * kIn + i]));
+  for (int i = 0; i < kIn; ++i)
+    xin[i] = __bfloat162float(__float2bfloat16((x[s * kIn + i] - scale[i]) / scale[kIn + i]));
   float h1[kH];
   for (int u = 0; u < kH; ++u) {
     float a = __bfloat162float(W[ob1 + u]);
@@ -469,26 +476,25 @@ hipError_t launch_radius_broadcast(const float* pred, const int32_t* blk, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float* params, const float* x, const float* y, int64_t n,
-                           float* grad, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(kT), 0, s, params, x, y, n, grad,
-                     loss);
+hipError_t launch_mlp_grad(const float* params, const float* scale, const float* x,
+                           const float* y, int64_t n, float* grad, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(kT), 0, s, params, scale, x, y, n, grad, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(float* params, float* m1, float* m2, const float* x, const float* y,
-                            const int32_t* order, int steps, int batch, float lr, int t0,
-                            float* losses, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(kT), 0, s, params, m1, m2, x, y,
-                     order, steps, batch, lr, t0, losses);
+hipError_t launch_mlp_train(float* params, float* m1, float* m2, const float* scale,
+                            const float* x, const float* y, const int32_t* order, int steps,
+                            int batch, float lr, int t0, float* losses, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(kT), 0, s, params, m1, m2, scale, x, y, order,
+                     steps, batch, lr, t0, losses);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer_bf16(const float* params, const float* x, int64_t n, float* out,
-                                 hipStream_t s) {
+hipError_t launch_mlp_infer_bf16(const float* params, const float* scale, const float* x,
+                                 int64_t n, float* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_infer_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params,
-                     x, n, out);
+                     scale, x, n, out);
   return hipGetLastError();
 }
 

@@ -122,6 +122,9 @@ hipError_t launch_radius_tables(const double* rho_in, double rho, int64_t m, dou
                                 double* rho2_c, double* irho_c, hipStream_t s);
 hipError_t launch_support_count(const PlanView& P, int32_t min_support, int32_t* count,
                                 uint8_t* active, hipStream_t s);
+// *dup = 1 if two active centres have the same coordinates and radius
+// (identical columns of A); needs the centre hash and the active marks.
+hipError_t launch_duplicate_centres(const PlanView& P, int32_t* dup, hipStream_t s);
 // Count pass (fill = false) then fill pass; `marks` (symbolic_marks_words(m)
 // words) carries the candidate marks from the first to the second.
 size_t symbolic_marks_words(int64_t m);

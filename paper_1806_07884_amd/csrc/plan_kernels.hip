@@ -503,6 +503,43 @@ hipError_t launch_radius_tables(const double* rho_in, double rho, int64_t m, dou
   return hipGetLastError();
 }
 
+// Identical columns of A: an active centre with the same coordinates and radius
+// as a centre of lower index (the two share a hash cell).  Every thread that
+// finds one stores 1 into *dup.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_duplicate_centres(PlanView P, int32_t* __restrict__ dup) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P.m || !P.active[j]) return;
+  double xj[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xj[d] = P.ctr[d * P.m + j];
+  int c[3];
+  if (!cell_of<DIM>(P.grid, xj, c)) return;
+  const int id = cell_id<DIM>(P.grid, c);
+  const double rj = P.rho[j];
+  for (int k = P.ccs[id]; k < P.ccs[id + 1]; ++k) {
+    const int32_t o = P.cperm[k];
+    if (o >= j) continue;
+    bool same = P.rho[o] == rj;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) same = same && P.ctr_s[d * P.m + k] == xj[d];
+    if (same) {
+      *dup = 1;
+      return;
+    }
+  }
+}
+
+hipError_t launch_duplicate_centres(const PlanView& P, int32_t* dup, hipStream_t s) {
+  if (P.m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((P.m + 255) / 256)), block(256);
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_duplicate_centres<2>, grid, block, 0, s, P, dup);
+  else
+    hipLaunchKernelGGL(k_duplicate_centres<3>, grid, block, 0, s, P, dup);
+  return hipGetLastError();
+}
+
 hipError_t launch_support_count(const PlanView& P, int32_t min_support, int32_t* count,
                                 uint8_t* active, hipStream_t s) {
   const int waves = 4;

@@ -123,28 +123,24 @@ def sweep_labels(points, values, test_points, test_values, centers, radii, spaci
 
 @dataclasses.dataclass
 class RadiusModel:
-    mlp: B.Mlp
+    mlp: B.Mlp        # carries the input standardisation of its training features
     mean: np.ndarray
     std: np.ndarray
-
-    def normalise(self, feats: torch.Tensor) -> torch.Tensor:
-        m = torch.as_tensor(self.mean, dtype=torch.float32, device=feats.device)
-        s = torch.as_tensor(self.std, dtype=torch.float32, device=feats.device)
-        return ((feats - m) / s).contiguous()
 
 
 def train(features: np.ndarray, labels: np.ndarray, init_params: np.ndarray, epochs: int,
           batch: int, lr: float, rng: np.random.Generator) -> tuple[RadiusModel, np.ndarray]:
     """Adam over shuffled mini-batches (the shuffles are drawn here, on the host,
     and passed to the kernel as row indices)."""
-    mean = features.mean(axis=0)
-    std = features.std(axis=0) + 1e-6
-    x = _dev(((features - mean) / std).astype(np.float32))
+    mean = features.mean(axis=0).astype(np.float32)
+    std = (features.std(axis=0) + 1e-6).astype(np.float32)
+    x = _dev(features.astype(np.float32))
     y = _dev(labels.astype(np.float32))
     n = features.shape[0]
     per_epoch = max(1, n // batch)
     order = np.concatenate([rng.permutation(n)[:per_epoch * batch] for _ in range(epochs)])
     mlp = B.Mlp(init_params.astype(np.float32))
+    mlp.set_input_scaling(mean, std)      # the kernels standardise as they load
     losses = mlp.train(x, y, order, batch, lr)
     return RadiusModel(mlp=mlp, mean=mean, std=std), losses
 
@@ -153,6 +149,6 @@ def predict_radii(model: RadiusModel, plan_for_centres: B.Plan, feats: torch.Ten
                   blocks_per_dim: int, spacing: float, rho_min: float, rho_max: float,
                   rho_fallback: float) -> torch.Tensor:
     """Per-centre radii (float64 [M], GPU) from the BF16 network."""
-    pred = model.mlp.infer_bf16(model.normalise(feats))
+    pred = model.mlp.infer_bf16(feats.contiguous())
     return B.rbf_radius_broadcast(plan_for_centres, pred, blocks_per_dim, spacing, rho_min,
                                   rho_max, rho_fallback)

@@ -45,23 +45,6 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def bf16_round(a):
-    """Round float64 values to bfloat16 (via float32, nearest even)."""
-    f = np.asarray(a, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    u = ((u + 0x7FFF + lsb) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def bf16_forward(theta, X):
-    W1, b1, W2, b2, W3, b3 = mo.unpack(bf16_round(np.asarray(theta, np.float32)))
-    x = bf16_round(X)
-    h1 = bf16_round(np.tanh(x @ W1 + b1))
-    h2 = bf16_round(np.tanh(h1 @ W2 + b2))
-    return h2 @ W3 + b3
-
-
 @pytest.mark.parametrize("dim", [2, 3])
 def test_density_features(rbf, dim):
     from paper_1806_07884_amd import radius
@@ -135,9 +118,69 @@ def test_mlp_bf16_inference(rbf):
     X = rng.standard_normal((777, 16)).astype(np.float32)
     mlp = rbf.Mlp(theta)
     out = mlp.infer_bf16(dev(X)).cpu().numpy().astype(np.float64)
-    ref = bf16_forward(theta, X.astype(np.float64))
+    ref = mo.bf16_forward(theta, X.astype(np.float64))
     full, _ = mo.forward(theta, X.astype(np.float64))
     say("bf16 vs emulation max", np.max(np.abs(out - ref)), "vs float64 net max",
         np.max(np.abs(out - full)))
     assert np.all(np.abs(out - ref) <= 2.0 ** -7 * (1 + np.abs(ref)))
     mlp.close()
+
+
+def test_mlp_input_scaling(rbf):
+    # the kernels standardise the inputs as they load them: gradient and
+    # inference on raw inputs equal the oracle's on (x - mean) / std formed in
+    # float32
+    rng = np.random.default_rng(53)
+    theta = mo.init_params(rng).astype(np.float32).astype(np.float64)
+    X = (rng.standard_normal((300, 16)) * 3.0 + 5.0).astype(np.float32)
+    y = rng.standard_normal(300).astype(np.float32)
+    mean = X.mean(axis=0).astype(np.float32)
+    std = (X.std(axis=0) + 1e-6).astype(np.float32)
+    Xs = ((X - mean) / std).astype(np.float32).astype(np.float64)
+    mlp = rbf.Mlp(theta)
+    mlp.set_input_scaling(mean, std)
+    loss, g = mlp.grad(dev(X), dev(y))
+    ref_loss, ref_g = mo.loss_and_grad(theta, Xs, y.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    assert np.all(np.abs(g - ref_g) <= 1e-4 * np.abs(ref_g).max() + 1e-5 * np.abs(ref_g))
+    out = mlp.infer_bf16(dev(X)).cpu().numpy().astype(np.float64)
+    ref = mo.bf16_forward(theta, Xs)
+    assert np.all(np.abs(out - ref) <= 2.0 ** -7 * (1 + np.abs(ref)))
+    st = mlp.state()
+    assert np.array_equal(st["mean"], mean) and np.array_equal(st["std"], std)
+    from paper_1806_07884_amd._lib import RbfError
+    with pytest.raises(RbfError):
+        mlp.set_input_scaling(mean, np.zeros(16, np.float32))
+    mlp.close()
+
+
+def test_mlp_checkpoint_resume_is_bit_exact(rbf):
+    # 3 + 4 Adam steps with a checkpoint in between (restored into a fresh MLP)
+    # give the bits of 7 steps in one go: parameters, both moments, step count
+    rng = np.random.default_rng(54)
+    theta = mo.init_params(rng)
+    X = rng.standard_normal((256, 16)).astype(np.float32)
+    y = (np.sin(X[:, 0]) - 0.5 * X[:, 3]).astype(np.float32)
+    order = np.concatenate([rng.permutation(256) for _ in range(2)])[:7 * 64]
+    mean = X.mean(axis=0).astype(np.float32)
+    std = X.std(axis=0).astype(np.float32)
+    whole = rbf.Mlp(theta)
+    whole.set_input_scaling(mean, std)
+    l_whole = whole.train(dev(X), dev(y), order, 64, 2e-3)
+    a = rbf.Mlp(theta)
+    a.set_input_scaling(mean, std)
+    l_a = a.train(dev(X), dev(y), order[:3 * 64], 64, 2e-3)
+    ck = a.state()
+    assert ck["step"] == 3
+    a.close()
+    b = rbf.Mlp(np.zeros(mo.N_PARAMS))
+    b.load_state(ck)
+    l_b = b.train(dev(X), dev(y), order[3 * 64:], 64, 2e-3)
+    sw, sb = whole.state(), b.state()
+    say("losses", l_whole, l_a, l_b)
+    assert np.array_equal(np.concatenate([l_a, l_b]), l_whole)
+    for k in ("params", "m1", "m2", "mean", "std"):
+        assert sw[k].tobytes() == sb[k].tobytes(), k
+    assert sw["step"] == sb["step"] == 7
+    whole.close()
+    b.close()

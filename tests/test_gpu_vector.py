@@ -9,7 +9,7 @@ Bars: g after rbf_set_values is bit for bit g of a fresh rbf_assemble with the
 same values (both assembly paths, float64 and float32), the coefficients of a
 component then equal those of a fresh fit bit for bit (the solver is
 deterministic), and each component's fit matches the oracle's Cholesky fit of
-that component (fitted values within 1e-9, as in test_gpu_parity).  The
+that component (fitted values within 1e-10, as in test_gpu_parity).  The
 batched solve (all components in one CG kernel per iteration) meets the same
 oracle bar in float64, and in the mixed path its held-out values agree with
 the sequential solves' to 1e-5 of their size (both stop at the same float64
@@ -24,6 +24,7 @@ import torch
 
 import synthdata as sd
 from oracle import rbf_oracle as orc
+from tolerances import FIT_FP64, FP64_RTOL
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +106,7 @@ def test_vector_valued_fit(rbf, poly):
             ref = ne.A @ c_ref
             fit = np.linalg.norm(ne.A @ ck - ref) / np.linalg.norm(ref)
         say(f"component {i}: fit {fit:.2e}, iterations {info['iterations']}")
-        assert fit <= 1e-9
+        assert fit <= FIT_FP64
     plan.close()
 
 
@@ -134,7 +135,8 @@ def test_batch_fp64_matches_oracle(rbf, nr):
         ne = orc.normal_equations(p, h, ctr, rho, "w31")
         c_ref = orc.solve(ne)
         fit = np.linalg.norm(ne.A @ (C[k] - c_ref)) / np.linalg.norm(ne.A @ c_ref)
-        assert fit <= 1e-9, (k, fit)
+        say(k, "fit", fit)
+        assert fit <= FIT_FP64, (k, fit)
     # the plan is left holding the last component's values
     _, g, _ = rbf.rbf_system_export(plan)
     rbf.rbf_set_values(plan, dev(H[-1]))
@@ -223,7 +225,7 @@ def test_batch_3d(rbf):
     H = [prob.values, np.sin(3 * p[0]) * np.cos(2 * p[2]) + p[1]]
     plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho, lambda_rel=1e-5)
     rbf.rbf_assemble(plan, prob.phi, "fp64", dev(H[0]))
-    C, infos = rbf.rbf_solve_batch(plan, dev(np.stack(H)), rtol=1e-12, max_iter=50000)
+    C, infos = rbf.rbf_solve_batch(plan, dev(np.stack(H)), rtol=FP64_RTOL, max_iter=50000)
     say("batched 3D", rbf.rbf_plan_info(plan)["solver_staged"], [i["iterations"] for i in infos])
     C = C.cpu().numpy()
     for k, h in enumerate(H):
@@ -232,5 +234,5 @@ def test_batch_3d(rbf):
         c_ref = orc.solve(ne)
         fit = np.linalg.norm(ne.A @ (C[k] - c_ref)) / np.linalg.norm(ne.A @ c_ref)
         say(k, "fit", fit)
-        assert fit <= 1e-8
+        assert fit <= FIT_FP64
     plan.close()

@@ -337,3 +337,34 @@ def test_sample_row_full_equals_full_matrix():
         a, b = full.indptr[j], full.indptr[j + 1]
         assert np.array_equal(row.cols, full.indices[a:b])
         assert np.allclose(row.vals, full.data[a:b], rtol=1e-14, atol=0)
+
+
+# -------------------------------------------------------------------- RMSE
+def test_rmse_closed_forms():
+    # a constant offset a gives |a|; errors +-a in any mix give a; the mean of
+    # e^2 over [3, 4] (12.5) gives sqrt(12.5)
+    h = np.linspace(-2.0, 5.0, 101)
+    assert orc.rmse(h + 0.375, h) == 0.375
+    s = np.where(np.arange(101) % 3 == 0, 1.0, -1.0)
+    assert orc.rmse(h + 0.25 * s, h) == 0.25
+    assert math.isclose(orc.rmse(np.array([3.0, 4.0]), np.zeros(2)), math.sqrt(12.5),
+                        rel_tol=1e-15)
+    assert orc.rmse(np.zeros(0), np.zeros(0)) == 0.0
+
+
+def test_franke_training_rmse_is_the_noise_level():
+    # least squares with M free coefficients on N samples of a smooth field
+    # plus N(0, sigma^2) noise leaves a training RMSE of about
+    # sigma sqrt(1 - M/N) (the residual lies in an (N - M)-dimensional space),
+    # once the basis resolves the field: 1024 centres, 10,000 points,
+    # sigma = 0.01 -> about 0.0095
+    p = sd.make_problem("franke2d")
+    ne = orc.normal_equations(p.points, p.values, p.centers, p.rho, p.phi)
+    c = orc.solve(ne)
+    r = orc.rmse(ne.A @ c, p.values)
+    sigma = 0.01
+    expect = sigma * math.sqrt(1.0 - p.centers.shape[1] / p.points.shape[1])
+    assert 0.95 * expect <= r <= 1.05 * expect, (r, expect)
+    # against the noise-free field the fit is much closer than the noise
+    clean = orc.rmse(ne.A @ c, sd.franke(p.points))
+    assert clean < 0.5 * sigma
