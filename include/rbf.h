@@ -258,6 +258,23 @@ int rbf_solve_batch(rbf_plan* plan, int32_t nrhs, const double* values,
 int rbf_eval(const rbf_plan* plan, int64_t n_query, const double* queries,
              const double* coeffs, double* out, const double* values, double* rmse_h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rbf_eval
+ * with every workspace in a static device array of the library instead of
+ * memory the plan allocates -- the coefficients gathered into centre-hash
+ * order (n_centers doubles) and the squared-error partial sums.  Same
+ * arguments, kernels and results (bit for bit) as rbf_eval; calls no
+ * allocating routine.  The array holds RBF_NOALLOC_MAX_CENTERS + 1025
+ * doubles (8.4 MB) per GPU, for the life of the process; its device address
+ * is taken at the first call on each GPU (that GPU current).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (from several
+ * threads or streams) race and must be serialised by the caller.  Errors: as
+ * rbf_eval, and INVALID for a plan with more than RBF_NOALLOC_MAX_CENTERS
+ * centres. */
+#define RBF_NOALLOC_MAX_CENTERS 1048576
+int rbf_eval_noalloc(const rbf_plan* plan, int64_t n_query, const double* queries,
+                     const double* coeffs, double* out, const double* values, double* rmse_h);
+
 /* ---- points streamed through the GPU in chunks -------------------------- *
  * B = A^T A and g = A^T h are sums over the points: with A_c the rows of A of
  * the points of chunk c, B = sum_c A_c^T A_c and g = sum_c A_c^T h_c (the

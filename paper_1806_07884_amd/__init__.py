@@ -17,7 +17,8 @@ Points that need not (or cannot) sit in HBM together stream through in chunks:
     rbf_stream_finish(plan)
     coeffs, info = rbf_solve(plan, rtol=1e-10)
 """
-from .binding import (Plan, rbf_assemble, rbf_eval, rbf_fit_plan, rbf_plan_info,  # noqa: F401
+from .binding import (Plan, rbf_assemble, rbf_eval, rbf_eval_noalloc, rbf_fit_plan,  # noqa: F401
+                      rbf_plan_info,
                       rbf_plan_pattern, rbf_solve, rbf_system_export, rbf_poly_export, rbf_set_values,
                       rbf_solve_batch, rbf_stream_begin, rbf_stream_add, rbf_stream_finish,
                       rbf_plan_destroy,

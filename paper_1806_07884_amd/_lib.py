@@ -141,6 +141,9 @@ SIGNATURES = {
                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "rbf_mlp_destroy": (None, [ctypes.c_void_p]),
+    "rbf_eval_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double)]),
     "rbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbf_last_error": (ctypes.c_char_p, []),
 }

@@ -314,6 +314,28 @@ def rbf_eval(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
     return out, (rmse.value if values is not None else None)
 
 
+def rbf_eval_noalloc(plan: Plan, queries: torch.Tensor, coeffs: torch.Tensor,
+                     out: torch.Tensor, values: Optional[torch.Tensor] = None):
+    """rbf_eval without any device allocation (rbf_eval_noalloc): the library's
+    static workspace replaces the plan's; `out` (Q,) float64 is the caller's."""
+    _need(queries, "queries")
+    if queries.dim() != 2 or queries.shape[0] != plan.dim:
+        raise ValueError("queries must be (dim, Q)")
+    nq = int(queries.shape[1])
+    _need(coeffs, "coeffs", (plan.m + plan.n_poly,))
+    _need(out, "out", (nq,))
+    rmse = ctypes.c_double(float("nan"))
+    if values is not None:
+        _need(values, "values", (nq,))
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_eval_noalloc(plan.handle, nq, queries.data_ptr(), coeffs.data_ptr(),
+                                      out.data_ptr(),
+                                      values.data_ptr() if values is not None else None,
+                                      ctypes.byref(rmse))
+    L.check(st, "rbf_eval_noalloc")
+    return out, (rmse.value if values is not None else None)
+
+
 def rbf_profile(plan: Plan, enable: bool) -> None:
     """Start (reset) or stop event timing of the assembly and CG iteration launches."""
     with torch.cuda.device(plan.device):

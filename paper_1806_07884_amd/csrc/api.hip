@@ -1288,6 +1288,36 @@ int ensure_batch(rbf_plan* P, bool fp32) {
   return RBF_OK;
 }
 
+// Partial sums of the squared error of an evaluation (the most blocks
+// sq_err_blocks gives), then their total.
+constexpr int64_t kEvalParts = 1024;
+
+// The allocation-free evaluation's workspace: one static device array per GPU
+// the library runs on, held until the process ends.  Host code never uses the
+// array's name as an address: noalloc_scratch() takes the device address of
+// this GPU's copy once (with the GPU current) and keeps it per device.
+constexpr int64_t kNoAllocScratch = RBF_NOALLOC_MAX_CENTERS + kEvalParts + 1;  // doubles
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RBF_ERR_INVALID, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(RBF_ERR_HIP, "hipGetSymbolAddress returned no address");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return RBF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1773,11 +1803,51 @@ int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double
       *rmse_h = 0.0;
       return RBF_OK;
     }
-    if (!P->eval_part) GET(P->eval_part, 1025);
+    if (!P->eval_part) GET(P->eval_part, kEvalParts + 1);
     const int nb = rbf::sq_err_blocks(nq);
-    HIPCHK(rbf::launch_sq_err(out, values, nq, P->eval_part, nb, P->eval_part + 1024, s));
+    HIPCHK(rbf::launch_sq_err(out, values, nq, P->eval_part, nb, P->eval_part + kEvalParts, s));
     double sum = 0.0;
-    HIPCHK(hipMemcpyAsync(&sum, P->eval_part + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&sum, P->eval_part + kEvalParts, sizeof(double), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    *rmse_h = sqrt(sum / (double)nq);
+  }
+  return RBF_OK;
+}
+
+int rbf_eval_noalloc(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,
+                     double* out, const double* values, double* rmse_h) {
+  rbf_plan* P = const_cast<rbf_plan*>(Pc);
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (nq < 0) return fail(RBF_ERR_INVALID, "n_query < 0");
+  if (nq > 0 && (!queries || !coeffs || !out)) return fail(RBF_ERR_INVALID, "NULL pointer");
+  if (values && !rmse_h) return fail(RBF_ERR_INVALID, "rmse_h is NULL");
+  if (P->m > RBF_NOALLOC_MAX_CENTERS)
+    return fail(RBF_ERR_INVALID,
+                "rbf_eval_noalloc takes at most %lld centres (the plan has %lld); use rbf_eval",
+                (long long)RBF_NOALLOC_MAX_CENTERS, (long long)P->m);
+  double* scr = nullptr;
+  const int rc = noalloc_scratch(&scr);
+  if (rc) return rc;
+  // scratch: the coefficients in centre-hash order [M], then the squared-error
+  // partial sums [kEvalParts] and their total
+  double* cs_sorted = scr;
+  double* part = scr + RBF_NOALLOC_MAX_CENTERS;
+  hipStream_t s = P->stream;
+  if (nq > 0) {
+    HIPCHK(rbf::launch_gather(coeffs, P->cperm, P->m, cs_sorted, s));
+    HIPCHK(rbf::launch_eval(P->view(), P->phi < 0 ? 1 : P->phi, nq, queries, cs_sorted,
+                            P->rho2_s, P->irho_s, P->npoly ? coeffs + P->m : nullptr, out, s));
+  }
+  if (values) {
+    if (nq == 0) {
+      *rmse_h = 0.0;
+      return RBF_OK;
+    }
+    const int nb = rbf::sq_err_blocks(nq);
+    HIPCHK(rbf::launch_sq_err(out, values, nq, part, nb, part + kEvalParts, s));
+    double sum = 0.0;
+    HIPCHK(hipMemcpyAsync(&sum, part + kEvalParts, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     *rmse_h = sqrt(sum / (double)nq);
   }
