@@ -12,7 +12,18 @@ One step = one whole fit on inputs already resident in HBM: hash + pattern
 evaluation of the held-out RMSE (rbf_eval).  The headline value is the
 mixed-precision path (float32 basis/assembly/CG with float64 reliable
 updates); the float64 path is timed the same way and reported beside it,
-with both held-out RMSEs (matched when they agree to 0.1 %).
+with both held-out RMSEs (matched when they agree to 0.1 %).  The ridge
+lambda_rel = 1e-4 is the largest of the swept values whose held-out RMSE lies
+within 1 % of the sweep's best; the same fits at lambda_rel = 1e-5 (the
+sweep's best RMSE, twice the iterations) are timed too and reported under
+"lambda_1e-5".
+
+roofline: the CG iteration kernel's algorithmic bytes per launch (8 bytes per
+nonzero of B plus ten float32 vector passes) over its average duration,
+timed live with start/stop events on one launch in 32 (a stamped launch reads
+about 1 us longer than the same launch in a kernel trace); the bytes the
+int16-delta layout moves (6 bytes per nonzero plus twelve vector passes) are
+reported beside it, and so is the bandwidth of a plain 2 GiB device copy.
 
 ``--workload terrain2d_big`` (N = 2^24, 1024 x 1024 centres, phi_{3,2}) and
 ``--workload field3d`` (N = 2^22 in 3D, 64^3 centres, scored at 10^6
@@ -55,11 +66,41 @@ def log(*a):
 
 def iter_bytes(nnz_full: int, m: int, val_bytes: int, col_bytes: int, vec_bytes: int,
                n_poly: int = 0) -> int:
-    """Algorithmic HBM bytes of one CG iteration launch: every nonzero of B
-    once (value and column index, padding excluded) and, per solver row (an
-    active centre), its state record (r, w, s, d) read and written plus p and
-    x read and written, and with a polynomial its n_poly entries of A^T P."""
+    """HBM bytes one CG iteration launch of this layout moves at least: every
+    nonzero of B once (value and column index as stored, padding excluded)
+    and, per solver row (an active centre), its state record (r, w, s, d)
+    read and written plus p and x read and written, and with a polynomial its
+    n_poly entries of A^T P."""
     return nnz_full * (val_bytes + col_bytes) + (12 + n_poly) * m * vec_bytes
+
+
+def algorithmic_iter_bytes(nnz_full: int, m: int, vec_bytes: int) -> int:
+    """Algorithmic bytes of one CG iteration, the per-unit figure of the
+    mixed-precision solve: one pass over B at 8 bytes per nonzero (a float32
+    value and a 32-bit column index) plus about ten passes over float32
+    vectors of the solver's size."""
+    return nnz_full * 8 + 10 * m * vec_bytes
+
+
+def copy_peak(gib: float = 2.0, reps: int = 5) -> float:
+    """Achievable HBM bandwidth: a plain device-to-device copy of `gib` GiB
+    (read + write bytes over the copy time, best of `reps`), in bytes/s."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / best
 
 
 def kernel_digest() -> str:
@@ -83,6 +124,7 @@ def cpu_baseline(prob, frac: float):
         threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
     except Exception:
         threads = 1
+    cores = len(os.sched_getaffinity(0))
     w = frac
     ctr = prob.centers
     keep_c = np.all(ctr <= w + 1e-12, axis=0)
@@ -95,10 +137,12 @@ def cpu_baseline(prob, frac: float):
     orc.solve(ne)
     dt = time.perf_counter() - t0
     n_used = p_win.shape[1]
-    return {"value": n_used / dt, "unit": "pts/s", "cores": int(threads), "kind": "oracle",
+    return {"value": n_used / dt, "unit": "pts/s", "cores": int(cores), "kind": "oracle",
+            "blas_threads": int(threads),
             "sample": (f"window [0,{w}]^2 of the same workload: {c_win.shape[1]} centres, "
                        f"{n_used} points (those within rho of the window), assembly of "
-                       f"A, B = A^T A, g = A^T h plus Cholesky solve; {dt:.1f} s"),
+                       f"A, B = A^T A, g = A^T h (single-threaded NumPy/SciPy) plus the "
+                       f"Cholesky solve (LAPACK, {threads} threads); {dt:.1f} s"),
             "seconds": dt}
 
 
@@ -126,6 +170,8 @@ def main() -> int:
                          "them from pinned host memory (PCIe-inclusive, reported beside)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--no-lambda-leg", action="store_true",
+                    help="skip the extra fits at lambda_rel = 1e-5 (the sweep's best held-out RMSE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -155,6 +201,19 @@ def main() -> int:
     pts, vals, ctr = dev(prob.points), dev(prob.values), dev(prob.centers)
     q, qh = sd.scoring_queries(prob)
     tpts, tvals = dev(q), dev(qh)
+    # the 3D field is scored at uniform queries; its held-out points and the
+    # queries inside some support are reported as second scores
+    second = prob.score == "uniform" and prob.test_points.shape[1] > 0
+    hpts, hvals = (dev(prob.test_points), dev(prob.test_values)) if second else (None, None)
+    scores = {}
+
+    def score2(plan, c, fq):
+        if not second:
+            return
+        cov = fq != 0
+        scores["covered_fraction"] = float(cov.double().mean().item())
+        scores["covered_rmse"] = float(torch.sqrt(torch.mean((fq[cov] - tvals[cov]) ** 2)).item())
+        _, scores["heldout_rmse"] = rbf.rbf_eval(plan, hpts, c, values=hvals)
     n_train = prob.points.shape[1]
     torch.cuda.synchronize()
 
@@ -185,19 +244,20 @@ def main() -> int:
     source = {"chunks": chunks_dev}
     torch.cuda.synchronize()
 
-    def fit(prec: str, profile: bool = False):
+    def fit(prec: str, profile: bool = False, lam: float = LAMBDA_REL):
         if args.stream:
             plan = rbf.rbf_stream_begin(ctr, max_chunk, rho=prob.rho, phi=prob.phi, prec=prec,
-                                        lambda_rel=LAMBDA_REL)
+                                        lambda_rel=lam)
             if profile:
                 rbf.rbf_profile(plan, True)
             for xc, hc in source["chunks"]:
                 rbf.rbf_stream_add(plan, xc, hc)
             rbf.rbf_stream_finish(plan)
             c, info = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
-            _, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+            fq, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+            score2(plan, c, fq)
             return plan, info, rmse
-        plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=LAMBDA_REL,
+        plan = rbf.rbf_fit_plan(pts, ctr, rho=prob.rho, lambda_rel=lam,
                                 polynomial=args.polynomial)
         if profile:
             rbf.rbf_profile(plan, True)
@@ -209,29 +269,31 @@ def main() -> int:
                 rbf.rbf_eval(plan, tpts, C[k].contiguous())
             return plan, infos[0], rmse
         c, info = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
-        _, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+        fq, rmse = rbf.rbf_eval(plan, tpts, c, values=tvals)
+        score2(plan, c, fq)
         for hk, qk in extra:
             rbf.rbf_set_values(plan, hk)
             ck, _ = rbf.rbf_solve(plan, rtol=RTOL, max_iter=200000)
             rbf.rbf_eval(plan, tpts, ck)
         return plan, info, rmse
 
-    def timed(prec: str, steps: int, warm: int):
+    def timed(prec: str, steps: int, warm: int, lam: float = LAMBDA_REL):
         for _ in range(warm):
-            plan, info, rmse = fit(prec)
+            plan, info, rmse = fit(prec, lam=lam)
             plan.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         per = []
         spmv_n, spmv_ms, asm_ms = 0, 0.0, 0.0
         for _ in range(steps):
-            plan, info, rmse = fit(prec, profile=True)
+            plan, info, rmse = fit(prec, profile=True, lam=lam)
+            sc = dict(scores)
             n, ms = rbf.rbf_profile_read(plan, "cg_iter_batch" if stacked is not None else "cg_iter")
             _, ams = rbf.rbf_profile_read(plan, "assemble")
             spmv_n += n
             spmv_ms += ms
             asm_ms += ams
-            per.append((info, rmse))
+            per.append((info, rmse, sc))
             stats = rbf.rbf_plan_info(plan)
             plan.close()
         torch.cuda.synchronize()
@@ -255,6 +317,14 @@ def main() -> int:
         source["chunks"] = chunks_dev
     rmse32, rmse64 = per32[-1][1], per64[-1][1]
     matched = abs(rmse32 - rmse64) <= 1e-3 * rmse64
+    second_scores = None
+    if second:
+        s32, s64 = per32[-1][2], per64[-1][2]
+        second_scores = {"heldout_points": int(prob.test_points.shape[1]),
+                         "mixed": s32, "fp64": s64,
+                         "heldout_matched": bool(abs(s32["heldout_rmse"] - s64["heldout_rmse"])
+                                                 <= 1e-3 * s64["heldout_rmse"])}
+        matched = matched and second_scores["heldout_matched"]
 
     # the solver's rows are the active centres
     nnz, m, cb = stats["nnz_full"], stats["n_active"], stats["solver_col_bytes"]
@@ -262,7 +332,8 @@ def main() -> int:
     # kernel time from start/stop events of sampled launches on the plan's stream
     kern32 = max(avg32, 1e-3) * 1e-6
     bytes32 = iter_bytes(nnz, m, 4, cb, 4, npoly)
-    achieved = bytes32 / kern32
+    algo32 = algorithmic_iter_bytes(nnz, m, 4)
+    achieved = algo32 / kern32
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"cg_iter_fp32_{wl}_traffic.json")
     if os.path.exists(tfile) and not npoly:
@@ -270,13 +341,36 @@ def main() -> int:
             t = json.load(fh)
         if t.get("kernel_digest") == kernel_digest():
             traffic = t.get("bytes_per_launch")
+    log("timing a plain device copy (achievable HBM bandwidth)")
+    copy_bw = copy_peak()
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "kernel": "k_cg_iter<float,float,int16,L>", "bytes_per_launch": bytes32,
+                "kernel": "k_cg_iter<float,float,int16,L>",
+                "algorithmic_bytes_per_launch": algo32,
+                "layout_bytes_per_launch": bytes32,
+                "frac_layout_bytes": bytes32 / kern32 / HBM_PEAK,
+                "measured_copy_peak": copy_bw / 1e9,
+                "frac_of_copy_peak": achieved / copy_bw,
                 "avg_kernel_us": kern32 * 1e6, "timed_launches": n32,
                 "solver_entries": stats["solver_entries"], "solver_lanes": stats["solver_lanes"]}
     kern64 = max(avg64, 1e-3) * 1e-6
     b64 = iter_bytes(nnz, m, 8, cb, 8, npoly)
+
+    # the same fits at lambda_rel = 1e-5, the ridge with the best held-out RMSE
+    # of the sweep: throughput not bought with regularisation
+    lam_leg = None
+    if (not args.no_lambda_leg and wl == "terrain2d" and not args.stream and not args.polynomial
+            and args.components == 1):
+        lam5 = 1e-5
+        d5, p5, _, _, a5, _ = timed("fp32", 1, 0, lam=lam5)
+        d5b, p5b, _, _, _, _ = timed("fp64", 1, 0, lam=lam5)
+        lam_leg = {"lambda_rel": lam5, "value": n_train / d5, "ms_per_fit": d5 * 1e3,
+                   "iterations": p5[-1][0]["iterations"], "scoring_rmse": p5[-1][1],
+                   "cg_iter_kernel_us": a5,
+                   "fp64": {"value": n_train / d5b, "ms_per_fit": d5b * 1e3,
+                            "iterations": p5b[-1][0]["iterations"],
+                            "scoring_rmse": p5b[-1][1]},
+                   "rmse_matched": bool(abs(p5[-1][1] - p5b[-1][1]) <= 1e-3 * p5b[-1][1])}
 
     cpu = None
     if not args.no_cpu_baseline and wl == "terrain2d" and not args.polynomial:
@@ -310,9 +404,11 @@ def main() -> int:
                  "assembly_ms": asm64, "cg_iter_kernel_us": kern64 * 1e6,
                  "cg_iter_gbps": b64 / kern64 / 1e9},
         "speedup_mixed_vs_fp64": dt64 / dt32,
+        "lambda_1e-5": lam_leg,
         "stream_from_host": pcie,
         "rmse_matched": bool(matched),
-        "scoring": (f"{q.shape[1]} held-out points vs noisy samples" if prob.test_points.shape[1]
+        "second_scores": second_scores,
+        "scoring": (f"{q.shape[1]} held-out points vs noisy samples" if prob.score == "heldout"
                     else f"{q.shape[1]} uniform queries vs the noise-free field"),
     }
     print(json.dumps(out), flush=True)

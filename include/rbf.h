@@ -248,6 +248,28 @@ int rbf_solve(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs, rbf_so
 int rbf_solve_batch(rbf_plan* plan, int32_t nrhs, const double* values,
                     const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info);
 
+/* The same least-squares fit as rbf_solve -- min ||A c + P k - h||^2 +
+ * lambda ||c||^2 (Section 2, eq. 4-5; with a polynomial, the columns of P of
+ * Section 3, eq. 9) -- by LSQR (Paige & Saunders, ACM TOMS 8, 1982) on the
+ * design matrix itself instead of CG on the normal equations: A v is an
+ * evaluation at the data points (eq. 3) and A^T u the assembly's g = A^T h
+ * pass, so the iteration sees the conditioning of A, not its square.  For
+ * dense or nearly dense A (large supports, as the paper's synthetic
+ * experiment has: Table 3) where kappa(A^T A) is beyond float64.  All in
+ * float64 with the basis of the last rbf_assemble and the values it (or
+ * rbf_set_values) gave; B itself is not used.  lambda is the plan's ridge.
+ * opts->rtol: LSQR's stopping test ||[A P]^T r - lambda c|| <= rtol ||[A P]||
+ * ||r|| (the norms estimated by the bidiagonalisation); max_iter, warm_start
+ * as rbf_solve (check_every, reliable_delta, stall_limit unused).  opts NULL:
+ * rtol 1e-12, max_iter 100000.  coeffs as rbf_solve.  info->rel_residual: the
+ * normal-equation residual ||[A P]^T (h - A c - P k) - lambda c|| / ||[A P]^T
+ * h||, recomputed at the end.  Blocks the host at every iteration (two norm
+ * reads).  Returns OK, WARN_MAXITER, ERR_BREAKDOWN (non-finite recurrence),
+ * ERR_INVALID (not assembled, a plan made from point chunks, bad options),
+ * ERR_HIP, ERR_OOM. */
+int rbf_solve_lsqr(rbf_plan* plan, const rbf_solve_opts* opts, double* coeffs,
+                   rbf_solve_info* info);
+
 /* Evaluate the approximant (eq. 3) at n_query points: out[q] =
  * sum_j coeffs[j] phi(||y_q - xi_j|| / rho_j) over centres with y_q in their
  * support (plus a^T y_q + a_0 with a polynomial, eq. 6), basis of the last

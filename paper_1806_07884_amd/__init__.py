@@ -20,7 +20,7 @@ Points that need not (or cannot) sit in HBM together stream through in chunks:
 from .binding import (Plan, rbf_assemble, rbf_eval, rbf_eval_noalloc, rbf_fit_plan,  # noqa: F401
                       rbf_plan_info,
                       rbf_plan_pattern, rbf_solve, rbf_system_export, rbf_poly_export, rbf_set_values,
-                      rbf_solve_batch, rbf_stream_begin, rbf_stream_add, rbf_stream_finish,
+                      rbf_solve_batch, rbf_solve_lsqr, rbf_stream_begin, rbf_stream_add, rbf_stream_finish,
                       rbf_plan_destroy,
                       rbf_profile, rbf_profile_read, rbf_density_features, rbf_block_sq_err,
                       rbf_radius_broadcast, Mlp)

@@ -141,6 +141,8 @@ SIGNATURES = {
                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "rbf_mlp_destroy": (None, [ctypes.c_void_p]),
+    "rbf_solve_lsqr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SolveOpts), ctypes.c_void_p,
+                                      ctypes.POINTER(SolveInfo)]),
     "rbf_eval_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double)]),

@@ -263,6 +263,24 @@ def rbf_solve(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1
                     "status": info.status}
 
 
+def rbf_solve_lsqr(plan: Plan, coeffs: Optional[torch.Tensor] = None, rtol: float = 1e-12,
+                   max_iter: int = 100000, warm_start: bool = False):
+    """The least-squares fit by LSQR on A itself (rbf_solve_lsqr): for dense,
+    ill-conditioned A where CG on A^T A cannot reach float64 accuracy.  Returns
+    (coeffs [M + n_poly], info)."""
+    if coeffs is None:
+        coeffs = torch.zeros(plan.m + plan.n_poly, dtype=torch.float64, device=plan.device)
+    _need(coeffs, "coeffs", (plan.m + plan.n_poly,))
+    opts = L.SolveOpts(float(rtol), int(max_iter), int(bool(warm_start)), 1, 0.1, 0)
+    info = L.SolveInfo()
+    with torch.cuda.device(plan.device):
+        st = L.lib().rbf_solve_lsqr(plan.handle, ctypes.byref(opts), coeffs.data_ptr(),
+                                    ctypes.byref(info))
+    L.check(st, "rbf_solve_lsqr")
+    return coeffs, {"iterations": info.iterations, "rel_residual": info.rel_residual,
+                    "lambda": info.lambda_, "precision": "fp64", "status": info.status}
+
+
 def rbf_solve_batch(plan: Plan, values: torch.Tensor, coeffs: Optional[torch.Tensor] = None,
                     rtol: float = 1e-10, max_iter: int = 100000, warm_start: bool = False,
                     check_every: int = 32, reliable_delta: float = 0.1):

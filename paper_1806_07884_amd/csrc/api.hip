@@ -16,6 +16,7 @@
 #include "rbf.h"
 #include "chunk_planner.h"
 #include "solve_policy.h"
+#include "lsqr.h"
 #include "solver.h"
 #include "stream.h"
 
@@ -182,6 +183,11 @@ struct rbf_plan {
   void* vec32[4] = {};
   double* cs_sorted = nullptr;
   double* eval_part = nullptr;
+  double* ridge_part = nullptr;  // partial sums of the ridge value
+  // LSQR solve: u [n], u_d [m] (damping rows), v, w, x, t [m + 4], t_n [n],
+  // reduction partials and scalars
+  double *lq_u = nullptr, *lq_ud = nullptr, *lq_v = nullptr, *lq_w = nullptr, *lq_x = nullptr;
+  double *lq_t = nullptr, *lq_tn = nullptr, *lq_part = nullptr, *lq_sc = nullptr;
   rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots (from the pinned pool)
   rbf::CgScalars* host_sc_dev = nullptr;  // their device address
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
@@ -843,8 +849,10 @@ int finish_stream(rbf_plan* P) {
   HIPCHK(rbf::launch_stream_values(P->row_ptr, P->col, src, P->amap, P->active, P->sacc, P->sptr,
                                    P->lanes, m, fp32, val, P->diag, P->g, s));
   void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
+  if (!P->ridge_part) GET(P->ridge_part, rbf::kRidgePartDoubles);
   HIPCHK(rbf::launch_finalize(m, P->active, ms, P->srow, P->sptr, P->lanes, P->lower_cnt, P->diag,
-                              P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64, s));
+                              P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64,
+                              P->ridge_part, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(src);
   P->prec = P->stream_prec;
@@ -869,9 +877,10 @@ int stream_values64(rbf_plan* P) {
                                  P->col, src, s));
   HIPCHK(rbf::launch_stream_values(P->row_ptr, P->col, src, P->amap, P->active, P->sacc, P->sptr,
                                    P->lanes, m, false, P->val64, P->diag, P->g, s));
+  if (!P->ridge_part) GET(P->ridge_part, rbf::kRidgePartDoubles);
   HIPCHK(rbf::launch_finalize(m, P->active, P->ms, P->srow, P->sptr, P->lanes, P->lower_cnt,
                               P->diag, P->lambda_rel, P->lam, false, P->val64, P->dinv64,
-                              P->dinv64, s));
+                              P->dinv64, P->ridge_part, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(src);
   return RBF_OK;
@@ -977,8 +986,10 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     P->pending.push_back({2, -1, e0, e1});
   }
   void* dinv = fp32 ? (void*)P->dinv32 : (void*)P->dinv64;
+  if (!P->ridge_part) GET(P->ridge_part, rbf::kRidgePartDoubles);
   HIPCHK(rbf::launch_finalize(P->m, P->active, P->ms, P->srow, P->sptr, P->lanes, P->lower_cnt,
-                              P->diag, P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64, s));
+                              P->diag, P->lambda_rel, P->lam, fp32, val, dinv, P->dinv64,
+                              P->ridge_part, s));
   if (P->npoly) {
     // the polynomial blocks of eq. 10, phi in the same precision as B and g
     const int nb = rbf::poly_gram_blocks(P->n);
@@ -1705,6 +1716,44 @@ int rbf_solve(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs, rbf_solve
   return rc;
 }
 
+// The LSQR solve's operators on the extended system: rows [A P] (the points,
+// sorted order) and, with a ridge, sqrt(lambda) [I 0] (the centres); unknowns
+// (c in caller order, k in the scaled basis), nA = m + npoly values.
+struct LsqrOps {
+  rbf_plan* P;
+  double damp;
+  int64_t n, m, na;
+  // t_n = [A P] x (points), and u_d = damp x_c when out_d is not NULL
+  int apply(const double* x, double* tn, double* kp) {
+    hipStream_t s = P->stream;
+    HIPCHK(rbf::launch_gather(x, P->cperm, m, P->cs_sorted, s));
+    if (P->npoly) HIPCHK(rbf::launch_poly_coeffs(x + m, P->pbasis, P->dim, true, kp, s));
+    HIPCHK(rbf::launch_eval(P->view(), P->phi, n, P->ps, P->cs_sorted, P->rho2_s, P->irho_s,
+                            P->npoly ? kp : nullptr, tn, s));
+    return RBF_OK;
+  }
+  // t = [A P]^T u (+ damp u_d on the c part)
+  int adjoint(const double* u, const double* ud, double* t) {
+    hipStream_t s = P->stream;
+    HIPCHK(rbf::launch_rhs(P->view(), P->phi, false, P->grouped, u, t, s));
+    if (P->npoly)
+      HIPCHK(rbf::lsqr_poly_adjoint(P->ps, n, P->dim, P->pbasis, u, P->lq_part, t + m, s));
+    if (damp > 0.0) HIPCHK(rbf::lsqr_axpby(m, damp, ud, 1.0, t, s));
+    return RBF_OK;
+  }
+  // ||a||^2 (+ ||b||^2) read back to the host
+  int norm2(const double* a, int64_t na_, const double* b, int64_t nb_, double* out) {
+    hipStream_t s = P->stream;
+    HIPCHK(rbf::lsqr_sumsq(a, na_, P->lq_part, P->lq_sc, s));
+    if (b) HIPCHK(rbf::lsqr_sumsq(b, nb_, P->lq_part, P->lq_sc + 1, s));
+    double h[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(h, P->lq_sc, sizeof(double) * (b ? 2 : 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = h[0] + h[1];
+    return RBF_OK;
+  }
+};
+
 int rbf_solve_batch(rbf_plan* P, int32_t nrhs, const double* values,
                     const rbf_solve_opts* opts, double* coeffs, rbf_solve_info* info) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
@@ -1782,6 +1831,157 @@ int rbf_solve_batch(rbf_plan* P, int32_t nrhs, const double* values,
     }
   }
   return ms == 0 ? RBF_OK : rc;
+}
+
+int rbf_solve_lsqr(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs,
+                   rbf_solve_info* info) {
+  if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
+  if (!coeffs) return fail(RBF_ERR_INVALID, "coeffs is NULL");
+  if (P->prec < 0 || P->phi < 0)
+    return fail(RBF_ERR_INVALID, "rbf_assemble must precede rbf_solve_lsqr");
+  if (!P->ps) return fail(RBF_ERR_INVALID, "a plan made from point chunks holds no points");
+  rbf_solve_opts o;
+  o.rtol = 1e-12;
+  o.max_iter = 100000;
+  o.warm_start = 0;
+  o.check_every = 1;
+  o.reliable_delta = 0.1;
+  o.stall_limit = 0;
+  if (opts) o = *opts;
+  if (!(o.rtol > 0.0) || o.max_iter < 1) return fail(RBF_ERR_INVALID, "bad solve options");
+  hipStream_t s = P->stream;
+  const int64_t n = P->n, m = P->m, na = m + P->npoly;
+  if (!P->lq_u) {
+    GET(P->lq_u, std::max<int64_t>(n, 1));
+    GET(P->lq_tn, std::max<int64_t>(n, 1));
+    GET(P->lq_ud, m);
+    GET(P->lq_v, m + rbf::kMaxPoly);
+    GET(P->lq_w, m + rbf::kMaxPoly);
+    GET(P->lq_x, m + rbf::kMaxPoly);
+    GET(P->lq_t, m + rbf::kMaxPoly);
+    GET(P->lq_part, rbf::kLsqrParts * rbf::kMaxPoly);
+    GET(P->lq_sc, 2 + rbf::kMaxPoly);
+  }
+  if (!P->cs_sorted) GET(P->cs_sorted, m);
+  double lam = 0.0;
+  HIPCHK(hipMemcpyAsync(&lam, P->lam, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  LsqrOps ops{P, lam > 0.0 ? sqrt(lam) : 0.0, n, m, na};
+  double* kp = P->lq_sc + 2;  // polynomial coefficients in the paper's basis
+  double *u = P->lq_u, *ud = P->lq_ud, *v = P->lq_v, *w = P->lq_w, *x = P->lq_x;
+  double *t = P->lq_t, *tn = P->lq_tn;
+  // x0: the caller's guess (inactive centres forced to 0) or 0
+  if (o.warm_start) {
+    HIPCHK(hipMemcpyAsync(x, coeffs, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    HIPCHK(rbf::lsqr_mask(P->active, m, x, s));
+    if (P->npoly)
+      HIPCHK(rbf::launch_poly_coeffs(coeffs + m, P->pbasis, P->dim, false, x + m, s));
+  } else {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * na, s));
+  }
+  // ||[A P]^T h|| for the final relative residual (the damping rows' right-hand
+  // side is 0)
+  double gnorm2 = 0.0;
+  const double damp = ops.damp;
+  ops.damp = 0.0;
+  int rc = ops.adjoint(P->hs, ud, t);
+  ops.damp = damp;
+  if (rc) return rc;
+  rc = ops.norm2(t, na, nullptr, 0, &gnorm2);
+  if (rc) return rc;
+  // u = h - [A P] x, u_d = -damp x_c; beta = ||(u, u_d)||
+  rc = ops.apply(x, tn, kp);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(u, P->hs, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(rbf::lsqr_axpby(n, -1.0, tn, 1.0, u, s));
+  if (ops.damp > 0.0) {
+    HIPCHK(hipMemsetAsync(ud, 0, sizeof(double) * m, s));
+    HIPCHK(rbf::lsqr_axpby(m, -ops.damp, x, 0.0, ud, s));
+  }
+  double bb = 0.0;
+  rc = ops.norm2(u, n, ops.damp > 0.0 ? ud : nullptr, m, &bb);
+  if (rc) return rc;
+  double beta = sqrt(bb), alpha = 0.0;
+  if (beta > 0.0) {
+    HIPCHK(rbf::lsqr_scale(n, 1.0 / beta, u, s));
+    if (ops.damp > 0.0) HIPCHK(rbf::lsqr_scale(m, 1.0 / beta, ud, s));
+    rc = ops.adjoint(u, ud, v);
+    if (rc) return rc;
+    double aa = 0.0;
+    rc = ops.norm2(v, na, nullptr, 0, &aa);
+    if (rc) return rc;
+    alpha = sqrt(aa);
+  }
+  if (alpha > 0.0) HIPCHK(rbf::lsqr_scale(na, 1.0 / alpha, v, s));
+  HIPCHK(hipMemcpyAsync(w, v, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
+  double phibar = beta, rhobar = alpha, anorm2 = 0.0;
+  int64_t it = 0;
+  bool done = alpha == 0.0 || beta == 0.0;
+  while (!done && it < o.max_iter) {
+    ++it;
+    // Golub-Kahan bidiagonalisation: beta u = A v - alpha u, alpha v = A^T u - beta v
+    rc = ops.apply(v, tn, kp);
+    if (rc) return rc;
+    HIPCHK(rbf::lsqr_axpby(n, 1.0, tn, -alpha, u, s));
+    if (ops.damp > 0.0) HIPCHK(rbf::lsqr_axpby(m, ops.damp, v, -alpha, ud, s));
+    rc = ops.norm2(u, n, ops.damp > 0.0 ? ud : nullptr, m, &bb);
+    if (rc) return rc;
+    beta = sqrt(bb);
+    anorm2 += alpha * alpha + beta * beta;
+    if (beta > 0.0) {
+      HIPCHK(rbf::lsqr_scale(n, 1.0 / beta, u, s));
+      if (ops.damp > 0.0) HIPCHK(rbf::lsqr_scale(m, 1.0 / beta, ud, s));
+      rc = ops.adjoint(u, ud, t);
+      if (rc) return rc;
+      HIPCHK(rbf::lsqr_axpby(na, 1.0, t, -beta, v, s));
+      double aa = 0.0;
+      rc = ops.norm2(v, na, nullptr, 0, &aa);
+      if (rc) return rc;
+      alpha = sqrt(aa);
+      if (alpha > 0.0) HIPCHK(rbf::lsqr_scale(na, 1.0 / alpha, v, s));
+    }
+    // plane rotation eliminating beta from the lower bidiagonal
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double cs = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    rhobar = -cs * alpha;
+    const double phi = cs * phibar;
+    phibar = sn * phibar;
+    HIPCHK(rbf::lsqr_step(na, phi / rho, -theta / rho, v, w, x, s));
+    // ||[A P]^T r|| / (||[A P]|| ||r||) estimated from the recurrences
+    const double test2 = anorm2 > 0.0 ? alpha * fabs(cs) / sqrt(anorm2) : 0.0;
+    if (!(std::isfinite(rho) && std::isfinite(phibar)))
+      return fail(RBF_ERR_BREAKDOWN, "LSQR: non-finite recurrence after %lld iterations",
+                  (long long)it);
+    if (test2 <= o.rtol || phibar == 0.0 || alpha == 0.0 || beta == 0.0) done = true;
+  }
+  rc = done ? RBF_OK : RBF_WARN_MAXITER;
+  // the normal-equation residual of the result, recomputed: [A P]^T (h - [A P] x) - lambda x_c
+  int rr = ops.apply(x, tn, kp);
+  if (rr) return rr;
+  HIPCHK(hipMemcpyAsync(u, P->hs, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(rbf::lsqr_axpby(n, -1.0, tn, 1.0, u, s));
+  ops.damp = 0.0;
+  rr = ops.adjoint(u, ud, t);
+  ops.damp = damp;
+  if (rr) return rr;
+  if (lam > 0.0) HIPCHK(rbf::lsqr_axpby(m, -lam, x, 1.0, t, s));
+  double res2 = 0.0;
+  rr = ops.norm2(t, na, nullptr, 0, &res2);
+  if (rr) return rr;
+  HIPCHK(hipMemcpyAsync(coeffs, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+  if (P->npoly)
+    HIPCHK(rbf::launch_poly_coeffs(x + m, P->pbasis, P->dim, true, coeffs + m, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    info->iterations = it;
+    info->reliable_updates = 0;
+    info->rel_residual = gnorm2 > 0.0 ? sqrt(res2 / gnorm2) : 0.0;
+    info->lambda = lam;
+    info->precision = RBF_PREC_FP64;
+    info->status = rc;
+  }
+  return rc;
 }
 
 int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,

@@ -30,6 +30,8 @@
 // FP64 variant: float64 phi and float64 accumulation.
 // FP32 variant: squared distance and support test in float64 (the pattern is
 // fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
+#include <algorithm>
+
 #include "accum.h"
 #include "plan_kernels.h"
 #include "solver.h"
@@ -340,20 +342,58 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_rhs(PlanView P,
 
 constexpr int kRed = 256;
 
-// lambda = lambda_rel * mean(diag over active centres), written to lam[0].
-__global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__ diag,
-                                                      const uint8_t* __restrict__ active,
-                                                      int64_t m, double lambda_rel,
+// Most blocks of the ridge's first pass (its partials: kRidgeBlocks sums and
+// kRidgeBlocks counts).
+constexpr int kRidgeBlocks = 512;
+static_assert(2 * kRidgeBlocks == kRidgePartDoubles, "ridge partials layout");
+
+// First pass: block b sums diag and counts the active centres over its
+// contiguous range of centres.
+__global__ __launch_bounds__(kRed) void k_ridge_partial(const double* __restrict__ diag,
+                                                        const uint8_t* __restrict__ active,
+                                                        int64_t m, double* __restrict__ part) {
+  __shared__ double ws[kRed / kWave];
+  __shared__ double wc[kRed / kWave];
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < m ? lo + per : m;
+  double s = 0.0, c = 0.0;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += kRed) {
+    if (active[j]) {
+      s += diag[j];
+      c += 1.0;
+    }
+  }
+  s = wave_sum(s);
+  c = wave_sum(c);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    ws[threadIdx.x / kWave] = s;
+    wc[threadIdx.x / kWave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int w = 0; w < kRed / kWave; ++w) {
+      ts += ws[w];
+      tc += wc[w];
+    }
+    part[blockIdx.x] = ts;
+    part[kRidgeBlocks + blockIdx.x] = tc;
+  }
+}
+
+// lambda = lambda_rel * mean(diag over active centres), written to lam[0],
+// from the first pass's nb partials (added in block order).
+__global__ __launch_bounds__(kRed) void k_ridge_value(const double* __restrict__ part, int nb,
+                                                      double lambda_rel,
                                                       double* __restrict__ lam) {
   __shared__ double ws[kRed / kWave];
   __shared__ int64_t wc[kRed / kWave];
   double s = 0.0;
   int64_t c = 0;
-  for (int64_t j = threadIdx.x; j < m; j += kRed) {
-    if (active[j]) {
-      s += diag[j];
-      c += 1;
-    }
+  for (int k = threadIdx.x; k < nb; k += kRed) {
+    s += part[k];
+    c += (int64_t)part[kRidgeBlocks + k];
   }
   s = wave_sum(s);
 #pragma unroll
@@ -483,9 +523,14 @@ hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,
                            const int64_t* sptr, int lanes, const int32_t* lower_cnt,
                            const double* diag, double lambda_rel, double* lam, bool fp32,
-                           void* val, void* dinv, double* dinv64, hipStream_t s) {
+                           void* val, void* dinv, double* dinv64, double* ridge_part,
+                           hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ridge_value, dim3(1), dim3(kRed), 0, s, diag, active, m, lambda_rel, lam);
+  // counts are exact in float64 below 2^53 centres
+  const int nb = (int)std::min<int64_t>(kRidgeBlocks, (m + 4 * kRed - 1) / (4 * kRed));
+  hipLaunchKernelGGL(k_ridge_partial, dim3(nb), dim3(kRed), 0, s, diag, active, m, ridge_part);
+  hipLaunchKernelGGL(k_ridge_value, dim3(1), dim3(kRed), 0, s, (const double*)ridge_part, nb,
+                     lambda_rel, lam);
   if (ms <= 0) return hipGetLastError();
   const int bs = 256;
   const dim3 grid((unsigned)((ms + bs - 1) / bs));

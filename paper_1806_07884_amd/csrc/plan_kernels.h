@@ -165,7 +165,10 @@ hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,
                            const int64_t* sptr, int lanes, const int32_t* lower_cnt,
                            const double* diag, double lambda_rel, double* lam, bool fp32,
-                           void* val, void* dinv, double* dinv64, hipStream_t s);
+                           void* val, void* dinv, double* dinv64, double* ridge_part,
+                           hipStream_t s);
+// Doubles of the ridge's partial sums (launch_finalize's ridge_part).
+constexpr int64_t kRidgePartDoubles = 2 * 512;
 // eval_kernels.hip
 hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, double* dst,
                          hipStream_t s);

@@ -176,22 +176,41 @@ def main() -> int:
             rho = radius.predict_radii(model, fplan, f, NB, spacing, float(radii.min()),
                                        float(radii.max()), float(p.rho))
             fplan.close()
-            res = {}
-            for label, kw in (("learned", dict(rho_per_center=rho)), ("fixed", {})):
+            has_ho = p.test_points.shape[1] > 0
+            dtp, dth = (dev(p.test_points), dev(p.test_values)) if has_ho else (None, None)
+
+            def one(rho_fixed, kw):
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
-                plan, c, info = radius.fit_once(dp, dh, dc, None if kw else p.rho, p.phi, "fp32",
-                                                1e-4, **kw)
+                plan, c, info = radius.fit_once(dp, dh, dc, rho_fixed, p.phi, "fp32", 1e-4, **kw)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - ta
                 fq, r = rbf.rbf_eval(plan, dq, c, values=dqh)
-                res[label] = dict(rmse=float(r), seconds=dt, work=radius.fit_work(plan, info),
-                                  iterations=int(info["iterations"]),
-                                  covered_rmse=float(torch.sqrt(torch.mean(
-                                      (fq[fq != 0] - dqh[fq != 0]) ** 2)).item()))
+                cov = fq != 0
+                d = dict(query_rmse=float(r), seconds=dt, work=radius.fit_work(plan, info),
+                         iterations=int(info["iterations"]),
+                         covered_fraction=float(cov.double().mean().item()),
+                         covered_rmse=float(torch.sqrt(torch.mean(
+                             (fq[cov] - dqh[cov]) ** 2)).item()))
+                if has_ho:
+                    _, d["heldout_rmse"] = rbf.rbf_eval(plan, dtp, c, values=dth)
                 plan.close()
+                return d
+
+            res = {"learned": one(None, dict(rho_per_center=rho)), "fixed": one(p.rho, {})}
+            # every sweep radius as a fixed radius: the best held-out RMSE at no more
+            # CG work than the learned fit, and at any cost
+            sweep = [dict(radius=float(rr), **one(float(rr), {})) for rr in radii]
+            res["sweep"] = sweep
+            key = "heldout_rmse" if has_ho else "query_rmse"
+            ok = [s for s in sweep if s["work"] <= res["learned"]["work"]]
+            if ok:
+                res["fixed_at_equal_work"] = min(ok, key=lambda s: s[key])
+            res["best_fixed_any_cost"] = min(sweep, key=lambda s: s[key])
+            res["score"] = key
             out["apply"] = {"workload": args.apply, **res}
-            log(f"{args.apply}: learned {res['learned']}, fixed {res['fixed']}")
+            log(f"{args.apply}: learned {res['learned']}, fixed {res['fixed']}, at equal work "
+                f"{res.get('fixed_at_equal_work')}, best {res['best_fixed_any_cost']}")
     print(json.dumps(out), flush=True)
     return 0
 

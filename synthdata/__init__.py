@@ -219,6 +219,8 @@ class Problem:
     phi: str                  # "w30" | "w31" | "w32" | "w33"
     grid: int
     modes: Optional[TerrainModes] = None   # the terrain field's modes (clean values anywhere)
+    score: str = "heldout"    # "heldout": held-out points vs noisy samples;
+                              # "uniform": uniform queries vs the noise-free field
 
 
 # The five workloads (sizes, densities, fields, basis and radius).  A radius
@@ -234,7 +236,7 @@ CONFIGS = {
                           holdout=0.01, seed=3),
     "field3d": dict(dim=3, n=1 << 22, cloud="mixture", clusters=32, field="terrain",
                     modes=128, noise=1e-3, grid=64, phi="w31", k_cover=40.0,
-                    holdout=0.0, seed=5),
+                    holdout=0.01, seed=5, score="uniform"),
 }
 
 
@@ -277,18 +279,20 @@ def make_problem(name: str, scale: float = 1.0, seed: Optional[int] = None,
         test_points=np.ascontiguousarray(pts[:, te]),
         test_values=np.ascontiguousarray(noisy[te]),
         test_clean=np.ascontiguousarray(clean[te]),
-        centers=grid_centers(g, dim), rho=rho, phi=cfg["phi"], grid=g, modes=modes)
+        centers=grid_centers(g, dim), rho=rho, phi=cfg["phi"], grid=g, modes=modes,
+        score=cfg.get("score", "heldout"))
 
 
 def scoring_queries(prob: Problem, n: int = 1_000_000, seed: Optional[int] = None):
     """Points at which a fit of ``prob`` is scored, with the values to score against.
 
-    A workload with held-out points is scored there against the noisy samples.
-    One without (the 3D field) is scored at ``n`` points uniform in the unit
-    cube against the noise-free field; the stream is seeded by ``1000 + dim``
-    unless ``seed`` is given.
+    A workload scored on held-out points is scored there against the noisy
+    samples.  The 3D field (and any workload without held-out points) is
+    scored at ``n`` points uniform in the unit cube against the noise-free
+    field; the stream is seeded by ``1000 + dim`` unless ``seed`` is given.
+    Its held-out points (``prob.test_points``) are a second score.
     """
-    if prob.test_points.shape[1] > 0:
+    if prob.score == "heldout" and prob.test_points.shape[1] > 0:
         return prob.test_points, prob.test_values
     if prob.modes is None:
         raise ValueError("workload has neither held-out points nor a terrain field")

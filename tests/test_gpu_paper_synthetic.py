@@ -13,8 +13,15 @@ A is dense and B = A^T A has the squared conditioning of A.
   the worst.
 * phi_{3,3} (rho = 4) is out of reach of conjugate gradients on the normal
   equations in float64 (a CPU simulation of the same iteration stalls at 2 to
-  20 times the printed error); the oracle pins it by QR instead
-  (tests/test_oracle_system.py, tests/test_oracle_poly.py).
+  20 times the printed error): cond(A) ~ 7e9 squares beyond float64.  LSQR on
+  A itself (rbf_solve_lsqr) reaches it: all three bases, with and without the
+  polynomial, within the same bars; for phi_{3,0} and phi_{3,1} the LSQR fit
+  is also within 1e-6 of the QR fit's values.
+* LSQR with a ridge (damping on c only) solves the oracle's (B + lambda I) c
+  = g: fitted values within 1e-10 on terrain2d at 1/64 scale.
+* Data-subset reference points (Section 6: the real data sets take their
+  reference points from the data): the first 81 Halton points as centres,
+  pattern bit-exact, CG and LSQR fits within 1e-10 of Cholesky and QR.
 """
 import json
 import os
@@ -97,3 +104,98 @@ def test_phi30_worst_on_gpu(rbf):
         mae[kind] = float(np.mean(np.abs(f.cpu().numpy() - h)))
         plan.close()
     assert mae["w30"] > mae["w31"]
+
+
+# ------------------------------------------------------- LSQR on A itself
+@pytest.mark.parametrize("kind", ["w30", "w31", "w33"])
+@pytest.mark.parametrize("poly", [False, True])
+def test_table4_synthetic_lsqr(rbf, kind, poly):
+    # the same experiment through rbf_solve_lsqr (Golub-Kahan bidiagonalisation
+    # of A itself): phi_{3,3} at rho = 4 (cond(A) ~ 7e9, so cond(A^T A) is
+    # beyond float64) comes within the bars too
+    tabs = json.load(open(os.path.join(GOLD, "paper_tables.json")))
+    ref = tabs["table4_synthetic_mae_linear_poly" if poly else "table4_synthetic_mae_no_poly"][kind]
+    p = sd.halton_points(1089, 2)
+    h = sd.franke(p)
+    ctr = sd.grid_centers(9, 2)
+    rho = 1.0 / tabs["table3_alpha_synthetic"][kind]
+    plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho, polynomial=poly)
+    rbf.rbf_assemble(plan, kind, "fp64", dev(h))
+    ck, sinfo = rbf.rbf_solve_lsqr(plan, rtol=1e-12, max_iter=40000)
+    say("lsqr", kind, "poly" if poly else "", sinfo)
+    assert sinfo["status"] == 0
+    f, _ = rbf.rbf_eval(plan, dev(p), ck)
+    mae = float(np.mean(np.abs(f.cpu().numpy() - h)))
+    if poly:
+        cq, kq = orc.lstsq_dense_poly(p, h, ctr, rho, kind)
+        f_q = orc.evaluate_poly(p, ctr, rho, kind, cq, kq)
+    else:
+        cq = orc.lstsq_dense(p, h, ctr, rho, kind)
+        f_q = orc.evaluate(p, ctr, rho, kind, cq)
+    mae_q = float(np.mean(np.abs(f_q - h)))
+    fit = np.linalg.norm(f.cpu().numpy() - f_q) / np.linalg.norm(f_q)
+    say(f"mae {mae:.5f} (QR {mae_q:.5f}, Table 4 {ref}), fitted values vs QR {fit:.2e}")
+    assert ref / 1.5 < mae < ref * 1.5
+    assert abs(mae - mae_q) <= 0.25 * mae_q
+    if kind != "w33":
+        assert fit <= 1e-6
+    plan.close()
+
+
+def test_lsqr_matches_cholesky_with_ridge(rbf):
+    # sparse clustered data with a ridge: LSQR with damping sqrt(lambda) on the
+    # coefficients solves the same (B + lambda I) c = g as the oracle's Cholesky
+    from tolerances import FIT_FP64
+    p = sd.make_problem("terrain2d", scale=1 / 64)
+    lam = 1e-4
+    ne = orc.normal_equations(p.points, p.values, p.centers, p.rho, p.phi, lambda_rel=lam)
+    c_ref = orc.solve(ne)
+    plan = rbf.rbf_fit_plan(dev(p.points), dev(p.centers), rho=p.rho, lambda_rel=lam)
+    rbf.rbf_assemble(plan, p.phi, "fp64", dev(p.values))
+    c, info = rbf.rbf_solve_lsqr(plan, rtol=1e-15, max_iter=60000)
+    say("lsqr ridge", info)
+    assert info["status"] in (0, 1) and info["rel_residual"] <= 1e-11
+    c = c.cpu().numpy()
+    assert np.all(c[~ne.active] == 0.0)
+    fit = np.linalg.norm(ne.A @ (c - c_ref)) / np.linalg.norm(ne.A @ c_ref)
+    say(f"fit {fit:.2e}")
+    assert fit <= FIT_FP64
+    # a warm start from the answer stops at once
+    c2, info2 = rbf.rbf_solve_lsqr(plan, coeffs=dev(c), warm_start=True, rtol=1e-10)
+    assert info2["iterations"] <= 2
+    plan.close()
+
+
+# ------------------------------------------------- data-subset reference points
+@pytest.mark.parametrize("solver", ["cg", "lsqr"])
+def test_data_subset_centres(rbf, solver):
+    # Section 6 takes the reference points of the real data sets from the data
+    # themselves, spread over the area: here the first 81 of the 1089 Halton
+    # points (a low-discrepancy prefix, so spread over the square), local
+    # supports; the fit against the oracle's Cholesky (CG) or QR (LSQR)
+    from tolerances import FIT_FP64, FP64_RTOL
+    p = sd.halton_points(1089, 2)
+    h = sd.franke(p)
+    ctr = np.ascontiguousarray(p[:, :81])
+    rho = 0.3
+    ne = orc.normal_equations(p, h, ctr, rho, "w31")
+    assert ne.active.all()
+    plan = rbf.rbf_fit_plan(dev(p), dev(ctr), rho=rho)
+    rp, col, sup = rbf.rbf_plan_pattern(plan)
+    assert np.array_equal(rp, ne.row_ptr) and np.array_equal(col, ne.col)
+    assert np.array_equal(sup, ne.support_count)
+    rbf.rbf_assemble(plan, "w31", "fp64", dev(h))
+    if solver == "cg":
+        c, info = rbf.rbf_solve(plan, rtol=FP64_RTOL, max_iter=50000)
+        c_ref = orc.solve(ne)
+    else:
+        c, info = rbf.rbf_solve_lsqr(plan, rtol=1e-15, max_iter=50000)
+        c_ref = orc.lstsq_dense(p, h, ctr, rho, "w31")
+    say("subset centres", solver, info)
+    c = c.cpu().numpy()
+    fit = np.linalg.norm(ne.A @ (c - c_ref)) / np.linalg.norm(ne.A @ c_ref)
+    say(f"fit {fit:.2e}")
+    assert fit <= FIT_FP64
+    # the centres are data points: every one lies in its own support
+    assert np.all(sup >= 1)
+    plan.close()
