@@ -182,23 +182,40 @@ struct Batch {
 };
 
 // HALO: the entries' LDS slots (hslot) instead of their column deltas.
+// raw_batch loads a batch as stored; mask_batch then drops the steps past the
+// slice's end (index = the row itself, value 0).  They are apart so that the
+// first batch of a slice, loaded before the kernel's reduction, is only waited
+// for where it is used.
 template <typename VT, typename XT, typename CT, bool HALO = false>
-__device__ __forceinline__ void load_batch(const CgMatrix& A, int64_t base, int32_t rowc, int st,
-                                           int steps, Batch<XT, kBatchH<XT, HALO>>& b) {
+__device__ __forceinline__ void raw_batch(const CgMatrix& A, int64_t base, int st,
+                                          Batch<XT, kBatchH<XT, HALO>>& b) {
   const CT* __restrict__ col = static_cast<const CT*>(A.col);
   const int16_t* __restrict__ slot = A.hslot;
   const VT* __restrict__ val = static_cast<const VT*>(A.val);
   // Loads are unconditional: past the slice's end they read the next slice or
-  // the zeroed tail of the arrays (kSellTail), and the select drops them.
+  // the zeroed tail of the arrays (kSellTail), and the mask drops them.
 #pragma unroll
   for (int t = 0; t < kBatchH<XT, HALO>; ++t) {
     const int64_t o = base + (int64_t)(st + t) * kWave;
-    const int32_t c = HALO ? (int32_t)slot[o] : (int32_t)col[o];
-    const XT v = (XT)val[o];
-    const bool in = st + t < steps;
-    b.l[t] = HALO ? (in ? c : 0) : rowc + (in ? c : 0);
-    b.v[t] = in ? v : (XT)0;
+    b.l[t] = HALO ? (int32_t)slot[o] : (int32_t)col[o];
+    b.v[t] = (XT)val[o];
   }
+}
+template <typename XT, bool HALO = false>
+__device__ __forceinline__ void mask_batch(int32_t rowc, int st, int steps,
+                                           Batch<XT, kBatchH<XT, HALO>>& b) {
+#pragma unroll
+  for (int t = 0; t < kBatchH<XT, HALO>; ++t) {
+    const bool in = st + t < steps;
+    b.l[t] = HALO ? (in ? b.l[t] : 0) : rowc + (in ? b.l[t] : 0);
+    b.v[t] = in ? b.v[t] : (XT)0;
+  }
+}
+template <typename VT, typename XT, typename CT, bool HALO = false>
+__device__ __forceinline__ void load_batch(const CgMatrix& A, int64_t base, int32_t rowc, int st,
+                                           int steps, Batch<XT, kBatchH<XT, HALO>>& b) {
+  raw_batch<VT, XT, CT, HALO>(A, base, st, b);
+  mask_batch<XT, HALO>(rowc, st, steps, b);
 }
 
 // One slice of a wave: its geometry and its first batch, loaded before the
@@ -220,7 +237,7 @@ __device__ __forceinline__ void open_slice(int64_t m, int64_t slice, const CgMat
   h.rowc = (int32_t)(h.row < m ? h.row : m - 1);
   h.base = A.sptr[slice] + lane;
   h.steps = A.slen[slice] / L;
-  load_batch<VT, XT, CT, HALO>(A, h.base, h.rowc, 0, h.steps, h.b);
+  raw_batch<VT, XT, CT, HALO>(A, h.base, 0, h.b);  // masked in finish_slice
 }
 
 // Row sum of an opened slice, complete in the lane with (lane % L) == 0:
@@ -233,6 +250,7 @@ __device__ __forceinline__ XT finish_slice(const SliceHead<XT, HALO>& h, const C
 #pragma unroll
   for (int t = 0; t < U; ++t) acc[t] = (XT)0;
   Batch<XT, U> cur = h.b;
+  mask_batch<XT, HALO>(h.rowc, 0, h.steps, cur);
   for (int st = U;; st += U) {
     const bool more = st < h.steps;
     Batch<XT, U> nxt;
@@ -382,9 +400,24 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
 #pragma unroll
   for (int t = 0; t < NP; ++t) red[t] = 0.0;
   if (!fixed) {
-    for (int k = threadIdx.x; k < n_in; k += BS) {
+    // every partial this thread adds is loaded before the first add (one
+    // round trip instead of one per block stride); added in the same order
+    // (the loads are unconditional, from a clamped block index, so that no
+    // branch separates them; the surplus ones are dropped by the select)
+    constexpr int KB = (kCgMaxBlocks + BS - 1) / BS;
+    double pv[KB][NP];
 #pragma unroll
-      for (int t = 0; t < NP; ++t) red[t] += part_in[NP * k + t];
+    for (int i = 0; i < KB; ++i) {
+      const int k = (int)threadIdx.x + i * BS;
+      const int kc = k < n_in ? k : n_in - 1;
+#pragma unroll
+      for (int t = 0; t < NP; ++t) pv[i][t] = part_in[NP * kc + t];
+    }
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      const bool in = (int)threadIdx.x + i * BS < n_in;
+#pragma unroll
+      for (int t = 0; t < NP; ++t) red[t] += in ? pv[i][t] : 0.0;
     }
   }
   const double gam_prev = sc->gam[q ^ 1];
