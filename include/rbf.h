@@ -104,6 +104,11 @@ typedef struct {
  * global memory instead of staging the slices' neighbourhoods in LDS (same
  * results bit for bit; for comparisons). */
 #define RBF_PLAN_NO_STAGING 1u
+/* rbf_plan_desc.flags: assemble B row by row (one workgroup per centre, the
+ * supported points streamed per row) instead of by point tiles (products of
+ * each tile's basis values on the matrix cores); the same values up to the
+ * order of the float64 sums, for comparisons. */
+#define RBF_PLAN_ROW_ASSEMBLY 2u
 
 typedef struct {
   int32_t dim;
@@ -125,6 +130,11 @@ typedef struct {
   int32_t solver_staged;        /* most distinct columns one slice stages in LDS
                                    for the float64 CG iteration (0: not staged;
                                    built at the plan's first float64 solve) */
+  int32_t assembly_tiles;       /* 1: the last assembly went by point tiles,
+                                   0: by rows (or none yet) */
+  int32_t tile_window;          /* most active centres within reach of one hash
+                                   cell (set at the first assembly; point tiles
+                                   need at most 256 in 2D, 384 in 3D) */
 } rbf_plan_stats;
 
 typedef struct {

@@ -23,6 +23,7 @@ RBF_ERR_OOM = -6
 
 KERNEL = {"cg_iter": 0, "cg_iter_batch": 1, "assemble": 2}
 PLAN_NO_STAGING = 1
+PLAN_ROW_ASSEMBLY = 2
 MLP_PARAMS = 5313
 MLP_INPUTS = 16
 MAX_RADII = 8
@@ -50,7 +51,8 @@ class PlanStats(ctypes.Structure):
                 ("support_max", ctypes.c_int32), ("row_max", ctypes.c_int32),
                 ("cell_size", ctypes.c_double), ("solver_entries", ctypes.c_int64),
                 ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32),
-                ("n_poly", ctypes.c_int32), ("solver_staged", ctypes.c_int32)]
+                ("n_poly", ctypes.c_int32), ("solver_staged", ctypes.c_int32),
+                ("assembly_tiles", ctypes.c_int32), ("tile_window", ctypes.c_int32)]
 
 
 class StreamDesc(ctypes.Structure):

@@ -73,12 +73,15 @@ def _make_allocator(device: torch.device, stream: torch.cuda.Stream):
 def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[float] = None,
                  rho_per_center: Optional[torch.Tensor] = None, min_support: int = 1,
                  lambda_rel: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
-                 polynomial: bool = False, staging: bool = True) -> Plan:
+                 polynomial: bool = False, staging: bool = True,
+                 row_assembly: bool = False) -> Plan:
     """Hash, support counts and the sparsity pattern of B (rbf_fit_plan).
 
     polynomial: linear polynomial reproduction (coefficients c, then k = (a, a_0)).
     staging: False sets RBF_PLAN_NO_STAGING (the CG iteration gathers from
     global memory; same results).
+    row_assembly: True sets RBF_PLAN_ROW_ASSEMBLY (B assembled row by row
+    instead of by point tiles; same values up to the order of the sums).
     """
     _need(points, "points")
     if points.dim() != 2:
@@ -102,7 +105,8 @@ def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[floa
                       float(rho) if rho is not None else 0.0,
                       rho_per_center.data_ptr() if rho_per_center is not None else None,
                       int(min_support), float(lambda_rel), int(bool(polynomial)),
-                      0 if staging else L.PLAN_NO_STAGING)
+                      (0 if staging else L.PLAN_NO_STAGING)
+                      | (L.PLAN_ROW_ASSEMBLY if row_assembly else 0))
     with torch.cuda.device(plan.device):
         st = L.lib().rbf_fit_plan(ctypes.byref(desc), ctypes.byref(plan._alloc),
                                   plan._stream_handle(), ctypes.byref(plan.handle))

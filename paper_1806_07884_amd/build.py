@@ -22,7 +22,7 @@ ARCH = "gfx950"
 
 SOURCES = ["sort_scan.hip", "plan_kernels.hip", "assemble_kernels.hip", "cg_kernels.hip",
            "eval_kernels.hip", "mlp_kernels.hip", "poly_kernels.hip", "halo_kernels.hip",
-           "stream_kernels.hip", "lsqr_kernels.hip",
+           "stream_kernels.hip", "lsqr_kernels.hip", "tile_kernels.hip",
            "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -19,6 +19,7 @@
 #include "lsqr.h"
 #include "solver.h"
 #include "stream.h"
+#include "tiles.h"
 
 namespace {
 
@@ -154,7 +155,18 @@ struct rbf_plan {
   float* dinv32 = nullptr;
   int phi = -1;
   int prec = -1;
-  bool grouped = false;  // the assembly took the grouped path
+  bool grouped = false;  // the row assembly took the grouped path (and g's sums follow it)
+  // assembly by point tiles (tile_kernels.hip), set up at the first assembly
+  bool row_assembly = false;  // RBF_PLAN_ROW_ASSEMBLY: always assemble by rows
+  int tile_state = 0;         // 0 not set up, 1 usable, 2 a window exceeds the limit
+  bool tiled = false;         // the last assembly took the tiles
+  int4* tiles = nullptr;
+  int64_t ntiles = 0;
+  int32_t* wids = nullptr;    // the cells' windows (caller indices), tiles point into it
+  int32_t tile_window = 0;    // most active centres within reach of one cell
+  unsigned long long* tacc = nullptr;  // [nnz_full] fixed-point sums
+  int32_t* kexp = nullptr;             // [m] their per-row exponents
+  int32_t* tile_err = nullptr;
   // solver workspace
   double* xhi = nullptr;
   double* r64 = nullptr;
@@ -949,6 +961,54 @@ int read_scalars(rbf_plan* P) {
   return RBF_OK;
 }
 
+// The point tiles of a resident plan, their windows' bound and the upper
+// entries' offsets; tile_state 2 when a window would exceed the kernel's limit
+// (the rows path is then used).
+int tile_setup(rbf_plan* P) {
+  hipStream_t s = P->stream;
+  const rbf::PlanView v = P->view();
+  const int64_t nc = P->grid.ncell;
+  uint32_t *cnt, *off, *wcnt, *woff;
+  int32_t* maxw;
+  GET(cnt, nc + 1);
+  GET(off, nc + 1);
+  GET(wcnt, nc + 1);
+  GET(woff, nc + 1);
+  GET(maxw, 1);
+  void* tmp = P->alloc_bytes(rbf::scan_temp_bytes(nc + 1));
+  if (!tmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
+  HIPCHK(hipMemsetAsync(maxw, 0, sizeof(int32_t), s));
+  HIPCHK(rbf::launch_tile_count(v, P->cell_size, cnt, wcnt, maxw, s));
+  HIPCHK(rbf::exclusive_scan(cnt, off, nc + 1, tmp, s));
+  HIPCHK(rbf::exclusive_scan(wcnt, woff, nc + 1, tmp, s));
+  uint32_t nt = 0, nwin = 0;
+  int32_t mw = 0;
+  HIPCHK(hipMemcpyAsync(&nt, off + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&nwin, woff + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&mw, maxw, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->tile_window = mw;
+  P->ntiles = nt;
+  P->tile_state = 2;
+  if (mw <= rbf::tile_window_max(P->dim) && nt > 0) {
+    GET(P->tiles, (int64_t)nt);
+    GET(P->wids, std::max<int64_t>(nwin, 1));
+    HIPCHK(rbf::launch_tile_fill(v, P->cell_size, off, woff, P->tiles, P->wids, s));
+    GET(P->tacc, std::max<int64_t>(P->nnz_full, 1));
+    GET(P->kexp, P->m);
+    GET(P->tile_err, 1);
+    P->tile_state = 1;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  P->release(tmp);
+  P->release(maxw);
+  P->release(woff);
+  P->release(wcnt);
+  P->release(off);
+  P->release(cnt);
+  return RBF_OK;
+}
+
 int assemble_into(rbf_plan* P, int phi, bool fp32) {
   hipStream_t s = P->stream;
   rbf::PlanView v = P->view();
@@ -979,8 +1039,25 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
   const double upper_mean =
       (double)(P->nnz_full + P->ms) / (2.0 * (double)std::max<int64_t>(P->ms, 1));
   P->grouped = upper_mean > 64.0;
-  HIPCHK(rbf::launch_assemble(v, phi, fp32, P->grouped, P->hs, P->row_ptr, P->lower_cnt,
-                              P->col, P->sptr, P->lanes, val, P->g, P->diag, s));
+  if (!P->row_assembly && P->tile_state == 0 && P->pcs) {
+    const int rc = tile_setup(P);
+    if (rc) return rc;
+  }
+  P->tiled = !P->row_assembly && P->tile_state == 1;
+  if (P->tiled) {
+    // g by the rows' support stream (the same sums as the rows path gives),
+    // with the rows' fixed-point exponents; then B by point tiles
+    HIPCHK(hipMemsetAsync(P->tacc, 0, sizeof(unsigned long long) * P->nnz_full, s));
+    HIPCHK(hipMemsetAsync(P->tile_err, 0, sizeof(int32_t), s));
+    HIPCHK(rbf::launch_rhs(v, phi, fp32, P->grouped, P->hs, P->g, s, P->kexp));
+    HIPCHK(rbf::launch_tile_assemble(v, phi, fp32, P->tiles, P->ntiles, P->wids, P->row_ptr,
+                                     P->col, P->kexp, P->tacc, P->tile_err, s));
+    HIPCHK(rbf::launch_tile_finish(v, fp32, P->row_ptr, P->lower_cnt, P->col, P->kexp, P->tacc,
+                                   P->sptr, P->lanes, val, P->diag, s));
+  } else {
+    HIPCHK(rbf::launch_assemble(v, phi, fp32, P->grouped, P->hs, P->row_ptr, P->lower_cnt,
+                                P->col, P->sptr, P->lanes, val, P->g, P->diag, s));
+  }
   if (P->prof_on) {
     HIPCHK(hipEventRecord(e1, s));
     P->pending.push_back({2, -1, e0, e1});
@@ -1003,6 +1080,13 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     if (fp32 && !P->q32) GET(P->q32, (int64_t)P->npoly * std::max<int64_t>(P->ms, 1));
     HIPCHK(rbf::launch_poly_system(v, phi, P->pbasis, P->ms, P->hs, P->q64,
                                    fp32 ? P->q32 : nullptr, P->gram_part, nb, P->psys, s));
+  }
+  if (P->tiled) {
+    int32_t te = 0;
+    HIPCHK(hipMemcpyAsync(&te, P->tile_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (te)
+      return fail(RBF_ERR_HIP, "internal error in the tile assembly (window overflow)");
   }
   return RBF_OK;
 }
@@ -1367,7 +1451,8 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
   if (d->min_support < 1) return fail(RBF_ERR_INVALID, "min_support must be >= 1");
   if (d->polynomial != 0 && d->polynomial != 1)
     return fail(RBF_ERR_INVALID, "polynomial must be 0 (none) or 1 (linear)");
-  if (d->flags & ~RBF_PLAN_NO_STAGING) return fail(RBF_ERR_INVALID, "unknown plan flags");
+  if (d->flags & ~(RBF_PLAN_NO_STAGING | RBF_PLAN_ROW_ASSEMBLY))
+    return fail(RBF_ERR_INVALID, "unknown plan flags");
   if (!(d->lambda_rel >= 0.0 && isfinite(d->lambda_rel)))
     return fail(RBF_ERR_INVALID, "lambda_rel must be finite and >= 0");
   if (allocator && (!allocator->alloc || !allocator->release))
@@ -1385,6 +1470,7 @@ int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* s
   P->lambda_rel = d->lambda_rel;
   P->npoly = d->polynomial ? d->dim + 1 : 0;
   P->staging = (d->flags & RBF_PLAN_NO_STAGING) == 0;
+  P->row_assembly = (d->flags & RBF_PLAN_ROW_ASSEMBLY) != 0;
   const int rc = build_plan(P, d);
   if (rc != RBF_OK) {
     delete P;
@@ -1435,6 +1521,8 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->nnz_upper = (P->nnz_full + na) / 2;
   o->n_points_in_box = P->pcs ? (int64_t)in_box : in_box64;
   o->density = (double)P->nnz_full / ((double)P->m * (double)P->m);
+  o->assembly_tiles = P->tiled ? 1 : 0;
+  o->tile_window = P->tile_window;
   o->solver_entries = P->nsell;
   o->solver_col_bytes = P->col16 ? 2 : 4;
   o->solver_lanes = P->lanes;
@@ -2074,7 +2162,8 @@ int rbf_stream_begin(const rbf_stream_desc* d, const rbf_allocator* allocator, v
     return fail(RBF_ERR_INVALID, "unknown precision");
   if (d->max_chunk < 1 || d->max_chunk >= (int64_t(1) << 31))
     return fail(RBF_ERR_INVALID, "max_chunk must be in [1, 2^31)");
-  if (d->flags & ~RBF_PLAN_NO_STAGING) return fail(RBF_ERR_INVALID, "unknown plan flags");
+  if (d->flags & ~(RBF_PLAN_NO_STAGING | RBF_PLAN_ROW_ASSEMBLY))
+    return fail(RBF_ERR_INVALID, "unknown plan flags");
   if (allocator && (!allocator->alloc || !allocator->release))
     return fail(RBF_ERR_INVALID, "allocator callbacks are NULL");
   rbf_plan* P = new rbf_plan();
@@ -2089,6 +2178,7 @@ int rbf_stream_begin(const rbf_stream_desc* d, const rbf_allocator* allocator, v
   P->min_support = d->min_support;
   P->lambda_rel = d->lambda_rel;
   P->staging = (d->flags & RBF_PLAN_NO_STAGING) == 0;
+  P->row_assembly = (d->flags & RBF_PLAN_ROW_ASSEMBLY) != 0;
   P->max_chunk = d->max_chunk;
   P->phi = (int)d->phi;
   P->stream_prec = (int)d->precision;

@@ -299,14 +299,17 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
 // g = A^T h alone, for new sample values with B kept (vector-valued data):
 // the same support stream, chunk size, lane assignment and accumulator as the
 // assembly's first column pass, so g is bit for bit what k_assemble gives.
+// With kexp, also an exponent k_j with sum_k phi_kj^2 < 2^(k_j - 1) (the
+// point tiles' fixed-point scale of row j).
 template <int DIM, int PHI, typename T, bool GROUPED>
 __global__ __launch_bounds__(kWave* kAsmWaves) void k_rhs(PlanView P,
                                                          const double* __restrict__ hs,
-                                                         double* __restrict__ g) {
+                                                         double* __restrict__ g,
+                                                         int32_t* __restrict__ kexp) {
   constexpr int kChunk = GROUPED ? kAsmChunk / 2 : kAsmChunk;
   __shared__ double sp[kAsmWaves][DIM][kChunk];
   __shared__ int32_t sidx[kAsmWaves][kChunk];
-  __shared__ double gred[kAsmWaves];
+  __shared__ double gred[kAsmWaves], dred[kAsmWaves];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
@@ -319,6 +322,7 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_rhs(PlanView P,
   for (int d = 0; d < DIM; ++d) xj[d] = P.ctr[d * P.m + j];
   const double r2j = P.rho2[j], irj = P.irho[j];
   Acc<T> gacc;
+  double dsum = 0.0;
   double(*wsp)[kChunk] = sp[w];
   const int32_t* widx = sidx[w];
   stream_support_part<DIM, kChunk>(P, xj, r2j, w, kAsmWaves, wsp, sidx[w], [&](int np) {
@@ -328,15 +332,27 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_rhs(PlanView P,
       for (int d = 0; d < DIM; ++d) p[d] = wsp[d][q];
       const T phij = wendland<PHI, T>(scaled_r<T>(sqdist<DIM>(p, xj), irj));
       gacc.add(phij * (T)hs[widx[q]]);
+      if (kexp) dsum += (double)phij * (double)phij;
     }
   });
   const double gl = wave_sum(partial_value<T>(gacc));
   if (lane == 0) gred[w] = gl;
+  if (kexp) {
+    dsum = wave_sum(dsum);
+    if (lane == 0) dred[w] = dsum;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double gs = 0.0;
     for (int u = 0; u < kAsmWaves; ++u) gs += gred[u];
     g[j] = gs;
+    if (kexp) {
+      double ds = 0.0;
+      for (int u = 0; u < kAsmWaves; ++u) ds += dred[u];
+      // 2^(ilogb + 1) > ds; one more power of two covers the rounding of
+      // this sum against the tiles' own
+      kexp[j] = ds > 0.0 ? ilogb(ds) + 2 : -1000;
+    }
   }
 }
 
@@ -488,35 +504,44 @@ hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, 
 }
 
 template <int DIM, typename T, bool GROUPED>
-void rhs_phi(const PlanView& P, int phi, const double* hs, double* g, hipStream_t s) {
+void rhs_phi(const PlanView& P, int phi, const double* hs, double* g, int32_t* kexp,
+             hipStream_t s) {
   const dim3 grid((unsigned)P.m), block(kWave * kAsmWaves);
   switch (phi) {
-    case 0: hipLaunchKernelGGL((k_rhs<DIM, 0, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
-    case 1: hipLaunchKernelGGL((k_rhs<DIM, 1, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
-    case 2: hipLaunchKernelGGL((k_rhs<DIM, 2, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
-    default: hipLaunchKernelGGL((k_rhs<DIM, 3, T, GROUPED>), grid, block, 0, s, P, hs, g); break;
+    case 0:
+      hipLaunchKernelGGL((k_rhs<DIM, 0, T, GROUPED>), grid, block, 0, s, P, hs, g, kexp);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_rhs<DIM, 1, T, GROUPED>), grid, block, 0, s, P, hs, g, kexp);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_rhs<DIM, 2, T, GROUPED>), grid, block, 0, s, P, hs, g, kexp);
+      break;
+    default:
+      hipLaunchKernelGGL((k_rhs<DIM, 3, T, GROUPED>), grid, block, 0, s, P, hs, g, kexp);
+      break;
   }
 }
 
 template <int DIM>
 void rhs_dim(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs, double* g,
-             hipStream_t s) {
+             int32_t* kexp, hipStream_t s) {
   if (fp32) {
-    if (grouped) rhs_phi<DIM, float, true>(P, phi, hs, g, s);
-    else rhs_phi<DIM, float, false>(P, phi, hs, g, s);
+    if (grouped) rhs_phi<DIM, float, true>(P, phi, hs, g, kexp, s);
+    else rhs_phi<DIM, float, false>(P, phi, hs, g, kexp, s);
   } else {
-    if (grouped) rhs_phi<DIM, double, true>(P, phi, hs, g, s);
-    else rhs_phi<DIM, double, false>(P, phi, hs, g, s);
+    if (grouped) rhs_phi<DIM, double, true>(P, phi, hs, g, kexp, s);
+    else rhs_phi<DIM, double, false>(P, phi, hs, g, kexp, s);
   }
 }
 
 hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
-                      double* g, hipStream_t s) {
+                      double* g, hipStream_t s, int32_t* kexp) {
   if (P.m <= 0) return hipSuccess;
   if (P.dim == 2)
-    rhs_dim<2>(P, phi, fp32, grouped, hs, g, s);
+    rhs_dim<2>(P, phi, fp32, grouped, hs, g, kexp, s);
   else
-    rhs_dim<3>(P, phi, fp32, grouped, hs, g, s);
+    rhs_dim<3>(P, phi, fp32, grouped, hs, g, kexp, s);
   return hipGetLastError();
 }
 

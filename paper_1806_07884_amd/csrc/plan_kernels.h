@@ -157,9 +157,11 @@ hipError_t launch_assemble(const PlanView& P, int phi, bool fp32, bool grouped, 
                            const int64_t* row_ptr, const int32_t* lower_cnt, const int32_t* col,
                            const int64_t* sptr, int lanes, void* val, double* g, double* diag,
                            hipStream_t s);
-// g = A^T h alone (same sums as launch_assemble's g for the same fp32/grouped).
+// g = A^T h alone (same sums as launch_assemble's g for the same fp32/grouped);
+// with kexp, also per active centre an exponent k_j with
+// sum_k phi_kj^2 < 2^(k_j - 1) (phi in the same precision).
 hipError_t launch_rhs(const PlanView& P, int phi, bool fp32, bool grouped, const double* hs,
-                      double* g, hipStream_t s);
+                      double* g, hipStream_t s, int32_t* kexp = nullptr);
 // lambda from the diagonals of the m centres, then, over the ms solver rows,
 // the diagonal entries + lambda and the Jacobi scales dinv[k] (in solver rows).
 hipError_t launch_finalize(int64_t m, const uint8_t* active, int64_t ms, const int32_t* srow,

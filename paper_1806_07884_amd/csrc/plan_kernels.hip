@@ -164,8 +164,11 @@ __global__ __launch_bounds__(256) void k_support_count(PlanView P, int32_t min_s
 }
 
 constexpr int kSymWaves = 4;
-constexpr int kSymChunk = 256;
+constexpr int kSymChunk = 128;
 constexpr int kCandWords = kMaxCand / 32;
+// Candidates whose coordinates and radii the count pass stages in LDS (rows
+// with more read them from global memory).
+constexpr int kSymStage = 448;
 
 // Pattern of row j (one block of kSymWaves waves per row).
 //
@@ -191,6 +194,8 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   __shared__ uint32_t word[kCandWords];
   __shared__ double sp[kSymWaves][DIM][kSymChunk];
   __shared__ int16_t glist[kSymWaves][kMaxCand];
+  __shared__ double scx[FILL ? 1 : DIM][FILL ? 1 : kSymStage];
+  __shared__ double srho[FILL ? 1 : kSymStage];
   __shared__ int nc_s;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -254,6 +259,27 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   }
 
   if (!FILL) {
+    // the candidates' coordinates and radii, read for every group below
+    const bool staged = nc <= kSymStage;
+    if (staged) {
+      for (int t = threadIdx.x; t < nc; t += kWave * kSymWaves) {
+        const int l = cand[t];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) scx[d][t] = P.ctr[d * P.m + l];
+        srho[t] = P.rho[l];
+      }
+      __syncthreads();
+    }
+    auto cx = [&](int t, int l, int d) -> double {
+      return staged ? scx[d][t] : P.ctr[d * P.m + l];
+    };
+    auto crho = [&](int t, int l) -> double { return staged ? srho[t] : P.rho[l]; };
+    // rho^2 as the radius tables form it (one rounded product)
+    auto crho2 = [&](int t, int l) -> double {
+      if (!staged) return P.rho2[l];
+      const double r = srho[t];
+      return r * r;
+    };
     stream_support_part<DIM, kSymChunk>(P, xj, P.rho2[j], w, kSymWaves, sp[w], nullptr,
                                         [&](int np) {
       // groups of 64 consecutive staged points (spatially close: points are
@@ -281,8 +307,8 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
             const int l = cand[t];
             double xl[DIM];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
-            const double reach = (P.rho[l] + (double)rg) * (1.0 + 1e-9);
+            for (int d = 0; d < DIM; ++d) xl[d] = cx(t, l, d);
+            const double reach = (crho(t, l) + (double)rg) * (1.0 + 1e-9);
             need = sqdist<DIM>(xl, c0) < reach * reach;
           }
           const uint64_t msk = __ballot(need);
@@ -297,13 +323,22 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
             const int l = cand[t];
             double xl[DIM];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xl[d] = P.ctr[d * P.m + l];
-            const double r2l = P.rho2[l];
-            for (int q = g0; q < g0 + n; ++q) {
-              double p[DIM];
+            for (int d = 0; d < DIM; ++d) xl[d] = cx(t, l, d);
+            const double r2l = crho2(t, l);
+            // four points per step, stopping after the step with a hit
+            const int q1 = g0 + n;
+            for (int q = g0; q < q1; q += 4) {
+              bool hit = false;
 #pragma unroll
-              for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q];
-              if (sqdist<DIM>(p, xl) < r2l) {
+              for (int u = 0; u < 4; ++u) {
+                if (q + u < q1) {
+                  double p[DIM];
+#pragma unroll
+                  for (int d = 0; d < DIM; ++d) p[d] = sp[w][d][q + u];
+                  hit |= sqdist<DIM>(p, xl) < r2l;
+                }
+              }
+              if (hit) {
                 atomicOr(&word[t >> 5], 1u << (t & 31));
                 break;
               }

@@ -1,0 +1,46 @@
+// Assembly of B by point tiles (tile_kernels.hip).
+#pragma once
+
+#include "plan_kernels.h"
+
+namespace rbf {
+
+// Points of one tile: a hash cell's points in sorted order, cut into pieces
+// of at most this many.
+constexpr int kTilePts = 512;
+
+// Most centres a tile's window may hold (centres whose support can reach
+// the tile's points), by dimension.
+constexpr int tile_window_max(int dim) { return dim == 2 ? 256 : 384; }
+
+// Per cell c < ncell: the number of tiles of its points (cnt[c]) and, for a
+// cell that holds points, its window size (wcnt[c]: the active centres whose
+// ball reaches the cell, widened by 1e-6 of a cell; 0 for an empty cell),
+// atomically maxed into *maxwin; cnt[ncell] = wcnt[ncell] = 0.
+hipError_t launch_tile_count(const PlanView& P, double cell_size, uint32_t* cnt, uint32_t* wcnt,
+                             int32_t* maxwin, hipStream_t s);
+// tiles[t] = {first point, end point, window offset, window size} (sorted
+// point positions; the window's caller indices in wids), in cell order, from
+// the exclusive scans off of cnt and woff of wcnt.
+hipError_t launch_tile_fill(const PlanView& P, double cell_size, const uint32_t* off,
+                            const uint32_t* woff, int4* tiles, int32_t* wids, hipStream_t s);
+// The tiles' shares of B summed into acc (one uint64 per stored entry of the
+// full pattern, zeroed by the caller; a pair's shares go to the entry in the
+// row of its first window centre), in units of 2^(k - 63) with
+// k = ceil((kexp[j] + kexp[l]) / 2) (kexp from launch_rhs): one block per
+// tile.  Sets bit 1 of *err when a window exceeds tile_window_max (an
+// internal error: the host checks the bound from launch_tile_count first).
+hipError_t launch_tile_assemble(const PlanView& P, int phi, bool fp32, const int4* tiles,
+                                int64_t ntiles, const int32_t* wids, const int64_t* row_ptr,
+                                const int32_t* col, const int32_t* kexp,
+                                unsigned long long* acc, int32_t* err, hipStream_t s);
+// Each upper entry's value (its accumulator plus its mirror's) into the
+// solver layout, upper entry and mirror, as T; and diag (0 for inactive
+// centres).
+hipError_t launch_tile_finish(const PlanView& P, bool fp32, const int64_t* row_ptr,
+                              const int32_t* lower_cnt, const int32_t* col,
+                              const int32_t* kexp, const unsigned long long* acc,
+                              const int64_t* sptr, int lanes, void* val, double* diag,
+                              hipStream_t s);
+
+}  // namespace rbf
