@@ -6,6 +6,9 @@ The expected sizes follow from the rule: without a decay, chunks start at 4
 takes half the iterations left to the trigger, ln(trigger / rr) / rate with
 rate = ln(rr1 / rr0) / (it1 - it0), minus the chunk still in flight, clamped
 to [4, check_every]; the soonest active right-hand side decides.
+
+Each check runs on a plain build and on one under the host address and
+undefined-behaviour sanitizers (any report aborts the driver).
 """
 import math
 import os
@@ -74,15 +77,20 @@ int main() {
 """
 
 
-@pytest.fixture(scope="module")
-def lines(tmp_path_factory):
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def lines(tmp_path_factory, request):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no g++")
     d = tmp_path_factory.mktemp("planner")
     src, exe = d / "drv.cpp", d / "drv"
     src.write_text(DRIVER)
-    subprocess.run([gxx, "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    extra = SANITIZE if request.param == "sanitized" else []
+    subprocess.run([gxx, "-std=c++17", "-O1", *extra, "-I", CSRC, str(src), "-o", str(exe)],
+                   check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     return [[int(v) for v in line.split()] for line in out.strip().splitlines()]
 

@@ -8,6 +8,9 @@ g++ and driven on synthetic inputs; no GPU.
   left goes on in float64 -- by re-assembly when the plan holds its points,
   from the float64 accumulators when it was made from point chunks; the
   iteration cap and every other status return as they are.
+
+Each check runs on a plain build and on one under the host address and
+undefined-behaviour sanitizers (any report aborts the driver).
 """
 import os
 import shutil
@@ -54,16 +57,20 @@ int main() {
 """
 
 
-@pytest.fixture(scope="module")
-def out(tmp_path_factory):
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def out(tmp_path_factory, request):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no g++")
     d = tmp_path_factory.mktemp("policy")
     src, exe = d / "drv.cpp", d / "drv"
     src.write_text(DRIVER)
-    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", "-I", CSRC, str(src), "-o",
-                    str(exe)], check=True)
+    extra = SANITIZE if request.param == "sanitized" else []
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", *extra, "-I", CSRC, str(src),
+                    "-o", str(exe)], check=True)
     return subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()
 
 
