@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   __shared__ double scx[FILL ? 1 : DIM][FILL ? 1 : kSymStage];
   __shared__ double srho[FILL ? 1 : kSymStage];
   __shared__ int nc_s;
+  __shared__ int rlo[25], rcnt[25], rpre[26], wcnt[kSymWaves];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t j = blockIdx.x;
@@ -215,34 +216,65 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
   int c[3];
   cell_of<DIM>(P.grid, xj, c);  // centres always lie inside the box
 
-  if (w == 0) {
-    int nc = 0;
+  {
+    // the walk's rows of cells (5 in 2D, 25 in 3D) as ranges of sorted
+    // centres, taken as one list over all threads; the candidates keep the
+    // walk order (ordered compaction over the block)
     NbrWalk<DIM> walk(P.grid, c, 2);
-    for (int k = 0; k < walk.rows(); ++k) {
-      int lo_id, hi_id;
-      if (!walk.range(k, lo_id, hi_id)) continue;
-      const int lo = P.ccs[lo_id], hi = P.ccs[hi_id + 1];
-      for (int i0 = lo; i0 < hi; i0 += kWave) {
-        const int i = i0 + lane;
-        bool ok = false;
-        int l = 0;
-        if (i < hi) {
-          l = P.cperm[i];
-          if (P.active[l]) {
-            double xl[DIM];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
-            const double reach = (rj + P.rho[l]) * (1.0 + 1e-9);
-            ok = sqdist<DIM>(xl, xj) <= reach * reach;
-          }
-        }
-        const uint64_t m = __ballot(ok);
-        const int pos = nc + __popcll(m & lt);
-        if (ok && pos < kMaxCand) cand[pos] = l;
-        nc += __popcll(m);
+    const int R = walk.rows();
+    if (threadIdx.x < R) {
+      int lo_id, hi_id, a = 0, b = 0;
+      if (walk.range(threadIdx.x, lo_id, hi_id)) {
+        a = P.ccs[lo_id];
+        b = P.ccs[hi_id + 1];
       }
+      rlo[threadIdx.x] = a;
+      rcnt[threadIdx.x] = b - a;
     }
-    if (lane == 0) nc_s = nc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int k = 0; k < R; ++k) {
+        rpre[k] = t;
+        t += rcnt[k];
+      }
+      rpre[R] = t;
+    }
+    __syncthreads();
+    const int T = rpre[R];
+    int nc = 0;
+    for (int q0 = 0; q0 < T; q0 += kWave * kSymWaves) {
+      const int q = q0 + (int)threadIdx.x;
+      bool ok = false;
+      int l = 0;
+      if (q < T) {
+        int k = 0;
+        while (rpre[k + 1] <= q) ++k;
+        const int i = rlo[k] + (q - rpre[k]);
+        l = P.cperm[i];
+        if (P.active[l]) {
+          double xl[DIM];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
+          const double reach = (rj + P.rho[l]) * (1.0 + 1e-9);
+          ok = sqdist<DIM>(xl, xj) <= reach * reach;
+        }
+      }
+      const uint64_t m = __ballot(ok);
+      if (lane == 0) wcnt[w] = __popcll(m);
+      __syncthreads();
+      int before = 0, all = 0;
+#pragma unroll
+      for (int u = 0; u < kSymWaves; ++u) {
+        before += u < w ? wcnt[u] : 0;
+        all += wcnt[u];
+      }
+      const int pos = nc + before + __popcll(m & lt);
+      if (ok && pos < kMaxCand) cand[pos] = l;
+      nc += all;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) nc_s = nc;
   }
   if (threadIdx.x < kCandWords) word[threadIdx.x] = FILL ? marks[j * kCandWords + threadIdx.x] : 0u;
   __syncthreads();
