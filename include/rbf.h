@@ -104,10 +104,11 @@ typedef struct {
  * global memory instead of staging the slices' neighbourhoods in LDS (same
  * results bit for bit; for comparisons). */
 #define RBF_PLAN_NO_STAGING 1u
-/* rbf_plan_desc.flags: assemble B row by row (one workgroup per centre, the
- * supported points streamed per row) instead of by point tiles (products of
- * each tile's basis values on the matrix cores); the same values up to the
- * order of the float64 sums, for comparisons. */
+/* rbf_plan_desc.flags: form the pattern and assemble B row by row (one
+ * workgroup per centre, the supported points streamed per row) instead of by
+ * point tiles (each hash cell's points against the centres that reach the
+ * cell, products on the matrix cores); the same pattern, and the same values
+ * up to the order of the float64 sums, for comparisons. */
 #define RBF_PLAN_ROW_ASSEMBLY 2u
 
 typedef struct {
@@ -133,8 +134,8 @@ typedef struct {
   int32_t assembly_tiles;       /* 1: the last assembly went by point tiles,
                                    0: by rows (or none yet) */
   int32_t tile_window;          /* most active centres within reach of one hash
-                                   cell (set at the first assembly; point tiles
-                                   need at most 256 in 2D, 384 in 3D) */
+                                   cell (0 with RBF_PLAN_ROW_ASSEMBLY; point
+                                   tiles need at most 256 in 2D, 384 in 3D) */
 } rbf_plan_stats;
 
 typedef struct {

@@ -80,8 +80,9 @@ def rbf_fit_plan(points: torch.Tensor, centers: torch.Tensor, rho: Optional[floa
     polynomial: linear polynomial reproduction (coefficients c, then k = (a, a_0)).
     staging: False sets RBF_PLAN_NO_STAGING (the CG iteration gathers from
     global memory; same results).
-    row_assembly: True sets RBF_PLAN_ROW_ASSEMBLY (B assembled row by row
-    instead of by point tiles; same values up to the order of the sums).
+    row_assembly: True sets RBF_PLAN_ROW_ASSEMBLY (pattern and B formed row by
+    row instead of by point tiles; same pattern, same values up to the order
+    of the sums).
     """
     _need(points, "points")
     if points.dim() != 2:

@@ -610,6 +610,8 @@ int setup_centres(rbf_plan* P, const double* centers, const double* rho_per_cent
   return RBF_OK;
 }
 
+int tile_setup(rbf_plan* P);
+
 int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   const int64_t n = P->n, m = P->m;
   const int dim = P->dim;
@@ -641,28 +643,65 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   GET(cnt, m + 1);
   GET(P->lower_cnt, m);
   GET(P->row_ptr, m + 1);
-  GET(err, 3);
+  GET(err, 4);
   maxd = err + 1;
-  HIPCHK(hipMemsetAsync(err, 0, 3 * sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(err, 0, 4 * sizeof(int32_t), s));
   // without a ridge, identical columns of A make B singular
   if (P->lambda_rel == 0.0) HIPCHK(rbf::launch_duplicate_centres(v, err + 2, s));
   HIPCHK(hipMemsetAsync(cnt + m, 0, sizeof(int64_t), s));
-  uint32_t* marks;
-  GET(marks, (int64_t)rbf::symbolic_marks_words(m));
-  HIPCHK(rbf::launch_symbolic(v, false, cnt, P->lower_cnt, nullptr, nullptr, err, maxd, marks, s));
+  // the pattern: by point tiles (marks over each row's walk of cells) when
+  // the windows fit, else row by row (marks over each row's candidates)
+  if (!P->row_assembly) {
+    rc = tile_setup(P);
+    if (rc) return rc;
+  }
+  const bool tiled = !P->row_assembly && P->tile_state == 1;
+  uint32_t* marks = nullptr;
+  int2* wtab = nullptr;
+  int32_t *spos = nullptr, *ccell = nullptr;
+  int words = 0;
+  if (tiled) {
+    const int R = rbf::walk_rows(dim);
+    int32_t* maxwalk;
+    GET(wtab, (int64_t)P->grid.ncell * R);
+    GET(spos, m);
+    GET(ccell, m);
+    GET(maxwalk, 1);
+    HIPCHK(hipMemsetAsync(maxwalk, 0, sizeof(int32_t), s));
+    HIPCHK(rbf::launch_walk_tables(v, wtab, maxwalk, s));
+    HIPCHK(rbf::launch_centre_slots(v, spos, ccell, s));
+    int32_t mwalk = 0;
+    HIPCHK(hipMemcpyAsync(&mwalk, maxwalk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    P->release(maxwalk);
+    words = std::max(1, (mwalk + 31) / 32);
+    GET(marks, m * (int64_t)words);
+    HIPCHK(hipMemsetAsync(marks, 0, sizeof(uint32_t) * m * words, s));
+    HIPCHK(rbf::launch_tile_pattern(v, P->tiles, P->ntiles, P->wids, wtab, spos, ccell, words,
+                                    marks, err + 3, s));
+    HIPCHK(rbf::launch_mark_rows(v, false, wtab, ccell, words, marks, cnt, P->lower_cnt, nullptr,
+                                 nullptr, err, maxd, s));
+  } else {
+    GET(marks, (int64_t)rbf::symbolic_marks_words(m));
+    HIPCHK(rbf::launch_symbolic(v, false, cnt, P->lower_cnt, nullptr, nullptr, err, maxd, marks,
+                                s));
+  }
   void* stmp = P->alloc_bytes(rbf::scan_temp_bytes(m + 1));
   if (!stmp) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
   HIPCHK(rbf::exclusive_scan(cnt, P->row_ptr, m + 1, stmp, s));
   int64_t nnz = 0, ms = 0;
-  int32_t flags[3] = {0, 0, 0};
+  int32_t flags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(&nnz, P->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&ms, apos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(flags, err, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(flags, err, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   P->release(cnt);
   P->release(apos);
   P->release(atmp);
   P->ms = ms;
+  if (flags[3])
+    return fail(RBF_ERR_HIP, "internal error in the tile pattern (%s)",
+                (flags[3] & 1) ? "window overflow" : "mark outside its row");
   if (flags[0])
     return fail(RBF_ERR_INVALID,
                 "a centre has more than %d neighbouring centres within two support radii",
@@ -675,12 +714,19 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   P->nnz_full = nnz;
   P->col16 = flags[1] <= 32767;
   GET(P->col, nnz);
-  HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, maxd, marks,
-                              s));
+  if (tiled)
+    HIPCHK(rbf::launch_mark_rows(v, true, wtab, ccell, words, marks, nullptr, P->lower_cnt,
+                                 P->row_ptr, P->col, err, maxd, s));
+  else
+    HIPCHK(rbf::launch_symbolic(v, true, nullptr, P->lower_cnt, P->row_ptr, P->col, err, maxd,
+                                marks, s));
   rc = build_layout(P);  // synchronises the stream
   P->release(stmp);
   P->release(err);
   P->release(marks);
+  P->release(wtab);
+  P->release(spos);
+  P->release(ccell);
   return rc;
 }
 
@@ -961,9 +1007,8 @@ int read_scalars(rbf_plan* P) {
   return RBF_OK;
 }
 
-// The point tiles of a resident plan, their windows' bound and the upper
-// entries' offsets; tile_state 2 when a window would exceed the kernel's limit
-// (the rows path is then used).
+// The point tiles of a resident plan and their windows; tile_state 2 when a
+// window would exceed the kernels' limit (the rows paths are then used).
 int tile_setup(rbf_plan* P) {
   hipStream_t s = P->stream;
   const rbf::PlanView v = P->view();
@@ -994,9 +1039,6 @@ int tile_setup(rbf_plan* P) {
     GET(P->tiles, (int64_t)nt);
     GET(P->wids, std::max<int64_t>(nwin, 1));
     HIPCHK(rbf::launch_tile_fill(v, P->cell_size, off, woff, P->tiles, P->wids, s));
-    GET(P->tacc, std::max<int64_t>(P->nnz_full, 1));
-    GET(P->kexp, P->m);
-    GET(P->tile_err, 1);
     P->tile_state = 1;
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -1044,6 +1086,11 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
     if (rc) return rc;
   }
   P->tiled = !P->row_assembly && P->tile_state == 1;
+  if (P->tiled && !P->tacc) {
+    GET(P->tacc, std::max<int64_t>(P->nnz_full, 1));
+    GET(P->kexp, P->m);
+    GET(P->tile_err, 1);
+  }
   if (P->tiled) {
     // g by the rows' support stream (the same sums as the rows path gives),
     // with the rows' fixed-point exponents; then B by point tiles

@@ -398,6 +398,346 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
   }
 }
 
+// ---- the pattern by point tiles ------------------------------------------
+//
+// Every centre's candidate columns are the centres of the 5^(d-1) rows of
+// cells of its cell's walk at radius 2 (all of them, in walk order, sorted
+// position within a row); a structural entry (j, l) is a mark bit at l's
+// position in that walk of j.  The position follows from a per-cell table of
+// the walk's rows (first sorted centre, offset in the walk), so a tile can
+// set it with one atomic OR.  A pair (j, l) is structural when some point
+// lies in both supports: the tile whose cell holds that point has j and l in
+// its window and counts the pair's common points as the MFMA product of the
+// 0/1 support indicators (exact small integers in float64).
+
+template <int DIM>
+__device__ __forceinline__ int walk_row(const int* cj, const int* cl) {
+  return DIM == 2 ? cl[1] - cj[1] + 2 : (cl[1] - cj[1] + 2) + 5 * (cl[2] - cj[2] + 2);
+}
+
+// tab[c * R + k] = {first sorted centre of row k of cell c's walk, offset of
+// the row in the walk}; wlen[c] = the walk's length; the longest walk of a
+// cell holding a centre maxed into *maxwalk.
+template <int DIM>
+__global__ void k_walk_tables(PlanView P, int2* __restrict__ tab, int32_t* __restrict__ maxwalk) {
+  constexpr int R = DIM == 2 ? 5 : 25;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= P.grid.ncell) return;
+  int c[3];
+  cell_coords<DIM>(P.grid, (int)cell, c);
+  NbrWalk<DIM> walk(P.grid, c, 2);
+  int off = 0;
+  for (int k = 0; k < R; ++k) {
+    int lo_id, hi_id, a = 0, len = 0;
+    if (walk.range(k, lo_id, hi_id)) {
+      a = P.ccs[lo_id];
+      len = P.ccs[hi_id + 1] - a;
+    }
+    tab[cell * R + k] = make_int2(a, off);
+    off += len;
+  }
+  if (P.ccs[cell + 1] > P.ccs[cell]) atomicMax(maxwalk, off);
+}
+
+// Per centre: its sorted position and its cell id.
+template <int DIM>
+__global__ void k_centre_slots(PlanView P, int32_t* __restrict__ spos, int32_t* __restrict__ ccell) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.m) return;
+  double x[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) x[d] = P.ctr_s[d * P.m + i];
+  int c[3];
+  cell_of<DIM>(P.grid, x, c);
+  const int l = P.cperm[i];
+  spos[l] = (int32_t)i;
+  ccell[l] = cell_id<DIM>(P.grid, c);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_tile_pattern(
+    PlanView P, const int4* __restrict__ tiles, const int32_t* __restrict__ wids,
+    const int2* __restrict__ tab, const int32_t* __restrict__ spos,
+    const int32_t* __restrict__ ccell, int words, uint32_t* __restrict__ marks,
+    int32_t* __restrict__ err) {
+  constexpr int W = TileCfg<DIM>::W;
+  constexpr int MAXP = TileCfg<DIM>::MAXP;
+  constexpr int NW = tile_window_max(DIM);
+  constexpr int NT = NW / 16;
+  constexpr int NTHR = kWave * W;
+  constexpr int STRIDE = NW + 16;
+  constexpr int kKC = 16;
+  constexpr int R = DIM == 2 ? 5 : 25;
+  constexpr int NC = DIM == 2 ? 9 : 27;  // cells around the tile's cell
+  static_assert(NTHR >= NW && NW % kWave == 0, "one column per thread");
+  __shared__ double spt[DIM][kTilePts];
+  __shared__ double wx[DIM][NW];
+  __shared__ double wr2[NW];
+  __shared__ int32_t wid[NW], wpos[NW];
+  __shared__ uint8_t wslot[NW];
+  __shared__ int8_t wc[NW][3];
+  __shared__ double ind[kKC * STRIDE];
+  __shared__ int2 ttab[NC][R];
+  __shared__ uint32_t nzmask[2];
+  __shared__ uint16_t pairs[NT * (NT + 1) / 2];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+
+  const int4 tl = tiles[blockIdx.x];
+  const int p0 = tl.x, npts = tl.y - tl.x, nw = tl.w;
+  if (nw > NW) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  if (nw == 0) return;
+  const int nt = (nw + 15) / 16;
+  const int np = nt * (nt + 1) / 2;
+  // the tile's cell, from its first point (hashed the same way)
+  int tc[3] = {0, 0, 0};
+  {
+    double x0[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) x0[d] = P.ps[d * P.n + p0];
+    cell_of<DIM>(P.grid, x0, tc);
+  }
+  for (int i = threadIdx.x; i < npts; i += NTHR) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) spt[d][i] = P.ps[d * P.n + p0 + i];
+  }
+  if (threadIdx.x < 2) nzmask[threadIdx.x] = 0u;
+  // walk tables of the cells around the tile's cell (off-grid ones unused)
+  for (int t = threadIdx.x; t < NC * R; t += NTHR) {
+    const int sl = t / R, k = t - sl * R;
+    int c[3] = {tc[0] + sl % 3 - 1, tc[1] + (sl / 3) % 3 - 1, DIM == 3 ? tc[2] + sl / 9 - 1 : 0};
+    bool in = c[0] >= 0 && c[0] < P.grid.g[0] && c[1] >= 0 && c[1] < P.grid.g[1];
+    if (DIM == 3) in = in && c[2] >= 0 && c[2] < P.grid.g[2];
+    ttab[sl][k] = in ? tab[(int64_t)cell_id<DIM>(P.grid, c) * R + k] : make_int2(0, 0);
+  }
+  if (threadIdx.x < nt * 16) {
+    const int a = threadIdx.x;
+    if (a < nw) {
+      const int l = wids[tl.z + a];
+      wid[a] = l;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) wx[d][a] = P.ctr[d * P.m + l];
+      wr2[a] = P.rho2[l];
+      wpos[a] = spos[l];
+      const int cid = ccell[l];
+      const int cx = cid % P.grid.g[0], cy = (cid / P.grid.g[0]) % P.grid.g[1];
+      const int cz = DIM == 3 ? cid / (P.grid.g[0] * P.grid.g[1]) : 0;
+      wc[a][0] = (int8_t)(cx - tc[0]);
+      wc[a][1] = (int8_t)(cy - tc[1]);
+      wc[a][2] = (int8_t)(cz - tc[2]);
+      // slot of the centre's cell among the tile cell's neighbours (ttab's
+      // order: x fastest, then y, then z)
+      wslot[a] = (uint8_t)((cx - tc[0] + 1) + 3 * (cy - tc[1] + 1) +
+                           (DIM == 3 ? 9 * (cz - tc[2] + 1) : 0));
+    } else {
+      wid[a] = -1;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) wx[d][a] = 0.0;
+      wr2[a] = -1.0;
+    }
+  }
+  if (threadIdx.x < nt) {
+    const int ta = threadIdx.x;
+    const int o = ta * nt - ta * (ta - 1) / 2;
+    for (int tb = ta; tb < nt; ++tb) pairs[o + tb - ta] = (uint16_t)((ta << 8) | tb);
+  }
+  __syncthreads();
+
+  const int ncol = nt * 16;
+  const int c_first = threadIdx.x % ncol, k_first = threadIdx.x / ncol;
+  const int c_step = NTHR % ncol, k_step = NTHR / ncol;
+  int chunk = 0;
+  for (int base = 0; base < np; base += W * MAXP) {
+    int ta[MAXP], tb[MAXP];
+    dbl4 s[MAXP];
+#pragma unroll
+    for (int sl = 0; sl < MAXP; ++sl) {
+      const int k = base + sl * W + w;
+      const int pr = k < np ? pairs[k] : 0;
+      ta[sl] = k < np ? (pr >> 8) : -1;
+      tb[sl] = pr & 255;
+      s[sl] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int k0 = 0; k0 < npts; k0 += kKC, ++chunk) {
+      if (threadIdx.x == 0) nzmask[(chunk + 1) & 1] = 0u;
+      uint32_t nz = 0u;
+      for (int k = k_first, cc = c_first; k < kKC;) {
+        double v = 0.0;
+        if (k0 + k < npts) {
+          double p[DIM], xc[DIM];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            p[d] = spt[d][k0 + k];
+            xc[d] = wx[d][cc];
+          }
+          v = sqdist<DIM>(p, xc) < wr2[cc] ? 1.0 : 0.0;
+        }
+        ind[k * STRIDE + cc] = v;
+        if (v != 0.0) nz |= 1u << (cc >> 4);
+        cc += c_step;
+        k += k_step;
+        if (cc >= ncol) {
+          cc -= ncol;
+          ++k;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) nz |= __shfl_xor(nz, off, kWave);
+      if (lane == 0 && nz) atomicOr(&nzmask[chunk & 1], nz);
+      __syncthreads();
+      const uint32_t nzm = nzmask[chunk & 1];
+      bool on[MAXP];
+#pragma unroll
+      for (int sl = 0; sl < MAXP; ++sl)
+        on[sl] = ta[sl] >= 0 && ((nzm >> ta[sl]) & 1u) && ((nzm >> tb[sl]) & 1u);
+#pragma unroll 1
+      for (int ks = 0; ks < kKC; ks += 4) {
+        const int row = (ks + (lane >> 4)) * STRIDE + (lane & 15);
+        double a[MAXP], b[MAXP];
+#pragma unroll
+        for (int sl = 0; sl < MAXP; ++sl) {
+          a[sl] = ind[row + (ta[sl] < 0 ? 0 : ta[sl]) * 16];
+          b[sl] = ind[row + tb[sl] * 16];
+        }
+#pragma unroll
+        for (int sl = 0; sl < MAXP; ++sl)
+          if (on[sl]) s[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl], b[sl], s[sl], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // every pair with a common point marks (j, l) and (l, j); output (i, j)
+    // of a 16 x 16 block sits in lane j + 16 (i % 4), item i / 4
+#pragma unroll
+    for (int sl = 0; sl < MAXP; ++sl) {
+      if (ta[sl] < 0) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = ta[sl] * 16 + 4 * v + (lane >> 4);
+        const int b = tb[sl] * 16 + (lane & 15);
+        if (a >= nw || b >= nw || (ta[sl] == tb[sl] && a > b) || s[sl][v] == 0.0) continue;
+        const int ca[3] = {wc[a][0], wc[a][1], wc[a][2]};
+        const int cb[3] = {wc[b][0], wc[b][1], wc[b][2]};
+        const int2 ra = ttab[wslot[a]][walk_row<DIM>(ca, cb)];
+        const int pab = ra.y + (wpos[b] - ra.x);
+        // a position outside the row's words would be an internal error:
+        // flagged, never written
+        if ((unsigned)pab < (unsigned)(32 * words))
+          atomicOr(&marks[(int64_t)wid[a] * words + (pab >> 5)], 1u << (pab & 31));
+        else
+          atomicOr(err, 2);
+        if (a != b) {
+          const int2 rb = ttab[wslot[b]][walk_row<DIM>(cb, ca)];
+          const int pba = rb.y + (wpos[a] - rb.x);
+          if ((unsigned)pba < (unsigned)(32 * words))
+            atomicOr(&marks[(int64_t)wid[b] * words + (pba >> 5)], 1u << (pba & 31));
+          else
+            atomicOr(err, 2);
+        }
+      }
+    }
+  }
+}
+
+// Per active centre j (one wave): the marked entries of its walk, i.e. its
+// row of the full pattern.  Count mode writes the row's size, the size of
+// its part left of the diagonal and maxes the largest |l - j| into
+// *maxdelta; fill mode writes the columns in ascending order.  Sets *err
+// when a row exceeds kMaxCand entries.
+template <int DIM, bool FILL>
+__global__ __launch_bounds__(256) void k_mark_rows(
+    PlanView P, const int2* __restrict__ tab, const int32_t* __restrict__ ccell, int words,
+    const uint32_t* __restrict__ marks, int64_t* __restrict__ full_cnt,
+    int32_t* __restrict__ lower_cnt, const int64_t* __restrict__ row_ptr,
+    int32_t* __restrict__ col, int32_t* __restrict__ err, int32_t* __restrict__ maxdelta) {
+  constexpr int R = DIM == 2 ? 5 : 25;
+  constexpr int WPB = 4;
+  __shared__ int32_t surv[WPB][kMaxCand];
+  __shared__ int2 rt[WPB][R + 1];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t j = (int64_t)blockIdx.x * WPB + w;
+  if (j >= P.m) return;
+  if (!P.active[j]) {
+    if (!FILL && lane == 0) {
+      full_cnt[j] = 0;
+      lower_cnt[j] = 0;
+    }
+    return;
+  }
+  const int cid = ccell[j];
+  if (lane < R) rt[w][lane] = tab[(int64_t)cid * R + lane];
+  wave_sync();
+  if (lane == 0) {
+    // the walk's length: the last row's offset plus its length
+    int c[3];
+    cell_coords<DIM>(P.grid, cid, c);
+    NbrWalk<DIM> walk(P.grid, c, 2);
+    int lo_id, hi_id, len = 0;
+    if (walk.range(R - 1, lo_id, hi_id)) len = P.ccs[hi_id + 1] - P.ccs[lo_id];
+    rt[w][R] = make_int2(0, rt[w][R - 1].y + len);
+  }
+  wave_sync();
+  const int L = rt[w][R].y;
+  const uint64_t lt = lanemask_lt();
+  int ns = 0, nlow = 0, dmax = 0;
+  const uint32_t* mrow = marks + j * words;
+  for (int p0 = 0; p0 < L; p0 += kWave) {
+    const int p = p0 + lane;
+    bool hit = false;
+    int l = 0;
+    if (p < L && ((mrow[p >> 5] >> (p & 31)) & 1u)) {
+      int k = 0;
+      while (k + 1 < R && rt[w][k + 1].y <= p) ++k;
+      l = P.cperm[rt[w][k].x + (p - rt[w][k].y)];
+      hit = true;
+    }
+    const uint64_t m = __ballot(hit);
+    const uint64_t ml = __ballot(hit && l < (int)j);
+    if (hit) {
+      const int pos = ns + __popcll(m & lt);
+      if (pos < kMaxCand) surv[w][pos] = l;
+      const int d = l > j ? l - (int)j : (int)j - l;
+      dmax = d > dmax ? d : dmax;
+    }
+    ns += __popcll(m);
+    nlow += __popcll(ml);
+  }
+  if (ns > kMaxCand) {
+    if (lane == 0) {
+      atomicExch(err, 1);
+      if (!FILL) {
+        full_cnt[j] = 0;
+        lower_cnt[j] = 0;
+      }
+    }
+    return;
+  }
+  wave_sync();
+  if (!FILL) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int o = __shfl_xor(dmax, off, kWave);
+      dmax = o > dmax ? o : dmax;
+    }
+    if (lane == 0) {
+      full_cnt[j] = ns;
+      lower_cnt[j] = nlow;
+      if (dmax > 0) atomicMax(maxdelta, dmax);
+    }
+    return;
+  }
+  const int64_t base = row_ptr[j];
+  for (int t = lane; t < ns; t += kWave) {
+    const int l = surv[w][t];
+    int rank = 0;
+    for (int u = 0; u < ns; ++u) rank += surv[w][u] < l ? 1 : 0;
+    col[base + rank] = l;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_tile_finish(
     PlanView P, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ lower_cnt,
@@ -519,6 +859,68 @@ hipError_t launch_tile_finish(const PlanView& P, bool fp32, const int64_t* row_p
   else
     hipLaunchKernelGGL(k_tile_finish<double>, grid, dim3(bs), 0, s, P, row_ptr, lower_cnt, col,
                        kexp, acc, sptr, lanes, (double*)val, diag);
+  return hipGetLastError();
+}
+
+int walk_rows(int dim) { return dim == 2 ? 5 : 25; }
+
+hipError_t launch_walk_tables(const PlanView& P, int2* tab, int32_t* maxwalk, hipStream_t s) {
+  const int bs = 256;
+  if (P.grid.ncell <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((P.grid.ncell + bs - 1) / bs));
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_walk_tables<2>, grid, dim3(bs), 0, s, P, tab, maxwalk);
+  else
+    hipLaunchKernelGGL(k_walk_tables<3>, grid, dim3(bs), 0, s, P, tab, maxwalk);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre_slots(const PlanView& P, int32_t* spos, int32_t* ccell, hipStream_t s) {
+  const int bs = 256;
+  if (P.m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((P.m + bs - 1) / bs));
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_centre_slots<2>, grid, dim3(bs), 0, s, P, spos, ccell);
+  else
+    hipLaunchKernelGGL(k_centre_slots<3>, grid, dim3(bs), 0, s, P, spos, ccell);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_pattern(const PlanView& P, const int4* tiles, int64_t ntiles,
+                               const int32_t* wids, const int2* tab, const int32_t* spos,
+                               const int32_t* ccell, int words, uint32_t* marks, int32_t* err,
+                               hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_tile_pattern<2>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<2>::W), 0,
+                       s, P, tiles, wids, tab, spos, ccell, words, marks, err);
+  else
+    hipLaunchKernelGGL(k_tile_pattern<3>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<3>::W), 0,
+                       s, P, tiles, wids, tab, spos, ccell, words, marks, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_rows(const PlanView& P, bool fill, const int2* tab, const int32_t* ccell,
+                            int words, const uint32_t* marks, int64_t* full_cnt,
+                            int32_t* lower_cnt, const int64_t* row_ptr, int32_t* col,
+                            int32_t* err, int32_t* maxdelta, hipStream_t s) {
+  if (P.m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((P.m + 3) / 4)), block(256);
+  if (P.dim == 2) {
+    if (fill)
+      hipLaunchKernelGGL((k_mark_rows<2, true>), grid, block, 0, s, P, tab, ccell, words, marks,
+                         full_cnt, lower_cnt, row_ptr, col, err, maxdelta);
+    else
+      hipLaunchKernelGGL((k_mark_rows<2, false>), grid, block, 0, s, P, tab, ccell, words, marks,
+                         full_cnt, lower_cnt, row_ptr, col, err, maxdelta);
+  } else {
+    if (fill)
+      hipLaunchKernelGGL((k_mark_rows<3, true>), grid, block, 0, s, P, tab, ccell, words, marks,
+                         full_cnt, lower_cnt, row_ptr, col, err, maxdelta);
+    else
+      hipLaunchKernelGGL((k_mark_rows<3, false>), grid, block, 0, s, P, tab, ccell, words, marks,
+                         full_cnt, lower_cnt, row_ptr, col, err, maxdelta);
+  }
   return hipGetLastError();
 }
 

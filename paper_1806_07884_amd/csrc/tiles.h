@@ -43,4 +43,31 @@ hipError_t launch_tile_finish(const PlanView& P, bool fp32, const int64_t* row_p
                               const int64_t* sptr, int lanes, void* val, double* diag,
                               hipStream_t s);
 
+// ---- the pattern by point tiles
+// Rows of cells in a centre's walk at radius 2 (5 in 2D, 25 in 3D).
+int walk_rows(int dim);
+// tab[c * walk_rows + k] = {first sorted centre of row k of cell c's walk,
+// the row's offset in the walk}; the longest walk of a cell holding a centre
+// maxed into *maxwalk.
+hipError_t launch_walk_tables(const PlanView& P, int2* tab, int32_t* maxwalk, hipStream_t s);
+// spos[l] = sorted position of centre l, ccell[l] = its cell id.
+hipError_t launch_centre_slots(const PlanView& P, int32_t* spos, int32_t* ccell, hipStream_t s);
+// Mark bits (words per row, zeroed by the caller) of every pair of window
+// centres with a common point in some tile, at the column's position in the
+// row's walk, both ways.  Bit 1 of *err: a window exceeds tile_window_max;
+// bit 2: a mark position outside its row (never written; both internal
+// errors).
+hipError_t launch_tile_pattern(const PlanView& P, const int4* tiles, int64_t ntiles,
+                               const int32_t* wids, const int2* tab, const int32_t* spos,
+                               const int32_t* ccell, int words, uint32_t* marks, int32_t* err,
+                               hipStream_t s);
+// From the marks: count mode writes full_cnt, lower_cnt (0 for inactive
+// centres) and maxes the largest |l - j| into *maxdelta; fill mode writes
+// each row's columns in ascending order at row_ptr.  Sets *err to 1 when a
+// row exceeds kMaxCand entries.
+hipError_t launch_mark_rows(const PlanView& P, bool fill, const int2* tab, const int32_t* ccell,
+                            int words, const uint32_t* marks, int64_t* full_cnt,
+                            int32_t* lower_cnt, const int64_t* row_ptr, int32_t* col,
+                            int32_t* err, int32_t* maxdelta, hipStream_t s);
+
 }  // namespace rbf

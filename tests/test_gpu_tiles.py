@@ -162,3 +162,29 @@ def test_wide_windows_assemble_by_rows(rbf):
     e, _, _ = scaled_error(rbf, plan, ne)
     assert e <= 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("dim,min_support", [(2, 1), (2, 20), (3, 1), (3, 8)])
+def test_tile_pattern_equals_rows_pattern(rbf, dim, min_support):
+    # the pattern by point tiles (marks over each row's walk of cells) and row
+    # by row (RBF_PLAN_ROW_ASSEMBLY) on clustered points with per-centre radii
+    rng = np.random.default_rng(340 + dim + min_support)
+    g = 20 if dim == 2 else 8
+    ctr = sd.grid_centers(g, dim)
+    m = ctr.shape[1]
+    rho_vec = (0.6 + 0.8 * rng.random(m)) * 2.4 / (g - 1)
+    pts = np.concatenate([rng.random((dim, 6000)),
+                          sd.gaussian_mixture_points(rng, 9000, dim, 5)], axis=1)
+    say("tile pattern", dim, min_support)
+    a = rbf.rbf_fit_plan(dev(pts), dev(ctr), rho_per_center=dev(rho_vec), min_support=min_support)
+    b = rbf.rbf_fit_plan(dev(pts), dev(ctr), rho_per_center=dev(rho_vec), min_support=min_support,
+                         row_assembly=True)
+    ia, ib = rbf.rbf_plan_info(a), rbf.rbf_plan_info(b)
+    assert ia["tile_window"] > 0 and ib["tile_window"] == 0
+    for x, y in zip(rbf.rbf_plan_pattern(a), rbf.rbf_plan_pattern(b)):
+        assert np.array_equal(x, y)
+    ne = orc.normal_equations(pts, pts[0], ctr, rho_vec, "w31", min_support=min_support)
+    rp, col, sup = rbf.rbf_plan_pattern(a)
+    assert np.array_equal(rp, ne.row_ptr) and np.array_equal(col, ne.col)
+    a.close()
+    b.close()
