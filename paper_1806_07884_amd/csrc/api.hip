@@ -655,7 +655,7 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
     rc = tile_setup(P);
     if (rc) return rc;
   }
-  const bool tiled = !P->row_assembly && P->tile_state == 1;
+  bool tiled = !P->row_assembly && P->tile_state == 1;
   uint32_t* marks = nullptr;
   int2* wtab = nullptr;
   int32_t *spos = nullptr, *ccell = nullptr;
@@ -663,7 +663,7 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   if (tiled) {
     const int R = rbf::walk_rows(dim);
     int32_t* maxwalk;
-    GET(wtab, (int64_t)P->grid.ncell * R);
+    GET(wtab, (int64_t)P->grid.ncell * (R + 1));
     GET(spos, m);
     GET(ccell, m);
     GET(maxwalk, 1);
@@ -675,10 +675,15 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
     HIPCHK(hipStreamSynchronize(s));
     P->release(maxwalk);
     words = std::max(1, (mwalk + 31) / 32);
+    // a tile's marks must fit its LDS: otherwise the rows path
+    if (sizeof(uint32_t) * (size_t)P->tile_window * (size_t)words > rbf::tile_pattern_lds_max(dim))
+      tiled = false;
+  }
+  if (tiled) {
     GET(marks, m * (int64_t)words);
     HIPCHK(hipMemsetAsync(marks, 0, sizeof(uint32_t) * m * words, s));
     HIPCHK(rbf::launch_tile_pattern(v, P->tiles, P->ntiles, P->wids, wtab, spos, ccell, words,
-                                    marks, err + 3, s));
+                                    P->tile_window, marks, err + 3, s));
     HIPCHK(rbf::launch_mark_rows(v, false, wtab, ccell, words, marks, cnt, P->lower_cnt, nullptr,
                                  nullptr, err, maxd, s));
   } else {

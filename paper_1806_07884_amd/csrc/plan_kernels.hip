@@ -414,7 +414,9 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
     if (lane == 0) {
       full_cnt[j] = ns;
       lower_cnt[j] = nlow;
-      if (dmax > 0) atomicMax(maxdelta, dmax);
+      // the running maximum is read first: one address shared by every row,
+      // so an atomic per row would serialise
+      if (dmax > 0 && dmax > *(volatile int32_t*)maxdelta) atomicMax(maxdelta, dmax);
     }
     return;
   }

@@ -437,7 +437,9 @@ __global__ __launch_bounds__(kWave* kRowWaves) void k_stream_row_count(
   if (lane == 0) {
     full_cnt[j] = n;
     lower_cnt[j] = nl;
-    atomicMax(maxdelta, dmax);
+    // the running maximum is read first: one address shared by every row,
+    // so an atomic per row would serialise
+    if (dmax > *(volatile int32_t*)maxdelta) atomicMax(maxdelta, dmax);
   }
 }
 

@@ -128,7 +128,7 @@ __global__ void k_tile_count(PlanView P, double cs, uint32_t* __restrict__ cnt,
   int nw = 0;
   if (np > 0) cell_window<DIM>(P, cs, cell, [&](int) { ++nw; });
   wcnt[cell] = (uint32_t)nw;
-  if (nw > 0) atomicMax(maxwin, nw);
+  if (nw > 0 && nw > *(volatile int32_t*)maxwin) atomicMax(maxwin, nw);
 }
 
 template <int DIM>
@@ -415,9 +415,9 @@ __device__ __forceinline__ int walk_row(const int* cj, const int* cl) {
   return DIM == 2 ? cl[1] - cj[1] + 2 : (cl[1] - cj[1] + 2) + 5 * (cl[2] - cj[2] + 2);
 }
 
-// tab[c * R + k] = {first sorted centre of row k of cell c's walk, offset of
-// the row in the walk}; wlen[c] = the walk's length; the longest walk of a
-// cell holding a centre maxed into *maxwalk.
+// tab[c * (R + 1) + k] = {first sorted centre of row k of cell c's walk,
+// offset of the row in the walk}, tab[c * (R + 1) + R] = {0, the walk's
+// length}; the longest walk of a cell holding a centre maxed into *maxwalk.
 template <int DIM>
 __global__ void k_walk_tables(PlanView P, int2* __restrict__ tab, int32_t* __restrict__ maxwalk) {
   constexpr int R = DIM == 2 ? 5 : 25;
@@ -433,10 +433,11 @@ __global__ void k_walk_tables(PlanView P, int2* __restrict__ tab, int32_t* __res
       a = P.ccs[lo_id];
       len = P.ccs[hi_id + 1] - a;
     }
-    tab[cell * R + k] = make_int2(a, off);
+    tab[cell * (R + 1) + k] = make_int2(a, off);
     off += len;
   }
-  if (P.ccs[cell + 1] > P.ccs[cell]) atomicMax(maxwalk, off);
+  tab[cell * (R + 1) + R] = make_int2(0, off);
+  if (P.ccs[cell + 1] > P.ccs[cell] && off > *(volatile int32_t*)maxwalk) atomicMax(maxwalk, off);
 }
 
 // Per centre: its sorted position and its cell id.
@@ -458,7 +459,7 @@ template <int DIM>
 __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_tile_pattern(
     PlanView P, const int4* __restrict__ tiles, const int32_t* __restrict__ wids,
     const int2* __restrict__ tab, const int32_t* __restrict__ spos,
-    const int32_t* __restrict__ ccell, int words, uint32_t* __restrict__ marks,
+    const int32_t* __restrict__ ccell, int words, int max_nw, uint32_t* __restrict__ marks,
     int32_t* __restrict__ err) {
   constexpr int W = TileCfg<DIM>::W;
   constexpr int MAXP = TileCfg<DIM>::MAXP;
@@ -480,18 +481,22 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
   __shared__ int2 ttab[NC][R];
   __shared__ uint32_t nzmask[2];
   __shared__ uint16_t pairs[NT * (NT + 1) / 2];
+  // the tile's marks per window row (words per row), sized at launch for the
+  // plan's widest window
+  extern __shared__ uint32_t lmask[];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
 
   const int4 tl = tiles[blockIdx.x];
   const int p0 = tl.x, npts = tl.y - tl.x, nw = tl.w;
-  if (nw > NW) {
+  if (nw > NW || nw > max_nw) {
     if (threadIdx.x == 0) atomicOr(err, 1);
     return;
   }
   if (nw == 0) return;
   const int nt = (nw + 15) / 16;
   const int np = nt * (nt + 1) / 2;
+  for (int t = threadIdx.x; t < nw * words; t += NTHR) lmask[t] = 0u;
   // the tile's cell, from its first point (hashed the same way)
   int tc[3] = {0, 0, 0};
   {
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
     int c[3] = {tc[0] + sl % 3 - 1, tc[1] + (sl / 3) % 3 - 1, DIM == 3 ? tc[2] + sl / 9 - 1 : 0};
     bool in = c[0] >= 0 && c[0] < P.grid.g[0] && c[1] >= 0 && c[1] < P.grid.g[1];
     if (DIM == 3) in = in && c[2] >= 0 && c[2] < P.grid.g[2];
-    ttab[sl][k] = in ? tab[(int64_t)cell_id<DIM>(P.grid, c) * R + k] : make_int2(0, 0);
+    ttab[sl][k] = in ? tab[(int64_t)cell_id<DIM>(P.grid, c) * (R + 1) + k] : make_int2(0, 0);
   }
   if (threadIdx.x < nt * 16) {
     const int a = threadIdx.x;
@@ -625,19 +630,26 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
         // a position outside the row's words would be an internal error:
         // flagged, never written
         if ((unsigned)pab < (unsigned)(32 * words))
-          atomicOr(&marks[(int64_t)wid[a] * words + (pab >> 5)], 1u << (pab & 31));
+          atomicOr(&lmask[a * words + (pab >> 5)], 1u << (pab & 31));
         else
           atomicOr(err, 2);
         if (a != b) {
           const int2 rb = ttab[wslot[b]][walk_row<DIM>(cb, ca)];
           const int pba = rb.y + (wpos[a] - rb.x);
           if ((unsigned)pba < (unsigned)(32 * words))
-            atomicOr(&marks[(int64_t)wid[b] * words + (pba >> 5)], 1u << (pba & 31));
+            atomicOr(&lmask[b * words + (pba >> 5)], 1u << (pba & 31));
           else
             atomicOr(err, 2);
         }
       }
     }
+  }
+  // the tile's marks, gathered in LDS per window row, go out once per word
+  __syncthreads();
+  for (int t = threadIdx.x; t < nw * words; t += NTHR) {
+    const uint32_t bits = lmask[t];
+    const int a = t / words;
+    if (bits) atomicOr(&marks[(int64_t)wid[a] * words + (t - a * words)], bits);
   }
 }
 
@@ -656,6 +668,7 @@ __global__ __launch_bounds__(256) void k_mark_rows(
   constexpr int WPB = 4;
   __shared__ int32_t surv[WPB][kMaxCand];
   __shared__ int2 rt[WPB][R + 1];
+  static_assert(R + 1 <= kWave, "one table row per lane");
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t j = (int64_t)blockIdx.x * WPB + w;
@@ -668,42 +681,50 @@ __global__ __launch_bounds__(256) void k_mark_rows(
     return;
   }
   const int cid = ccell[j];
-  if (lane < R) rt[w][lane] = tab[(int64_t)cid * R + lane];
-  wave_sync();
-  if (lane == 0) {
-    // the walk's length: the last row's offset plus its length
-    int c[3];
-    cell_coords<DIM>(P.grid, cid, c);
-    NbrWalk<DIM> walk(P.grid, c, 2);
-    int lo_id, hi_id, len = 0;
-    if (walk.range(R - 1, lo_id, hi_id)) len = P.ccs[hi_id + 1] - P.ccs[lo_id];
-    rt[w][R] = make_int2(0, rt[w][R - 1].y + len);
-  }
+  if (lane <= R) rt[w][lane] = tab[(int64_t)cid * (R + 1) + lane];
   wave_sync();
   const int L = rt[w][R].y;
   const uint64_t lt = lanemask_lt();
   int ns = 0, nlow = 0, dmax = 0;
   const uint32_t* mrow = marks + j * words;
-  for (int p0 = 0; p0 < L; p0 += kWave) {
-    const int p = p0 + lane;
-    bool hit = false;
-    int l = 0;
-    if (p < L && ((mrow[p >> 5] >> (p & 31)) & 1u)) {
-      int k = 0;
-      while (k + 1 < R && rt[w][k + 1].y <= p) ++k;
-      l = P.cperm[rt[w][k].x + (p - rt[w][k].y)];
-      hit = true;
+  // positions in batches of UB * 64: the batch's mark words, then the
+  // marked entries' centres, are loaded before any is used
+  constexpr int UB = 4;
+  for (int p0 = 0; p0 < L; p0 += UB * kWave) {
+    uint32_t wd[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int p = p0 + u * kWave + lane;
+      wd[u] = p < L ? mrow[p >> 5] : 0u;
     }
-    const uint64_t m = __ballot(hit);
-    const uint64_t ml = __ballot(hit && l < (int)j);
-    if (hit) {
-      const int pos = ns + __popcll(m & lt);
-      if (pos < kMaxCand) surv[w][pos] = l;
-      const int d = l > j ? l - (int)j : (int)j - l;
-      dmax = d > dmax ? d : dmax;
+    int lv[UB];
+    bool hv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int p = p0 + u * kWave + lane;
+      hv[u] = p < L && ((wd[u] >> (p & 31)) & 1u);
+      lv[u] = 0;
+      if (hv[u]) {
+        int k = 0;
+        while (k + 1 < R && rt[w][k + 1].y <= p) ++k;
+        lv[u] = P.cperm[rt[w][k].x + (p - rt[w][k].y)];
+      }
     }
-    ns += __popcll(m);
-    nlow += __popcll(ml);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const bool hit = hv[u];
+      const int l = lv[u];
+      const uint64_t m = __ballot(hit);
+      const uint64_t ml = __ballot(hit && l < (int)j);
+      if (hit) {
+        const int pos = ns + __popcll(m & lt);
+        if (pos < kMaxCand) surv[w][pos] = l;
+        const int d = l > j ? l - (int)j : (int)j - l;
+        dmax = d > dmax ? d : dmax;
+      }
+      ns += __popcll(m);
+      nlow += __popcll(ml);
+    }
   }
   if (ns > kMaxCand) {
     if (lane == 0) {
@@ -725,7 +746,9 @@ __global__ __launch_bounds__(256) void k_mark_rows(
     if (lane == 0) {
       full_cnt[j] = ns;
       lower_cnt[j] = nlow;
-      if (dmax > 0) atomicMax(maxdelta, dmax);
+      // the running maximum is read first: one address shared by every row,
+      // so an atomic per row would serialise
+      if (dmax > 0 && dmax > *(volatile int32_t*)maxdelta) atomicMax(maxdelta, dmax);
     }
     return;
   }
@@ -888,15 +911,16 @@ hipError_t launch_centre_slots(const PlanView& P, int32_t* spos, int32_t* ccell,
 
 hipError_t launch_tile_pattern(const PlanView& P, const int4* tiles, int64_t ntiles,
                                const int32_t* wids, const int2* tab, const int32_t* spos,
-                               const int32_t* ccell, int words, uint32_t* marks, int32_t* err,
-                               hipStream_t s) {
+                               const int32_t* ccell, int words, int max_nw, uint32_t* marks,
+                               int32_t* err, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint32_t) * (size_t)max_nw * (size_t)words;
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_tile_pattern<2>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<2>::W), 0,
-                       s, P, tiles, wids, tab, spos, ccell, words, marks, err);
+    hipLaunchKernelGGL(k_tile_pattern<2>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<2>::W), lds,
+                       s, P, tiles, wids, tab, spos, ccell, words, max_nw, marks, err);
   else
-    hipLaunchKernelGGL(k_tile_pattern<3>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<3>::W), 0,
-                       s, P, tiles, wids, tab, spos, ccell, words, marks, err);
+    hipLaunchKernelGGL(k_tile_pattern<3>, dim3((unsigned)ntiles), dim3(kWave * TileCfg<3>::W), lds,
+                       s, P, tiles, wids, tab, spos, ccell, words, max_nw, marks, err);
   return hipGetLastError();
 }
 

@@ -46,9 +46,9 @@ hipError_t launch_tile_finish(const PlanView& P, bool fp32, const int64_t* row_p
 // ---- the pattern by point tiles
 // Rows of cells in a centre's walk at radius 2 (5 in 2D, 25 in 3D).
 int walk_rows(int dim);
-// tab[c * walk_rows + k] = {first sorted centre of row k of cell c's walk,
-// the row's offset in the walk}; the longest walk of a cell holding a centre
-// maxed into *maxwalk.
+// tab[c * (walk_rows + 1) + k] = {first sorted centre of row k of cell c's
+// walk, the row's offset in the walk}, and at k = walk_rows {0, the walk's
+// length}; the longest walk of a cell holding a centre maxed into *maxwalk.
 hipError_t launch_walk_tables(const PlanView& P, int2* tab, int32_t* maxwalk, hipStream_t s);
 // spos[l] = sorted position of centre l, ccell[l] = its cell id.
 hipError_t launch_centre_slots(const PlanView& P, int32_t* spos, int32_t* ccell, hipStream_t s);
@@ -57,10 +57,16 @@ hipError_t launch_centre_slots(const PlanView& P, int32_t* spos, int32_t* ccell,
 // row's walk, both ways.  Bit 1 of *err: a window exceeds tile_window_max;
 // bit 2: a mark position outside its row (never written; both internal
 // errors).
+// The marks of one tile gather in LDS first (max_nw * words words, max_nw
+// the plan's widest window; the caller keeps that within
+// tile_pattern_lds_max bytes) and go out with one atomic OR per nonzero word.
 hipError_t launch_tile_pattern(const PlanView& P, const int4* tiles, int64_t ntiles,
                                const int32_t* wids, const int2* tab, const int32_t* spos,
-                               const int32_t* ccell, int words, uint32_t* marks, int32_t* err,
-                               hipStream_t s);
+                               const int32_t* ccell, int words, int max_nw, uint32_t* marks,
+                               int32_t* err, hipStream_t s);
+// Most bytes of a tile's LDS marks, by dimension (with the kernel's own LDS
+// this keeps one workgroup per CU possible).
+constexpr size_t tile_pattern_lds_max(int dim) { return dim == 2 ? 48 * 1024 : 64 * 1024; }
 // From the marks: count mode writes full_cnt, lower_cnt (0 for inactive
 // centres) and maxes the largest |l - j| into *maxdelta; fill mode writes
 // each row's columns in ascending order at row_ptr.  Sets *err to 1 when a
