@@ -8,6 +8,11 @@
 namespace rbf {
 namespace {
 
+// One wave per query: the centres of the 3^(d-1) rows of cells around the
+// query's cell, taken as one list, are split over the lanes (consecutive
+// sorted centres on consecutive lanes, so the loads coalesce and every lane
+// has the same number of steps); the lanes' partial sums are added by a
+// butterfly of fixed order, so the value is deterministic.
 template <int DIM, int PHI>
 __global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const double* __restrict__ y,
                                               const double* __restrict__ cs,
@@ -15,35 +20,69 @@ __global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const doub
                                               const double* __restrict__ irho_s,
                                               const double* __restrict__ kpoly,
                                               double* __restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= nq) return;
   double p[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) p[d] = y[d * nq + q];
-  int c[3];
+  int c[3] = {0, 0, 0};
   double acc = 0.0;
   if (cell_of<DIM>(P.grid, p, c)) {
     NbrWalk<DIM> walk(P.grid, c, 1);
-    for (int k = 0; k < walk.rows(); ++k) {
+    constexpr int R = DIM == 2 ? 3 : 9;
+    // row k's first sorted centre and the prefix of the row lengths, one row per lane
+    int lo = 0, len = 0;
+    if (lane < R) {
       int lo_id, hi_id;
-      if (!walk.range(k, lo_id, hi_id)) continue;
-      const int lo = P.ccs[lo_id], hi = P.ccs[hi_id + 1];
-      for (int i = lo; i < hi; ++i) {
-        double xl[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
-        const double s = sqdist<DIM>(p, xl);
-        if (s < rho2_s[i]) acc += cs[i] * wendland<PHI, double>(__builtin_sqrt(s) * irho_s[i]);
+      if (walk.range(lane, lo_id, hi_id)) {
+        lo = P.ccs[lo_id];
+        len = P.ccs[hi_id + 1] - lo;
       }
     }
-  }
-  if (kpoly) {
-    double pv = kpoly[DIM];
+    int pre = len;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) pv += kpoly[d] * p[d];
-    acc += pv;
+    for (int off = 1; off < 16; off <<= 1) {
+      const int t = __shfl_up(pre, off, kWave);
+      if (lane >= off) pre += t;
+    }
+    // every lane takes the whole table (all lanes active here)
+    int rpre[R], rlo[R], rlen[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rpre[r] = __shfl(pre, r, kWave);
+      rlo[r] = __shfl(lo, r, kWave);
+      rlen[r] = __shfl(len, r, kWave);
+    }
+    const int total = rpre[R - 1];
+    for (int t = lane; t < total; t += kWave) {
+      // the row holding list position t (rows of no centres hold none)
+      int start = 0, lok = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (t >= rpre[r] - rlen[r] && t < rpre[r]) {
+          start = rpre[r] - rlen[r];
+          lok = rlo[r];
+        }
+      }
+      const int i = lok + (t - start);
+      double xl[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
+      const double s = sqdist<DIM>(p, xl);
+      if (s < rho2_s[i]) acc += cs[i] * wendland<PHI, double>(__builtin_sqrt(s) * irho_s[i]);
+    }
   }
-  out[q] = acc;
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    if (kpoly) {
+      double pv = kpoly[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) pv += kpoly[d] * p[d];
+      acc += pv;
+    }
+    out[q] = acc;
+  }
 }
 
 __global__ void k_gather(const double* __restrict__ src, const int32_t* __restrict__ perm,
@@ -99,7 +138,7 @@ void eval_dim(const PlanView& P, int phi, int64_t nq, const double* y, const dou
               const double* rho2_s, const double* irho_s, const double* kp, double* out,
               hipStream_t s) {
   const int bs = 256;
-  const dim3 grid((unsigned)((nq + bs - 1) / bs));
+  const dim3 grid((unsigned)((nq + bs / kWave - 1) / (bs / kWave)));
   switch (phi) {
     case 0: hipLaunchKernelGGL((k_eval<DIM, 0>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
     case 1: hipLaunchKernelGGL((k_eval<DIM, 1>), grid, dim3(bs), 0, s, P, nq, y, cs, rho2_s, irho_s, kp, out); break;
