@@ -37,6 +37,13 @@
  *    operation rounded separately (no fused multiply-add).  The sparsity
  *    pattern is therefore reproducible bit for bit on any IEEE-754 machine.
  *  - Limits: dim in {2, 3}; 1 <= N < 2^31; 1 <= M < 2^31.
+ *  - The checked build (librbf_checked.so, the same entry points) bounds-checks
+ *    the data-dependent indices of the plan, assembly and evaluation kernels
+ *    on the device: an index outside its buffer skips its access, and
+ *    rbf_fit_plan, rbf_assemble, rbf_eval, rbf_eval_noalloc and
+ *    rbf_stream_finish then return RBF_ERR_HIP naming the check's source file
+ *    and line (rbf_fit_plan releases the plan).  Those calls then block the
+ *    host.  A correct plan never trips a check.
  */
 #ifndef RBF_H_
 #define RBF_H_
@@ -475,6 +482,9 @@ void rbf_plan_destroy(rbf_plan* plan);
 
 const char* rbf_status_string(int status);
 const char* rbf_last_error(void);
+/* 1 in the checked build (device index checks, see the conventions above),
+ * 0 otherwise. */
+int rbf_build_checked(void);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,8 @@
 """ctypes declarations of librbf's C-ABI (see include/rbf.h).
 
 Loading fails loudly when the HIP library has not been built: there is no
-fallback implementation of any step.
+fallback implementation of any step.  RBF_LIBRARY=checked in the environment
+loads the checked build (librbf_checked.so: device index checks) instead.
 """
 from __future__ import annotations
 
@@ -10,6 +11,7 @@ import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librbf.so")
+CHECKED_LIB_PATH = os.path.join(_PKG, "librbf_checked.so")
 
 RBF_OK = 0
 RBF_WARN_MAXITER = 1
@@ -150,26 +152,44 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_double)]),
     "rbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbf_last_error": (ctypes.c_char_p, []),
+    "rbf_build_checked": (ctypes.c_int, []),
 }
 
 _lib = None
 
 
+def load(path: str) -> ctypes.CDLL:
+    """A handle on the library at path with the C-ABI's signatures set;
+    raises when it was not built."""
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_1806_07884_amd.build)")
+    handle = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    return handle
+
+
 def lib() -> ctypes.CDLL:
-    """The loaded librbf.so; raises when it was not built."""
+    """The loaded librbf.so (librbf_checked.so with RBF_LIBRARY=checked)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(
-                f"{LIB_PATH} is missing: build the HIP library first "
-                "(python -m paper_1806_07884_amd.build)")
-        handle = ctypes.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
-            fn = getattr(handle, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = handle
+        _lib = load(CHECKED_LIB_PATH if os.environ.get("RBF_LIBRARY") == "checked"
+                    else LIB_PATH)
     return _lib
+
+
+def use(handle: ctypes.CDLL) -> ctypes.CDLL:
+    """Makes handle (from load) the library every later call goes through;
+    returns the previous one.  A plan must be used and destroyed through the
+    library that made it."""
+    global _lib
+    prev = lib()
+    _lib = handle
+    return prev
 
 
 class RbfError(RuntimeError):

@@ -38,6 +38,7 @@ class Plan:
         self.stream = None
         self._alloc = None
         self._keep = []       # inputs the stream may still read
+        self._lib = L.lib()   # the library that made the plan releases it
 
     def _stream_handle(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
@@ -45,7 +46,7 @@ class Plan:
     def close(self):
         if self.handle and self.handle.value:
             with torch.cuda.device(self.device):
-                L.lib().rbf_plan_destroy(self.handle)
+                self._lib.rbf_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p()
         self._keep.clear()
 

@@ -167,6 +167,7 @@ struct rbf_plan {
   unsigned long long* tacc = nullptr;  // [nnz_full] fixed-point sums
   int32_t* kexp = nullptr;             // [m] their per-row exponents
   int32_t* tile_err = nullptr;
+  int32_t* check = nullptr;   // the checked build's check word (see checks.h)
   // solver workspace
   double* xhi = nullptr;
   double* r64 = nullptr;
@@ -329,6 +330,9 @@ struct rbf_plan {
     v.irho = irho;
     v.active = active;
     v.amap = amap;
+    v.nnz = nnz_full;
+    v.nsell = nsell;
+    v.check = check;
     return v;
   }
   // The solver layout with values `val`; staged neighbourhoods when built and
@@ -510,7 +514,7 @@ int build_layout(rbf_plan* P) {
   if (!P->scol) return fail(RBF_ERR_OOM, "device allocation of the solver columns failed");
   HIPCHK(hipMemsetAsync(P->scol, 0, cbytes, s));
   HIPCHK(rbf::launch_sell_cols(P->row_ptr, P->col, P->srow, P->amap, ms, P->sptr, P->lanes,
-                               P->col16, P->scol, s));
+                               P->col16, P->scol, P->check, s));
   return RBF_OK;
 }
 
@@ -522,6 +526,10 @@ int setup_centres(rbf_plan* P, const double* centers, const double* rho_per_cent
   const int64_t n = points ? P->n : 0, m = P->m;
   const int dim = P->dim;
   hipStream_t s = P->stream;
+  if (RBF_CHECKED_BUILD) {
+    GET(P->check, 1);
+    HIPCHK(hipMemsetAsync(P->check, 0, sizeof(int32_t), s));
+  }
   GET(P->ctr, dim * m);
   HIPCHK(hipMemcpyAsync(P->ctr, centers, sizeof(double) * dim * m, hipMemcpyDeviceToDevice, s));
   GET(P->rho, m);
@@ -608,6 +616,22 @@ int setup_centres(rbf_plan* P, const double* centers, const double* rho_per_cent
   HIPCHK(rbf::launch_gather(P->rho2, P->cperm, m, P->rho2_s, s));
   HIPCHK(rbf::launch_gather(P->irho, P->cperm, m, P->irho_s, s));
   return RBF_OK;
+}
+
+// The check word of a checked build (checks.h), read after an entry point's
+// kernels: a failed device check becomes RBF_ERR_HIP naming its place.  A
+// normal build holds no check word and passes rc on.
+int device_checks(const rbf_plan* P, int rc) {
+  if (!RBF_CHECKED_BUILD || !P || !P->check) return rc;
+  int32_t w = 0;
+  HIPCHK(hipMemcpyAsync(&w, P->check, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  if (w == 0) return rc;
+  static const char* const files[] = {"?", "tile_kernels.hip", "assemble_kernels.hip",
+                                      "plan_kernels.hip", "eval_kernels.hip"};
+  const int f = w / 100000;
+  return fail(RBF_ERR_HIP, "device check failed: %s line %d",
+              f >= 1 && f <= 4 ? files[f] : files[0], w % 100000);
 }
 
 int tile_setup(rbf_plan* P);
@@ -717,6 +741,7 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
                 "B is singular");
   if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
   P->nnz_full = nnz;
+  v.nnz = nnz;
   P->col16 = flags[1] <= 32767;
   GET(P->col, nnz);
   if (tiled)
@@ -1471,6 +1496,8 @@ extern "C" {
 
 const char* rbf_last_error(void) { return g_last_error.c_str(); }
 
+int rbf_build_checked(void) { return RBF_CHECKED_BUILD; }
+
 const char* rbf_status_string(int status) {
   switch (status) {
     case RBF_OK: return "ok";
@@ -1486,8 +1513,8 @@ const char* rbf_status_string(int status) {
   }
 }
 
-int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* stream,
-                 rbf_plan** out) {
+static int fit_plan_impl(const rbf_plan_desc* d, const rbf_allocator* allocator, void* stream,
+                         rbf_plan** out) {
   if (!out) return fail(RBF_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (!d) return fail(RBF_ERR_INVALID, "desc is NULL");
@@ -1613,7 +1640,7 @@ int rbf_plan_pattern(const rbf_plan* P, int64_t* row_ptr_h, int32_t* col_h,
   return RBF_OK;
 }
 
-int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* values) {
+static int assemble_impl(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* values) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (!P->ps) return fail(RBF_ERR_INVALID, "a stream plan holds no points to assemble from");
   if ((int)phi < 0 || (int)phi > 3) return fail(RBF_ERR_INVALID, "unknown basis function");
@@ -2124,8 +2151,8 @@ int rbf_solve_lsqr(rbf_plan* P, const rbf_solve_opts* opts, double* coeffs,
   return rc;
 }
 
-int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,
-             double* out, const double* values, double* rmse_h) {
+static int eval_impl(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,
+                     double* out, const double* values, double* rmse_h) {
   rbf_plan* P = const_cast<rbf_plan*>(Pc);
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (nq < 0) return fail(RBF_ERR_INVALID, "n_query < 0");
@@ -2155,8 +2182,9 @@ int rbf_eval(const rbf_plan* Pc, int64_t nq, const double* queries, const double
   return RBF_OK;
 }
 
-int rbf_eval_noalloc(const rbf_plan* Pc, int64_t nq, const double* queries, const double* coeffs,
-                     double* out, const double* values, double* rmse_h) {
+static int eval_noalloc_impl(const rbf_plan* Pc, int64_t nq, const double* queries,
+                             const double* coeffs, double* out, const double* values,
+                             double* rmse_h) {
   rbf_plan* P = const_cast<rbf_plan*>(Pc);
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (nq < 0) return fail(RBF_ERR_INVALID, "n_query < 0");
@@ -2290,7 +2318,7 @@ int rbf_stream_add(rbf_plan* P, int64_t n, const double* points, const double* v
   return RBF_OK;
 }
 
-int rbf_stream_finish(rbf_plan* P) {
+static int stream_finish_impl(rbf_plan* P) {
   if (!P) return fail(RBF_ERR_INVALID, "plan is NULL");
   if (P->stream_state != 1)
     return fail(RBF_ERR_INVALID, P->stream_state ? "the stream is finished"
@@ -2591,4 +2619,42 @@ int rbf_mlp_load_state(rbf_mlp* M, const float* params_h, const float* m1_h, con
 
 void rbf_mlp_destroy(rbf_mlp* M) { delete M; }
 
+
+// The exported entry points whose kernels carry the checked build's device
+// checks (checks.h): in that build a failed check turns the status into
+// RBF_ERR_HIP naming the place; in a normal build they pass the status on.
+
+int rbf_fit_plan(const rbf_plan_desc* d, const rbf_allocator* allocator, void* stream,
+                 rbf_plan** out) {
+  int rc = fit_plan_impl(d, allocator, stream, out);
+  if (rc < 0) return rc;
+  rc = device_checks(*out, rc);
+  if (rc < 0) {
+    delete *out;
+    *out = nullptr;
+  }
+  return rc;
+}
+
+int rbf_assemble(rbf_plan* P, rbf_phi phi, rbf_precision prec, const double* values) {
+  const int rc = assemble_impl(P, phi, prec, values);
+  return rc < 0 ? rc : device_checks(P, rc);
+}
+
+int rbf_eval(const rbf_plan* P, int64_t nq, const double* queries, const double* coeffs,
+             double* out, const double* values, double* rmse_h) {
+  const int rc = eval_impl(P, nq, queries, coeffs, out, values, rmse_h);
+  return rc < 0 ? rc : device_checks(P, rc);
+}
+
+int rbf_eval_noalloc(const rbf_plan* P, int64_t nq, const double* queries, const double* coeffs,
+                     double* out, const double* values, double* rmse_h) {
+  const int rc = eval_noalloc_impl(P, nq, queries, coeffs, out, values, rmse_h);
+  return rc < 0 ? rc : device_checks(P, rc);
+}
+
+int rbf_stream_finish(rbf_plan* P) {
+  const int rc = stream_finish_impl(P);
+  return rc < 0 ? rc : device_checks(P, rc);
+}
 }  // extern "C"

@@ -30,6 +30,7 @@
 // FP64 variant: float64 phi and float64 accumulation.
 // FP32 variant: squared distance and support test in float64 (the pattern is
 // fixed in float64), then phi in float32 and float32 Kahan-compensated sums.
+#define RBF_CHECK_FILE 2  // place ids of the checked build's device checks
 #include <algorithm>
 
 #include "accum.h"
@@ -97,6 +98,10 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
       const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
       ok[t] = t < nslot && e < e1;
       lcol[t] = ok[t] ? col[e] : 0;
+      if (ok[t] && !RBF_CHECK(P, (unsigned)lcol[t] < (unsigned)P.m)) {
+        ok[t] = false;
+        lcol[t] = 0;
+      }
       if (!GROUPED) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xl[t][d] = ok[t] ? P.ctr[d * P.m + lcol[t]] : 0.0;
@@ -108,7 +113,8 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
     const int ncol = (int)(R - cb < kCols ? R - cb : kCols);
     if (GROUPED) {
       for (int t = threadIdx.x; t < ncol; t += kWave * kAsmWaves) {
-        const int32_t l = col[e0 + cb + t];
+        const int32_t l0 = col[e0 + cb + t];
+        const int32_t l = RBF_CHECK(P, (unsigned)l0 < (unsigned)P.m) ? l0 : 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) cxs[d][t] = P.ctr[d * P.m + l];
         crs[t] = P.rho[l];
@@ -269,7 +275,8 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
         }
         const T v = (T)sum;
         const int64_t e = e0 + cb + lane + (int64_t)kWave * t;
-        val[sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j])] = v;
+        const int64_t pj = sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j]);
+        if (RBF_CHECK(P, pj < P.nsell)) val[pj] = v;
         const int32_t l = lcol[t];
         if (l == (int32_t)j) {
           diag[j] = (double)v;
@@ -280,7 +287,10 @@ __global__ __launch_bounds__(kWave* kAsmWaves) void k_assemble(
             const int64_t mid = (lo + hi) >> 1;
             if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
           }
-          val[sell_pos(sptr, lanes, P.amap[l], lo - row_ptr[l])] = v;
+          if (RBF_CHECK(P, lo < P.nnz && col[lo] == (int32_t)j)) {
+            const int64_t pl = sell_pos(sptr, lanes, P.amap[l], lo - row_ptr[l]);
+            if (RBF_CHECK(P, pl < P.nsell)) val[pl] = v;
+          }
         }
       }
     }

@@ -3,6 +3,7 @@
 // plus, with polynomial reproduction, a^T y + a_0 (Section 3, eq. 6-7); one
 // thread per query point, centres found through the centre hash, and the
 // root-mean-square error against given values.
+#define RBF_CHECK_FILE 4  // place ids of the checked build's device checks
 #include "plan_kernels.h"
 
 namespace rbf {
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(256) void k_eval(PlanView P, int64_t nq, const doub
         }
       }
       const int i = lok + (t - start);
+      if (!RBF_CHECK(P, (unsigned)i < (unsigned)P.m)) continue;
       double xl[DIM];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];

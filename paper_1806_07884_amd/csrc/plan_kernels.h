@@ -3,6 +3,7 @@
 
 #include <type_traits>
 
+#include "checks.h"
 #include "internal.h"
 
 namespace rbf {
@@ -27,6 +28,9 @@ struct PlanView {
   const double* irho;     // 1 / rho
   const uint8_t* active;  // centre has >= min_support points
   const int32_t* amap;    // centre -> row of the solver's system (active centres in order), -1 if inactive
+  int64_t nnz;            // entries of the full pattern (0 before it is built)
+  int64_t nsell;          // stored entries of the solver layout (0 before it is built)
+  int32_t* check;         // check word of the checked build (see checks.h), else NULL
 };
 
 // Orders LDS traffic among the lanes of one wave (no workgroup barrier).
@@ -139,12 +143,12 @@ hipError_t launch_solver_rows(const uint8_t* active, int64_t m, int64_t* pos, vo
                               int32_t* amap, int32_t* srow, hipStream_t s);
 // Sliced-ELL layout of the solver (see CgMatrix) over its ms rows: slice
 // lengths and sizes, then the column deltas (in solver rows) at their
-// positions.
+// positions (check: the checked build's check word, or null).
 hipError_t launch_slice_lengths(const int64_t* row_ptr, const int32_t* srow, int64_t ms, int lanes,
                                 int64_t nslices, int32_t* slen, int64_t* ssize, hipStream_t s);
 hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, const int32_t* srow,
                             const int32_t* amap, int64_t ms, const int64_t* sptr, int lanes,
-                            bool col16, void* cols, hipStream_t s);
+                            bool col16, void* cols, int32_t* check, hipStream_t s);
 
 }  // namespace rbf
 

@@ -6,6 +6,7 @@
 // Pattern of row j of B (both triangles are produced; the stored upper CSR is
 // the suffix l >= j of each sorted row):
 //     { l active : supp(j) and supp(l) share a point }.
+#define RBF_CHECK_FILE 3  // place ids of the checked build's device checks
 #include "plan_kernels.h"
 #include "solver.h"
 
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
         int k = 0;
         while (rpre[k + 1] <= q) ++k;
         const int i = rlo[k] + (q - rpre[k]);
-        l = P.cperm[i];
-        if (P.active[l]) {
+        l = RBF_CHECK(P, (unsigned)i < (unsigned)P.m) ? P.cperm[i] : 0;
+        if (RBF_CHECK(P, (unsigned)l < (unsigned)P.m) && P.active[l]) {
           double xl[DIM];
 #pragma unroll
           for (int d = 0; d < DIM; ++d) xl[d] = P.ctr_s[d * P.m + i];
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(kWave* kSymWaves) void k_symbolic(
     const int l = surv[t];
     int rank = 0;
     for (int u = 0; u < ns; ++u) rank += surv[u] < l ? 1 : 0;
-    col[base + rank] = l;
+    if (RBF_CHECK(P, base + rank < P.nnz)) col[base + rank] = l;
   }
 }
 
@@ -487,14 +488,18 @@ __global__ __launch_bounds__(256) void k_sell_cols(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ srow,
                                                    const int32_t* __restrict__ amap, int64_t ms,
                                                    const int64_t* __restrict__ sptr, int lanes,
-                                                   CT* __restrict__ cols) {
+                                                   CT* __restrict__ cols, CheckWord C) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (k >= ms) return;
   const int64_t j = srow[k];
   const int64_t a = row_ptr[j], n = row_ptr[j + 1] - a;
-  for (int64_t e = lane; e < n; e += kWave)
-    cols[sell_pos(sptr, lanes, k, e)] = (CT)(amap[col[a + e]] - (int32_t)k);
+  for (int64_t e = lane; e < n; e += kWave) {
+    const int32_t r = amap[col[a + e]];
+    // every column is an active centre: a solver row, and the iteration's
+    // reads of x at k + delta stay in [0, ms)
+    if (RBF_CHECK(C, r >= 0 && (int64_t)r < ms)) cols[sell_pos(sptr, lanes, k, e)] = (CT)(r - (int32_t)k);
+  }
 }
 
 }  // namespace
@@ -522,15 +527,15 @@ hipError_t launch_slice_lengths(const int64_t* row_ptr, const int32_t* srow, int
 
 hipError_t launch_sell_cols(const int64_t* row_ptr, const int32_t* col, const int32_t* srow,
                             const int32_t* amap, int64_t ms, const int64_t* sptr, int lanes,
-                            bool col16, void* cols, hipStream_t s) {
+                            bool col16, void* cols, int32_t* check, hipStream_t s) {
   if (ms <= 0) return hipSuccess;
   const dim3 grid((unsigned)((ms + 3) / 4));
   if (col16)
     hipLaunchKernelGGL(k_sell_cols<int16_t>, grid, dim3(256), 0, s, row_ptr, col, srow, amap, ms,
-                       sptr, lanes, (int16_t*)cols);
+                       sptr, lanes, (int16_t*)cols, CheckWord{check});
   else
     hipLaunchKernelGGL(k_sell_cols<int32_t>, grid, dim3(256), 0, s, row_ptr, col, srow, amap, ms,
-                       sptr, lanes, (int32_t*)cols);
+                       sptr, lanes, (int32_t*)cols, CheckWord{check});
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@
 // two accumulators, converts the sum to float64 once (exactly rescaled),
 // rounds it to the stored type and writes it and its mirror into the solver
 // layout.
+#define RBF_CHECK_FILE 1  // place ids of the checked build's device checks
 #include "accum.h"
 #include "solver.h"
 #include "tiles.h"
@@ -206,7 +207,8 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
   if (threadIdx.x < nt * 16) {
     const int a = threadIdx.x;
     if (a < nw) {
-      const int l = wids[tl.z + a];
+      const int l0 = wids[tl.z + a];
+      const int l = RBF_CHECK(P, (unsigned)l0 < (unsigned)P.m) ? l0 : 0;
       wid[a] = l;
       wke[a] = kexp[l];
 #pragma unroll
@@ -347,8 +349,10 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
             for (int step = 8; step > 0; step >>= 1)
               if (pre[i + step] <= q) i += step;
             ee[u] = rbeg[rt * 16 + i] + (q - pre[i]);
-            cc[u] = col[ee[u]];
-            ii[u] = i;
+            if (RBF_CHECK(P, ee[u] >= 0 && ee[u] < P.nnz)) {
+              cc[u] = col[ee[u]];
+              ii[u] = i;
+            }
           }
         }
       };
@@ -521,7 +525,8 @@ __global__ __launch_bounds__(kWave* TileCfg<DIM>::W, TileCfg<DIM>::EU) void k_ti
   if (threadIdx.x < nt * 16) {
     const int a = threadIdx.x;
     if (a < nw) {
-      const int l = wids[tl.z + a];
+      const int l0 = wids[tl.z + a];
+      const int l = RBF_CHECK(P, (unsigned)l0 < (unsigned)P.m) ? l0 : 0;
       wid[a] = l;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) wx[d][a] = P.ctr[d * P.m + l];
@@ -707,7 +712,8 @@ __global__ __launch_bounds__(256) void k_mark_rows(
       if (hv[u]) {
         int k = 0;
         while (k + 1 < R && rt[w][k + 1].y <= p) ++k;
-        lv[u] = P.cperm[rt[w][k].x + (p - rt[w][k].y)];
+        const int i = rt[w][k].x + (p - rt[w][k].y);
+        lv[u] = RBF_CHECK(P, (unsigned)i < (unsigned)P.m) ? P.cperm[i] : 0;
       }
     }
 #pragma unroll
@@ -757,7 +763,7 @@ __global__ __launch_bounds__(256) void k_mark_rows(
     const int l = surv[w][t];
     int rank = 0;
     for (int u = 0; u < ns; ++u) rank += surv[w][u] < l ? 1 : 0;
-    col[base + rank] = l;
+    if (RBF_CHECK(P, base + rank < P.nnz)) col[base + rank] = l;
   }
 }
 
@@ -778,6 +784,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(
   const int kj = kexp[j];
   for (int64_t e = e0 + lane; e < e1; e += kWave) {
     const int32_t l = col[e];
+    if (!RBF_CHECK(P, (unsigned)l < (unsigned)P.m)) continue;
     unsigned long long t = acc[e];
     int64_t mirror = -1;
     if (l != (int32_t)j) {
@@ -788,14 +795,18 @@ __global__ __launch_bounds__(256) void k_tile_finish(
         if (col[mid] < (int32_t)j) lo = mid + 1; else hi = mid;
       }
       mirror = lo;
+      if (!RBF_CHECK(P, mirror < P.nnz && col[mirror] == (int32_t)j)) continue;
       t += acc[mirror];
     }
     const T v = (T)ldexp((double)t, pair_exp(kj, kexp[l]) - 63);
-    val[sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j])] = v;
-    if (mirror < 0)
+    const int64_t pj = sell_pos(sptr, lanes, P.amap[j], e - row_ptr[j]);
+    if (RBF_CHECK(P, pj < P.nsell)) val[pj] = v;
+    if (mirror < 0) {
       diag[j] = (double)v;
-    else
-      val[sell_pos(sptr, lanes, P.amap[l], mirror - row_ptr[l])] = v;
+    } else {
+      const int64_t pl = sell_pos(sptr, lanes, P.amap[l], mirror - row_ptr[l]);
+      if (RBF_CHECK(P, pl < P.nsell)) val[pl] = v;
+    }
   }
 }
 

@@ -1,5 +1,6 @@
-"""The C-ABI library loads on a machine without a GPU and exports every entry
-point that include/rbf.h declares (no compute calls here)."""
+"""The C-ABI library, and its checked build, load on a machine without a GPU
+and export every entry point that include/rbf.h declares (no compute calls
+here)."""
 import ctypes
 import os
 import re
@@ -27,15 +28,18 @@ def test_header_declares_entry_points():
         assert required in names
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("checked", [False, True])
+def test_library_exports_every_declared_symbol(checked):
     from paper_1806_07884_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("librbf.so not built")
-    handle = ctypes.CDLL(_lib.LIB_PATH)
+    path = _lib.CHECKED_LIB_PATH if checked else _lib.LIB_PATH
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not built")
+    handle = _lib.load(path)
     missing = [n for n in declared_functions() if not hasattr(handle, n)]
     assert not missing, missing
     # and the binding declares a signature for each of them
     assert set(declared_functions()) <= set(_lib.SIGNATURES)
+    assert handle.rbf_build_checked() == int(checked)
 
 
 def test_status_strings_without_gpu():
