@@ -20,7 +20,7 @@ sweep's best RMSE, twice the iterations) are timed too and reported under
 
 roofline: the CG iteration kernel's algorithmic bytes per launch (8 bytes per
 nonzero of B plus ten float32 vector passes) over its average duration,
-timed live with start/stop events on one launch in 32 (a stamped launch reads
+timed live with start/stop events on one launch in 128 (a stamped launch reads
 about 1 us longer than the same launch in a kernel trace); the bytes the
 int16-delta layout moves (6 bytes per nonzero plus twelve vector passes) are
 reported beside it, and so is the bandwidth of a plain 2 GiB device copy.

@@ -381,7 +381,7 @@ int rbf_stream_finish(rbf_plan* plan);
 
 /* Kernel timing for measurement.  rbf_profile(plan, 1) resets the counters and
  * starts timing, with HIP events on the plan's stream, the assembly launch
- * (events recorded around it) and one CG iteration launch in 32
+ * (events recorded around it) and one CG iteration launch in 128
  * (events stamped at the kernel's own start and end by the extended launch;
  * launches that returned at entry after convergence are not counted);
  * rbf_profile(plan, 0) stops.

@@ -26,9 +26,10 @@ namespace {
 thread_local std::string g_last_error;
 
 // With timing on, one CG iteration launch in kProfPeriod carries start/stop
-// events.  Each stamped launch costs about 6 us of extra gap on the stream,
-// so the sample is kept sparse (a terrain2d fit still times ~160).
-constexpr int64_t kProfPeriod = 32;
+// events.  Stamped launches cost extra time on the stream (one in 32 added
+// 0.8 ms to a 89 ms terrain2d fit), so the sample is kept sparse (a terrain2d
+// fit still times ~40).
+constexpr int64_t kProfPeriod = 128;
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
