@@ -156,7 +156,7 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="timed float64 fits for the comparison (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=float, default=0.7)
+    ap.add_argument("--cpu-window", type=float, default=0.75)
     ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
     ap.add_argument("--polynomial", action="store_true",
                     help="linear polynomial reproduction (bordered system of eq. 10)")
