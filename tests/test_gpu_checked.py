@@ -100,6 +100,37 @@ def test_checked_build_matches(libs, dim, g, rc, n, kw):
         same(a, b)
 
 
+def test_checked_build_radii_support_polynomial(libs):
+    # per-centre radii, a support threshold and the linear polynomial (the
+    # bordered system's moments are assembled too)
+    rng = np.random.default_rng(720)
+    g = 20
+    ctr = sd.grid_centers(g, 2)
+    m = ctr.shape[1]
+    rho_vec = (0.6 + 0.8 * rng.random(m)) * 2.4 / (g - 1)
+    pts = np.concatenate([rng.random((2, 12000)),
+                          sd.gaussian_mixture_points(rng, 12000, 2, 4)], axis=1)
+    h = 3.0 + 2.0 * pts[0] - pts[1] + 0.1 * np.sin(6 * pts[0])
+    q = rng.random((2, 4000))
+
+    def run(rbf):
+        plan = rbf.rbf_fit_plan(dev(pts), dev(ctr), rho_per_center=dev(rho_vec), min_support=8,
+                                lambda_rel=1e-5, polynomial=True)
+        rp, col, sup = rbf.rbf_plan_pattern(plan)
+        rbf.rbf_assemble(plan, "w32", "fp64", dev(h))
+        val, gv, lam = rbf.rbf_system_export(plan)
+        c, _ = rbf.rbf_solve(plan, rtol=1e-10)
+        f, _ = rbf.rbf_eval(plan, dev(q), c)
+        torch.cuda.synchronize()
+        out = dict(rp=rp, col=col, sup=sup, val=val, g=gv, c=c.cpu().numpy(), f=f.cpu().numpy())
+        plan.close()
+        return out
+
+    say("checked radii, min_support 8, polynomial")
+    a, b = both(libs, run)
+    same(a, b)
+
+
 def test_checked_build_stream(libs):
     rng = np.random.default_rng(710)
     ctr = sd.grid_centers(20, 2)
