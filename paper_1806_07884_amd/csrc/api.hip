@@ -69,8 +69,9 @@ rbf::CgScalars* pinned_acquire() {
     }
   }
   void* p = nullptr;
-  // mapped and coherent: the CG kernel that ends a chunk writes its slot
-  if (hipHostMalloc(&p, 2 * sizeof(rbf::CgScalars), hipHostMallocMapped | hipHostMallocCoherent) !=
+  // mapped and coherent: the CG kernel that ends a chunk writes its slot; the
+  // third slot's `done` is the word an iteration raising a flag sets
+  if (hipHostMalloc(&p, 3 * sizeof(rbf::CgScalars), hipHostMallocMapped | hipHostMallocCoherent) !=
       hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
@@ -202,7 +203,7 @@ struct rbf_plan {
   // reduction partials and scalars
   double *lq_u = nullptr, *lq_ud = nullptr, *lq_v = nullptr, *lq_w = nullptr, *lq_x = nullptr;
   double *lq_t = nullptr, *lq_tn = nullptr, *lq_part = nullptr, *lq_sc = nullptr;
-  rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots (from the pinned pool)
+  rbf::CgScalars* host_sc = nullptr;  // pinned, two snapshot slots and a flag slot (pinned pool)
   rbf::CgScalars* host_sc_dev = nullptr;  // their device address
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
 
@@ -988,6 +989,7 @@ rbf::CgArgs<XT> make_args(rbf_plan* P, void** vec, const XT* dinv) {
   a.r64 = P->r64;
   a.sc = P->sc;
   a.snap = nullptr;
+  a.flag = &P->host_sc_dev[2].done;
   a.part[0] = P->part_it;
   a.part[1] = P->part_it + rbf::kCgParts * rbf::kCgMaxBlocks;
   a.part_ref = P->part_ref;
@@ -1176,7 +1178,10 @@ int assemble_into(rbf_plan* P, int phi, bool fp32) {
 // rbf::ChunkPlanner); the last launch of a chunk writes the scalars into one
 // of two pinned host slots, and an event follows it.  The next chunk is always queued before the host
 // waits on the previous one, so the GPU never idles on a convergence check;
-// launches after a raised flag return at entry.  Launches never exceed the
+// launches after a raised flag return at entry.  The iteration that raises a
+// flag also sets a pinned host word, and a chunk being queued when it is seen
+// ends with the next launch (which returns at entry and writes the slot), so
+// that few launches are queued past a flag.  Launches never exceed the
 // iteration budget.
 template <typename VT, typename XT>
 int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_solve_opts& o,
@@ -1198,16 +1203,20 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
 
   rbf::ChunkPlanner plan(o.check_every);
   int64_t slot_len[2] = {0, 0};
+  // the flag word the iterations set (no launch of this plan is in flight)
+  volatile int32_t* const flag_h = &P->host_sc[2].done;
+  *flag_h = 0;
   // queue one chunk and its snapshot into slot `slot` (the other slot's
   // chunk, if queued, is still unobserved); false if none is left
   auto enqueue = [&](int slot, bool* queued) -> int {
     *queued = false;
     const int64_t step = plan.next(slot_len[slot ^ 1]);
-    const int64_t chunk = std::min<int64_t>(budget - launched, step);
+    int64_t chunk = std::min<int64_t>(budget - launched, step);
     slot_len[slot] = 0;
     if (chunk <= 0) return RBF_OK;
-    slot_len[slot] = chunk;
     for (int64_t it = 0; it < chunk; ++it) {
+      // a flag already raised: this launch ends the chunk
+      if (it < chunk - 1 && *flag_h != 0) chunk = it + 1;
       const int q = (int)((launched + refreshes) & 1);
       // one launch in kProfPeriod carries start/stop events when timing is on
       const bool timed = P->prof_on && launched % kProfPeriod == kProfPeriod - 1;
@@ -1225,6 +1234,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       ++launched;
     }
     a.snap = nullptr;
+    slot_len[slot] = chunk;
     HIPCHK(hipEventRecord(P->snap_ev[slot], s));
     *queued = true;
     return RBF_OK;
@@ -1283,6 +1293,7 @@ int run_cg(rbf_plan* P, const VT* val, const XT* dinv, void** vec, const rbf_sol
       plan.restart();     // the refresh sets a new trigger
       slot_len[0] = slot_len[1] = 0;
       launched = h.iter;  // every queued launch has run; later ones returned at entry
+      *flag_h = 0;        // the flag of the iteration that raised it
       cur = 0;
       rc = enqueue(cur, &cur_q);
       if (rc) return rc;

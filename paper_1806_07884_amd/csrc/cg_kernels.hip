@@ -342,7 +342,8 @@ template <typename VT, typename XT, typename CT, int L, int BS, bool POLY, bool 
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1))) void k_cg_iter(
     int64_t m, CgMatrix A, const CgState<XT>* __restrict__ sin, CgState<XT>* __restrict__ sout,
     XT* __restrict__ p, XT* __restrict__ xlo, CgScalars* __restrict__ sc, CgScalars* snap,
-    const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int xg, int q,
+    int32_t* flag, const double* __restrict__ part_in, double* __restrict__ part_out, int n_in,
+    int xg, int q,
     int fixed, int np, const XT* __restrict__ Q, const PolySys* __restrict__ psys,
     const PolyState* __restrict__ pin, PolyState* __restrict__ pout) {
   constexpr int W = BS / kWave;
@@ -500,6 +501,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->done = 2;
       snapshot(sc, snap);
+      if (flag) *flag = 2;
     }
     return;
   }
@@ -508,6 +510,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
       sc->rr = rr;
       sc->done = 1;
       snapshot(sc, snap);
+      if (flag) *flag = 1;
     }
     return;
   }
@@ -515,6 +518,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->done = 2;
       snapshot(sc, snap);
+      if (flag) *flag = 2;
     }
     return;
   }
@@ -968,12 +972,12 @@ void launch_iter_p(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, hip
     // the extended launch stamps the events at the kernel's own start and end
     hipExtLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
                           dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p,
-                          a.xlo, a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
+                          a.xlo, a.sc, a.snap, a.flag, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
                           q, fixed, a.np, a.Q, a.psys, pin, pout);
   } else {
     hipLaunchKernelGGL((k_cg_iter<VT, XT, CT, L, BS, POLY>), dim3(a.blocks + (POLY ? 1 : 0)),
                        dim3(BS), 0, s, a.m,
-                       A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
+                       A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap, a.flag,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed, a.np,
                        a.Q, a.psys, pin, pout);
   }
@@ -1036,12 +1040,12 @@ void launch_iter_halo(const CgArgs<XT>& a, const CgMatrix& A, int q, int fixed, 
   if (e0) {
     hipExtLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks),
                           dim3(BS), 0, s, e0, e1, 0, a.m, A, (const CgState<XT>*)a.st[q],
-                          a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q],
+                          a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap, a.flag, (const double*)a.part[q ^ 1], a.part[q],
                           a.blocks, a.xg, q, fixed, 0, (const XT*)nullptr,
                           (const PolySys*)nullptr, (const PolyState*)nullptr, (PolyState*)nullptr);
   } else {
     hipLaunchKernelGGL((k_cg_iter<VT, XT, int16_t, L, BS, false, true>), dim3(a.blocks), dim3(BS),
-                       0, s, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
+                       0, s, a.m, A, (const CgState<XT>*)a.st[q], a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap, a.flag,
                        (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed, 0,
                        (const XT*)nullptr, (const PolySys*)nullptr, (const PolyState*)nullptr,
                        (PolyState*)nullptr);

@@ -93,6 +93,10 @@ struct CgArgs {
   // host snapshot slot (device address of pinned, coherent host memory) that
   // the launch copies the scalars into when it ends a chunk; NULL otherwise
   CgScalars* snap;
+  // a pinned, coherent host word that the iteration raising a flag (1
+  // reliable-update trigger, 2 breakdown) also sets, so that the host stops
+  // queueing launches that would return at entry; NULL: none
+  int32_t* flag;
   double* part[2];     // [kCgParts * blocks] partials of an iteration, by state buffer
   double* part_ref;    // [kCgParts * blocks] partials of a refresh
   int blocks;          // grid of every slice kernel
