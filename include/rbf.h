@@ -143,6 +143,11 @@ typedef struct {
   int32_t tile_window;          /* most active centres within reach of one hash
                                    cell (0 with RBF_PLAN_ROW_ASSEMBLY; point
                                    tiles need at most 256 in 2D, 384 in 3D) */
+  int32_t solver_rows_sorted;   /* 1: the solver's rows were reordered within
+                                   windows of 64, longest first, because the
+                                   layout padded the rows to more than 1.3
+                                   times the nonzeros; 0: centre order */
+  int32_t pad_;
 } rbf_plan_stats;
 
 typedef struct {

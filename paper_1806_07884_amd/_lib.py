@@ -54,7 +54,8 @@ class PlanStats(ctypes.Structure):
                 ("cell_size", ctypes.c_double), ("solver_entries", ctypes.c_int64),
                 ("solver_col_bytes", ctypes.c_int32), ("solver_lanes", ctypes.c_int32),
                 ("n_poly", ctypes.c_int32), ("solver_staged", ctypes.c_int32),
-                ("assembly_tiles", ctypes.c_int32), ("tile_window", ctypes.c_int32)]
+                ("assembly_tiles", ctypes.c_int32), ("tile_window", ctypes.c_int32),
+                ("solver_rows_sorted", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class StreamDesc(ctypes.Structure):

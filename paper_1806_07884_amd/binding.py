@@ -122,6 +122,7 @@ def rbf_plan_info(plan: Plan) -> dict:
         L.check(L.lib().rbf_plan_info(plan.handle, ctypes.byref(s)), "rbf_plan_info")
     out = {k: getattr(s, k) for k, _ in L.PlanStats._fields_}
     out["grid"] = list(s.grid)
+    out.pop("pad_", None)
     return out
 
 

@@ -166,6 +166,7 @@ struct rbf_plan {
   int64_t ntiles = 0;
   int32_t* wids = nullptr;    // the cells' windows (caller indices), tiles point into it
   int32_t tile_window = 0;    // most active centres within reach of one cell
+  bool rows_sorted = false;   // solver rows reordered within windows (build_layout)
   unsigned long long* tacc = nullptr;  // [nnz_full] fixed-point sums
   int32_t* kexp = nullptr;             // [m] their per-row exponents
   int32_t* tile_err = nullptr;
@@ -489,6 +490,14 @@ int build_halo(rbf_plan* P) {
 // The solver layout over the plan's full CSR (row_ptr, col, ms solver rows,
 // nnz_full entries, col16): sliced ELL with L lanes per row.  Reads its size
 // back, so it synchronises the plan's stream.
+//
+// When the slices pad the rows to more than kSortPad times the nonzeros, the
+// rows are first reordered within windows of rbf::kSortRows, longest first,
+// so that a slice's rows have similar lengths.  A slice's rows are then no
+// longer consecutive centres, and its gathers touch more lines: on
+// terrain2d (padding 1.13) the reordered iteration took 18.0 against 16.9 us,
+// on the clustered 3D field (padding 1.53, 1.18 reordered) 23.4 against 24.6.
+constexpr double kSortPad = 1.3;
 int build_layout(rbf_plan* P) {
   hipStream_t s = P->stream;
   const int64_t ms = P->ms;
@@ -501,12 +510,19 @@ int build_layout(rbf_plan* P) {
   GET(ssize, P->nslices + 1);
   void* stmp2 = P->alloc_bytes(rbf::scan_temp_bytes(P->nslices + 1));
   if (!stmp2) return fail(RBF_ERR_OOM, "scan workspace allocation failed");
-  HIPCHK(rbf::launch_slice_lengths(P->row_ptr, P->srow, ms, P->lanes, P->nslices, P->slen, ssize,
-                                   s));
-  HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
   int64_t total = 0;
-  HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  for (int pass = 0; pass < 2; ++pass) {
+    HIPCHK(rbf::launch_slice_lengths(P->row_ptr, P->srow, ms, P->lanes, P->nslices, P->slen,
+                                     ssize, s));
+    HIPCHK(rbf::exclusive_scan(ssize, P->sptr, P->nslices + 1, stmp2, s));
+    HIPCHK(hipMemcpyAsync(&total, P->sptr + P->nslices, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (pass == 1 || (double)total <= kSortPad * (double)P->nnz_full) break;
+    // rows of similar length share a slice (the slices pad to their longest)
+    HIPCHK(rbf::launch_sort_rows(P->row_ptr, ms, P->srow, P->amap, s));
+    P->rows_sorted = true;
+  }
   P->release(stmp2);
   P->release(ssize);
   if (total >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "solver layout exceeds 2^31 entries");
@@ -744,7 +760,8 @@ int build_plan(rbf_plan* P, const rbf_plan_desc* d) {
   if (nnz >= (int64_t(1) << 31)) return fail(RBF_ERR_INVALID, "pattern exceeds 2^31 entries");
   P->nnz_full = nnz;
   v.nnz = nnz;
-  P->col16 = flags[1] <= 32767;
+  // a column delta grows by less than kSortRows when the rows are sorted
+  P->col16 = flags[1] + rbf::kSortRows <= 32767;
   GET(P->col, nnz);
   if (tiled)
     HIPCHK(rbf::launch_mark_rows(v, true, wtab, ccell, words, marks, nullptr, P->lower_cnt,
@@ -915,7 +932,7 @@ int finish_stream(rbf_plan* P) {
                 "B is singular");
   P->ms = ms;
   P->nnz_full = nnz;
-  P->col16 = dm[0] <= 32767;
+  P->col16 = dm[0] + rbf::kSortRows <= 32767;
   int64_t* src;
   GET(P->col, nnz);
   GET(src, nnz);
@@ -1614,6 +1631,8 @@ int rbf_plan_info(const rbf_plan* P, rbf_plan_stats* o) {
   o->density = (double)P->nnz_full / ((double)P->m * (double)P->m);
   o->assembly_tiles = P->tiled ? 1 : 0;
   o->tile_window = P->tile_window;
+  o->solver_rows_sorted = P->rows_sorted ? 1 : 0;
+  o->pad_ = 0;
   o->solver_entries = P->nsell;
   o->solver_col_bytes = P->col16 ? 2 : 4;
   o->solver_lanes = P->lanes;

@@ -139,6 +139,13 @@ hipError_t launch_symbolic(const PlanView& P, bool fill, int64_t* full_cnt, int3
 // int64, scratch of a scan with `temp` of scan_temp_bytes(m + 1) bytes) ends
 // with pos[m] = number of solver rows; amap[j] = row of centre j or -1;
 // srow[k] = centre of row k (room for m entries).
+// launch_sort_rows then reorders the ms rows within windows of kSortRows
+// consecutive rows, longest first (ties in order), updating srow and amap,
+// so that the rows of a slice of the solver's layout have similar lengths.
+// A row moves by less than kSortRows.
+constexpr int kSortRows = 64;
+hipError_t launch_sort_rows(const int64_t* row_ptr, int64_t ms, int32_t* srow, int32_t* amap,
+                            hipStream_t s);
 hipError_t launch_solver_rows(const uint8_t* active, int64_t m, int64_t* pos, void* temp,
                               int32_t* amap, int32_t* srow, hipStream_t s);
 // Sliced-ELL layout of the solver (see CgMatrix) over its ms rows: slice

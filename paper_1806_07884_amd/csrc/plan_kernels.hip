@@ -479,6 +479,31 @@ __global__ void k_slice_lengths(const int64_t* __restrict__ row_ptr,
   ssize[s] = mx * rows;
 }
 
+// One block per window of kSortRows solver rows: each row's rank among the
+// window's rows by descending length (ties by position) is its new place.
+__global__ __launch_bounds__(kSortRows) void k_sort_rows(const int64_t* __restrict__ row_ptr,
+                                                         int64_t ms, int32_t* __restrict__ srow,
+                                                         int32_t* __restrict__ amap) {
+  __shared__ int32_t sj[kSortRows];
+  __shared__ int64_t sl[kSortRows];
+  const int t = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kSortRows;
+  const int n = ms - k0 < kSortRows ? (int)(ms - k0) : kSortRows;
+  if (t < n) {
+    const int32_t j = srow[k0 + t];
+    sj[t] = j;
+    sl[t] = row_ptr[j + 1] - row_ptr[j];
+  }
+  __syncthreads();
+  if (t < n) {
+    const int64_t lt = sl[t];
+    int r = 0;
+    for (int u = 0; u < n; ++u) r += (sl[u] > lt || (sl[u] == lt && u < t)) ? 1 : 0;
+    srow[k0 + r] = sj[t];
+    amap[sj[t]] = (int32_t)(k0 + r);
+  }
+}
+
 // Column deltas amap[l] - k of every stored entry of solver row k at its
 // sliced-ELL position, one wave per row (padding stays 0 from the
 // allocation).  Every column of the pattern is an active centre.
@@ -503,6 +528,14 @@ __global__ __launch_bounds__(256) void k_sell_cols(const int64_t* __restrict__ r
 }
 
 }  // namespace
+
+hipError_t launch_sort_rows(const int64_t* row_ptr, int64_t ms, int32_t* srow, int32_t* amap,
+                            hipStream_t s) {
+  if (ms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)((ms + kSortRows - 1) / kSortRows)),
+                     dim3(kSortRows), 0, s, row_ptr, ms, srow, amap);
+  return hipGetLastError();
+}
 
 hipError_t launch_solver_rows(const uint8_t* active, int64_t m, int64_t* pos, void* temp,
                               int32_t* amap, int32_t* srow, hipStream_t s) {

@@ -75,7 +75,11 @@ def check_values(rbf, plan, ne, h, tol):
     ref = ne.val.copy()
     diag_pos = ne.row_ptr[:-1][ne.active]
     ref[diag_pos] += ne.lam
+    # a stored diagonal is b_jj + lambda: its scale includes the ridge, whose
+    # own rounding (a float64 mean over the diagonals) is relative to lambda
+    # (a centre with one far point in its support has b_jj ~ 1e-26 << lambda)
     scale = entry_scale(ne)
+    scale[diag_pos] += ne.lam
     err = np.abs(val - ref)
     assert np.all(err <= tol * scale + 1e-300), float(np.max(err / (scale + 1e-300)))
     gscale = np.abs(ne.A).T @ np.abs(h)
@@ -370,3 +374,62 @@ def test_staged_iteration_is_bit_identical(rbf, name, scale):
         res[staging] = (c.cpu().numpy().tobytes(), info["iterations"])
         plan.close()
     assert res[True] == res[False]
+
+
+def _unsorted_padding(ne, lanes):
+    """Stored entries over nonzeros of the solver layout with the rows in
+    centre order (slices of 64 / lanes rows padded to their longest row)."""
+    fl = np.diff(ne.full_matrix().tocsr().indptr)[ne.active]
+    s = 64 // lanes
+    tot = sum(int(np.ceil(fl[k:k + s].max() / lanes) * lanes) * s for k in range(0, len(fl), s))
+    return tot / fl.sum()
+
+
+@pytest.mark.parametrize("n_uniform,rvar,sorted_rows", [(1000, 0.8, 1), (3000, 0.0, 0)])
+def test_sorted_solver_rows(rbf, n_uniform, rvar, sorted_rows):
+    # clustered 3D points with (optionally) per-centre radii: row lengths vary
+    # enough for the layout to pad by more than 1.3x, and the plan reorders
+    # the rows within windows of 64; values, solve and evaluation stay the
+    # oracle's, with the rows in either order
+    rng = np.random.default_rng(910)
+    g = 14
+    ctr = sd.grid_centers(g, 3)
+    pts = np.concatenate([rng.random((3, n_uniform)),
+                          sd.gaussian_mixture_points(rng, 12000, 3, 3)], axis=1)
+    h = np.sin(3 * pts[0]) + pts[1] * pts[2]
+    m = ctr.shape[1]
+    rho = 1.9 / (g - 1) * (1 + rvar * (rng.random(m) - 0.5)) if rvar else 1.9 / (g - 1)
+    say("sorted rows", n_uniform, rvar)
+    ne = orc.normal_equations(pts, h, ctr, rho, "w31", lambda_rel=1e-4)
+    kw = {"rho_per_center": dev(rho)} if rvar else {"rho": rho}
+    plan = rbf.rbf_fit_plan(dev(pts), dev(ctr), lambda_rel=1e-4, **kw)
+    check_pattern(rbf, plan, ne)
+    info = rbf.rbf_plan_info(plan)
+    pad = _unsorted_padding(ne, info["solver_lanes"])
+    say("padding in centre order", round(pad, 3), "sorted", info["solver_rows_sorted"],
+        "stored", info["solver_entries"])
+    assert (pad > 1.3) == bool(sorted_rows)
+    assert info["solver_rows_sorted"] == sorted_rows
+    if sorted_rows:
+        assert info["solver_entries"] < pad * info["nnz_full"]
+    rbf.rbf_assemble(plan, "w31", "fp64", dev(h))
+    check_values(rbf, plan, ne, h, 1e-12)
+    c_ref = orc.solve(ne)
+    c, sinfo = rbf.rbf_solve(plan, rtol=1e-13, max_iter=50000)
+    assert sinfo["status"] == 0
+    c = c.cpu().numpy()
+    A = ne.A
+    assert np.linalg.norm(A @ (c - c_ref)) <= FIT_FP64 * np.linalg.norm(A @ c_ref)
+    q = rng.random((3, 2000))
+    f, _ = rbf.rbf_eval(plan, dev(q), dev(c))
+    f_ref = orc.evaluate(q, ctr, rho, "w31", c)
+    absum = orc.evaluate(q, ctr, rho, "w31", np.abs(c))
+    assert np.all(np.abs(f.cpu().numpy() - f_ref) <= 1e-12 * absum + 1e-300)
+    # the mixed solve on the same plan
+    rbf.rbf_assemble(plan, "w31", "fp32", dev(h))
+    c32, i32 = rbf.rbf_solve(plan, rtol=1e-10)
+    assert i32["status"] in (0, 2)
+    r32 = np.linalg.norm(A @ c32.cpu().numpy() - h) / np.sqrt(len(h))
+    r64 = np.linalg.norm(A @ c - h) / np.sqrt(len(h))
+    assert abs(r32 - r64) <= 1e-3 * r64
+    plan.close()
