@@ -433,3 +433,22 @@ def test_sorted_solver_rows(rbf, n_uniform, rvar, sorted_rows):
     r64 = np.linalg.norm(A @ c - h) / np.sqrt(len(h))
     assert abs(r32 - r64) <= 1e-3 * r64
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_chunking_does_not_change_iterates(rbf, prec):
+    # the host only decides how many launches it queues between checks (and
+    # stops queueing at a flag the iteration raises); which iteration raises
+    # a flag, and every iterate, are the device's: any chunk length gives the
+    # same bits, the same iteration count and the same reliable updates
+    p = sd.make_problem("terrain2d", scale=1 / 64)
+    plan = rbf.rbf_fit_plan(dev(p.points), dev(p.centers), rho=p.rho, lambda_rel=1e-5)
+    rbf.rbf_assemble(plan, p.phi, prec, dev(p.values))
+    out = []
+    for ce in (1, 5, 32, 200):
+        c, info = rbf.rbf_solve(plan, rtol=1e-10, check_every=ce)
+        say(prec, "check_every", ce, "iterations", info["iterations"], "updates",
+            info["reliable_updates"])
+        out.append((c.cpu().numpy().tobytes(), info["iterations"], info["reliable_updates"]))
+    assert all(o == out[0] for o in out)
+    plan.close()
