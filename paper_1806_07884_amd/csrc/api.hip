@@ -193,7 +193,7 @@ struct rbf_plan {
   double* bpart_it = nullptr;     // [2][6 kMaxRhs kCgMaxBlocks]
   double* bpart_ref = nullptr;
   rbf::CgScalarsN* bsc = nullptr;
-  rbf::CgScalarsN* host_bsc = nullptr;  // pinned, two snapshot slots
+  rbf::CgScalarsN* host_bsc = nullptr;  // pinned, two snapshot slots and a flag slot
   rbf::CgScalarsN* host_bsc_dev = nullptr;  // their device address
   void* vec64[4] = {};         // state buffers 0 and 1 (4 per row), p, x_lo
   void* vec32[4] = {};
@@ -1344,6 +1344,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   a.r64 = P->br64;
   a.sc = P->bsc;
   a.snap = nullptr;
+  a.flag = &P->host_bsc_dev[2].done;
   a.part[0] = P->bpart_it;
   a.part[1] = P->bpart_it + 6 * rbf::kMaxRhs * rbf::kCgMaxBlocks;
   a.part_ref = P->bpart_ref;
@@ -1359,15 +1360,19 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
   bool fixed = true;
   rbf::ChunkPlanner plan(o.check_every);
   int64_t slot_len[2] = {0, 0};
-  // queue one chunk and its snapshot into slot `slot`
+  // the flag word the iterations set (no launch of this plan is in flight)
+  volatile int32_t* const flag_h = &P->host_bsc[2].done;
+  *flag_h = 0;
+  // queue one chunk and its snapshot into slot `slot` (as run_cg: a flag seen
+  // while queueing ends the chunk with the next launch)
   auto enqueue = [&](int slot, bool* queued) -> int {
     *queued = false;
     const int64_t step = plan.next(slot_len[slot ^ 1]);
-    const int64_t chunk = std::min<int64_t>(budget - launched, step);
+    int64_t chunk = std::min<int64_t>(budget - launched, step);
     slot_len[slot] = 0;
     if (chunk <= 0) return RBF_OK;
-    slot_len[slot] = chunk;
     for (int64_t it = 0; it < chunk; ++it) {
+      if (it < chunk - 1 && *flag_h != 0) chunk = it + 1;
       const int q = (int)((launched + refreshes) & 1);
       const bool timed = P->prof_on && launched % kProfPeriod == kProfPeriod - 1;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1384,6 +1389,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
       ++launched;
     }
     a.snap = nullptr;
+    slot_len[slot] = chunk;
     HIPCHK(hipEventRecord(P->snap_ev[slot], s));
     *queued = true;
     return RBF_OK;
@@ -1433,6 +1439,7 @@ int run_cgn(rbf_plan* P, const VT* val, const XT* dinv, int nr, int prec_idx,
       plan.restart();
       slot_len[0] = slot_len[1] = 0;
       launched = h.iter;  // every queued launch has run; later ones returned at entry
+      *flag_h = 0;        // the flag of the iteration that raised it
       cur = 0;
       rc = enqueue(cur, &cur_q);
       if (rc) return rc;
@@ -1475,8 +1482,9 @@ int ensure_batch(rbf_plan* P, bool fp32) {
   }
   if (!P->host_bsc) {
     void* h = nullptr;
-    // mapped and coherent: the CG kernel that ends a chunk writes its slot
-    if (hipHostMalloc(&h, 2 * sizeof(rbf::CgScalarsN),
+    // mapped and coherent: the CG kernel that ends a chunk writes its slot;
+    // the third slot's `done` is the word an iteration raising a flag sets
+    if (hipHostMalloc(&h, 3 * sizeof(rbf::CgScalarsN),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
       (void)hipGetLastError();
       return fail(RBF_ERR_OOM, "pinned host allocation failed");

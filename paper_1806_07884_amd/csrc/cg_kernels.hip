@@ -1303,8 +1303,9 @@ template <typename VT, typename XT, typename CT, int L, int BS, int NR, bool HAL
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_cgn_iter(
     int64_t m, CgMatrix A, const CgStateN<XT, NR>* __restrict__ sin,
     CgStateN<XT, NR>* __restrict__ sout, XT* __restrict__ p, XT* __restrict__ xlo,
-    CgScalarsN* __restrict__ sc, CgScalarsN* snap, const double* __restrict__ part_in,
-    double* __restrict__ part_out, int n_in, int xg, int q, int fixed) {
+    CgScalarsN* __restrict__ sc, CgScalarsN* snap, int32_t* hflag,
+    const double* __restrict__ part_in, double* __restrict__ part_out, int n_in, int xg, int q,
+    int fixed) {
   constexpr int W = BS / kWave;
   constexpr int NPT = 6 * NR;
   constexpr int U = kBatchN<XT, NR>;
@@ -1393,6 +1394,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
       for (int k = 0; k < NR; ++k) sc->rr[k] = rr_d[k];
       sc->done = flag;
       if (snap) *snap = *sc;
+      if (hflag) *hflag = flag;
     }
     return;
   }
@@ -1709,12 +1711,12 @@ void cgn_iter_launch_h(const CgArgsN<XT>& a, const CgMatrix& A, int q, int fixed
   if (e0) {
     hipExtLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0,
                           s, e0, e1, 0, a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo,
-                          a.sc, a.snap, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg,
-                          q, fixed);
+                          a.sc, a.snap, a.flag, (const double*)a.part[q ^ 1], a.part[q], a.blocks,
+                          a.xg, q, fixed);
   } else {
     hipLaunchKernelGGL((k_cgn_iter<VT, XT, CT, L, BS, NR, HALO>), dim3(a.blocks), dim3(BS), 0, s,
                        a.m, A, (const St*)a.st[q], (St*)a.st[q ^ 1], a.p, a.xlo, a.sc, a.snap,
-                       (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed);
+                       a.flag, (const double*)a.part[q ^ 1], a.part[q], a.blocks, a.xg, q, fixed);
   }
 }
 

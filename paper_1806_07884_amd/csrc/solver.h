@@ -228,6 +228,7 @@ struct CgArgsN {
   double* r64;      // [nr][m]
   CgScalarsN* sc;
   CgScalarsN* snap;  // host snapshot slot written by a chunk's last launch, or NULL
+  int32_t* flag;     // pinned host word set by the iteration raising a flag (see CgArgs)
   double* part[2];  // [blocks][6 nr] partials of an iteration, by state buffer
   double* part_ref; // [blocks][6 nr] partials of a refresh
   int blocks;
