@@ -30,11 +30,12 @@ def libs():
         pytest.skip("no GPU")
     import paper_1806_07884_amd as rbf
     from paper_1806_07884_amd import _lib
-    normal = _lib.lib()
+    prev = _lib.lib()  # the checked one too when RBF_LIBRARY=checked
+    normal = _lib.load(_lib.LIB_PATH)
     checked = _lib.load(_lib.CHECKED_LIB_PATH)
     assert normal.rbf_build_checked() == 0 and checked.rbf_build_checked() == 1
     yield rbf, _lib, normal, checked
-    _lib.use(normal)
+    _lib.use(prev)
 
 
 def dev(a):
