@@ -365,20 +365,32 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
   int64_t slice = (int64_t)blk * W + wave;
 
   // Loads that do not depend on this iteration's scalars go out first: the
-  // first slice's geometry and first batch, the row's own state, the
-  // previous kernel's partials and the scalars.
-  SliceHead<XT, HALO> h;
-  CgState<XT> own;
-  XT p_old = (XT)0, x_old = (XT)0;
-  const bool have = !poly_block && slice < A.nslices;
-  if (have) {
-    open_slice<VT, XT, CT, L, HALO>(m, slice, A, h);
-    if ((lane & (L - 1)) == 0 && h.row < m) {
-      own = sin[h.row];
-      p_old = p[h.row];
-      x_old = xlo[h.row];
-    }
+  // previous kernel's partials (so that their sum waits for them alone), then
+  // the first slice's geometry and first batch, the row's own state and the
+  // scalars.  Every partial this thread adds is loaded before the first add
+  // (one round trip instead of one per block stride); the loads are
+  // unconditional, from a clamped block index, so that no branch separates
+  // them, and the surplus ones are dropped by a select.  They are loaded in
+  // a launch with fixed scalars too (which ignores them) so that no branch
+  // holds their first adds.
+  constexpr int KB = (kCgMaxBlocks + BS - 1) / BS;
+  double pv[KB][NP];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int k = (int)threadIdx.x + i * BS;
+    const int kc = k < n_in ? k : n_in - 1;
+#pragma unroll
+    for (int t = 0; t < NP; ++t) pv[i][t] = part_in[NP * kc + t];
   }
+  // These loads take no branch either (a branch around them would make the
+  // partials' sum wait for them too): a wave with no slice (padding or
+  // polynomial block) loads the last slice and every lane its clamped row;
+  // only the waves with a slice and the rows' owner lanes use them.
+  SliceHead<XT, HALO> h;
+  const bool have = !poly_block && slice < A.nslices;
+  open_slice<VT, XT, CT, L, HALO>(m, have ? slice : A.nslices - 1, A, h);
+  CgState<XT> own = sin[h.rowc];
+  XT p_old = p[h.rowc], x_old = xlo[h.rowc];
   // the first slice's neighbourhood records (they do not depend on this
   // iteration's scalars): the first rounds go out before the reduction
   constexpr int kStagePre = HALO ? (sizeof(XT) == 4 ? 8 : 4) : 1;
@@ -397,30 +409,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1
       }
     }
   }
+  // added in block order (also in a launch with fixed scalars, which drops
+  // the sum), a surplus load times 0: every load's value is used on every
+  // path, so none is made conditional (and the sum waits for no later load)
   double red[NP];
 #pragma unroll
   for (int t = 0; t < NP; ++t) red[t] = 0.0;
-  if (!fixed) {
-    // every partial this thread adds is loaded before the first add (one
-    // round trip instead of one per block stride); added in the same order
-    // (the loads are unconditional, from a clamped block index, so that no
-    // branch separates them; the surplus ones are dropped by the select)
-    constexpr int KB = (kCgMaxBlocks + BS - 1) / BS;
-    double pv[KB][NP];
 #pragma unroll
-    for (int i = 0; i < KB; ++i) {
-      const int k = (int)threadIdx.x + i * BS;
-      const int kc = k < n_in ? k : n_in - 1;
+  for (int i = 0; i < KB; ++i) {
+    const double wgt = (int)threadIdx.x + i * BS < n_in ? 1.0 : 0.0;
 #pragma unroll
-      for (int t = 0; t < NP; ++t) pv[i][t] = part_in[NP * kc + t];
-    }
-#pragma unroll
-    for (int i = 0; i < KB; ++i) {
-      const bool in = (int)threadIdx.x + i * BS < n_in;
-#pragma unroll
-      for (int t = 0; t < NP; ++t) red[t] += in ? pv[i][t] : 0.0;
-    }
+    for (int t = 0; t < NP; ++t) red[t] = __builtin_fma(pv[i][t], wgt, red[t]);
   }
+#pragma unroll
+  for (int t = 0; t < NP; ++t) red[t] = fixed ? 0.0 : red[t];
   const double gam_prev = sc->gam[q ^ 1];
   const double trigger2 = sc->trigger2;
   const double fgamma = sc->fix_gamma, frr = sc->fix_rr;
